@@ -1,0 +1,143 @@
+"""Pins for the oracle's TV (eq. 34) and KL (eq. 35) fields and the truncated fields."""
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import cityblock
+from scipy.stats import entropy
+
+from conftest import frac, read_golden
+from oracle import disk as odisk
+from oracle import divergence as dv
+from workloads import build_config, grid_domain
+from workloads.seeds import rng
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return build_config("c1")
+
+
+@pytest.fixture(scope="module")
+def grid_P():
+    g = grid_domain(49, 2, (0.1, 0.3), config_id=11)
+    P = g.poisson_kernel()
+    keep = P.max(axis=0) > 0
+    return P[:, keep]
+
+
+def test_kl_is_library_relative_entropy_with_target_as_reference(grid_P):
+    # scipy.stats.entropy(pk, qk) = sum pk log(pk/qk): KL with pk the reference.
+    P = grid_P
+    t = 123
+    d = dv.kl_field(P, t)
+    for x in (0, 7, 400, P.shape[0] - 1):
+        assert d[x] == pytest.approx(entropy(P[t], P[x]), rel=1e-12, abs=1e-15)
+    # the reversed argument order is a different number on this domain
+    x = 400
+    assert abs(entropy(P[x], P[t]) - d[x]) > 1e-3 * d[x]
+
+
+def test_tv_is_library_l1_distance(grid_P):
+    P = grid_P
+    t = 55
+    d = dv.tv_field(P, t)
+    for x in (0, 9, 333, P.shape[0] - 1):
+        assert d[x] == pytest.approx(cityblock(P[t], P[x]), rel=1e-13)
+
+
+def test_hand_solved_two_vertex_grid_divergences():
+    rows = {r[0]: r[1:] for r in read_golden("grid4x3_two_vertex.txt")}
+    P = np.array([[frac(v) for v in rows["a"]], [frac(v) for v in rows["b"]]])
+    assert dv.tv_field(P, 0)[1] == pytest.approx(frac(rows["TV_a_to_b"][0]), rel=1e-15)
+    assert dv.kl_field(P, 0)[1] == pytest.approx(frac(rows["KL_a_to_b_over_log4"][0]) * np.log(4),
+                                                 rel=1e-15)
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_disk_fields_match_closed_forms(c1, k):
+    # Appendix eqs. A6 and A8 carried to any target by the Moebius map (A10)
+    # and conformal invariance (Theorem A2).  The sampled kernel is a B-point
+    # trapezoid rule, exact up to O(r^B) for KL; TV has a kink, so its
+    # quadrature converges algebraically.
+    t = int(rng(0, "targets").integers(0, c1.N, size=3)[k])
+    kl = dv.kl_field(c1.P, t)
+    tv = dv.tv_field(c1.P, t)
+    assert np.abs(kl - odisk.kl_closed(c1.z, c1.z[t])).max() < 5e-6
+    assert np.abs(tv - odisk.tv_closed(c1.z, c1.z[t])).max() < 2.5e-3
+
+
+def test_fields_vanish_at_target_and_respect_ranges(grid_P):
+    P = grid_P
+    for t in (0, 100, 700):
+        kl = dv.kl_field(P, t)
+        tv = dv.tv_field(P, t)
+        assert kl[t] == 0.0 and tv[t] == 0.0
+        assert kl.min() >= 0.0                      # Gibbs' inequality
+        assert tv.min() >= 0.0 and tv.max() <= 2.0
+        others = np.arange(P.shape[0]) != t
+        assert kl[others].min() > 0.0 and tv[others].min() > 0.0
+
+
+def test_brute_force_loops_on_tiny_stochastic_matrix():
+    g = np.random.default_rng(5)
+    P = g.random((9, 6)) ** 3
+    P[2, 4] = 0.0                    # a zero in the reference row
+    P /= P.sum(axis=1, keepdims=True)
+    t = 2
+    kl, tv = dv.kl_field(P, t), dv.tv_field(P, t)
+    for x in range(9):
+        s_kl = 0.0
+        s_tv = 0.0
+        for b in range(6):
+            s_tv += abs(P[t, b] - P[x, b])
+            if P[t, b] > 0:
+                s_kl += P[t, b] * np.log(P[t, b] / P[x, b])
+        assert kl[x] == pytest.approx(s_kl, rel=1e-13, abs=1e-16)
+        assert tv[x] == pytest.approx(s_tv, rel=1e-13, abs=1e-16)
+
+
+def test_kl_infinite_when_reference_mass_meets_zero():
+    P = np.array([[0.5, 0.5], [1.0, 0.0]])
+    assert np.isinf(dv.kl_field(P, 0)[1])
+    assert dv.kl_field(P, 1)[0] == pytest.approx(np.log(2.0))
+
+
+def test_truncation_threshold_zero_is_dense(grid_P):
+    P = grid_P
+    Pt, thr = dv.truncate(P, 0.0)
+    assert np.array_equal(Pt, P)
+    t = 321
+    assert np.array_equal(dv.tv_trunc_field(Pt, t), dv.tv_field(P, t))
+    assert np.allclose(dv.kl_trunc_field(Pt, t, thr), dv.kl_field(P, t), rtol=1e-12, atol=1e-15)
+
+
+def test_truncated_fields_brute_force(grid_P):
+    P = grid_P[:40]
+    tau = 1e-3
+    Pt, thr = dv.truncate(P, tau)
+    assert 0 < (Pt == 0).sum() < Pt.size
+    t = 11
+    kl = dv.kl_trunc_field(Pt, t, thr)
+    tv = dv.tv_trunc_field(Pt, t)
+    for x in range(P.shape[0]):
+        rowmax = max(P[x])
+        s_kl = 0.0
+        s_tv = 0.0
+        for b in range(P.shape[1]):
+            pt = P[t, b] if P[t, b] >= tau * max(P[t]) else 0.0
+            qx = P[x, b] if P[x, b] >= tau * rowmax else 0.0
+            s_tv += abs(pt - qx)
+            if pt > 0:
+                s_kl += pt * (np.log(pt) - np.log(qx if qx > 0 else tau * rowmax))
+        assert kl[x] == pytest.approx(s_kl, rel=1e-12, abs=1e-14)
+        assert tv[x] == pytest.approx(s_tv, rel=1e-12, abs=1e-15)
+    assert kl[t] == 0.0 and tv[t] == 0.0
+
+
+def test_csr_round_trip(grid_P):
+    Pt, _ = dv.truncate(grid_P, 1e-4)
+    ptr, col, val = dv.csr_from_truncated(Pt)
+    back = np.zeros_like(Pt)
+    for x in range(Pt.shape[0]):
+        back[x, col[ptr[x]:ptr[x + 1]]] = val[ptr[x]:ptr[x + 1]]
+    assert np.array_equal(back, Pt)
