@@ -1,0 +1,212 @@
+/*
+ * dd.h -- divergence-distance fields and steepest-descent paths on MI355X.
+ *
+ * C ABI of libdd.so.  The library evaluates, for a target interior vertex t,
+ * the total-variation and Kullback-Leibler divergence distances between the
+ * discrete Poisson-kernel row of t and the row of every interior vertex x
+ * (Section IV, eqs. 34 and 35 of Chen, Gotsman, Hormann, "Path Planning with
+ * Divergence-Based Distance Functions"), and traces the edge-based
+ * steepest-descent path of Section IV ("Gradient-descent path generation").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns dd_status (DD_OK == 0).  No C++ exception crosses
+ *   this boundary.  On failure dd_last_error() returns a message for the most
+ *   recent failure on the calling thread; on DD_EINVAL nothing has been written
+ *   to any output.
+ * - Vertex ids are 0-based interior-vertex ids in [0, N).  Boundary vertices
+ *   are not rows: P here is the interior block P_IB of eq. (33).
+ * - "Device pointer" means memory on the handle's GPU (hipMalloc, or a torch
+ *   CUDA tensor); "host pointer" means ordinary CPU memory.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Field kernels are enqueued on it asynchronously; outputs are valid once
+ *   the stream reaches that point.
+ * - One dd_kernel may be used from several host threads and streams at once;
+ *   per-call scratch memory is stream-ordered (hipMallocAsync on `stream`).
+ *
+ * Error bounds
+ * ------------
+ * Field entry points can report, per field, a bound {abs, rel} such that
+ *     |d_hat(x) - d(x)| <= abs + rel * |d_hat(x)|      for every x,
+ * where d_hat is the returned FP32 field and d the exact FP64 evaluation of
+ * the same definition on the kernel matrix exactly as it was passed to the
+ * load call (upcast to FP64).
+ */
+#ifndef DD_H
+#define DD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DD_OK = 0,
+  DD_EINVAL = 1,   /* bad argument or bad input data; nothing written */
+  DD_ENOMEM = 2,   /* the HBM footprint does not fit in free device memory */
+  DD_EDEVICE = 3,  /* a HIP runtime call failed */
+  DD_ESTATE = 4    /* freed, foreign or mismatched handle */
+} dd_status;
+
+typedef enum {
+  DD_TV = 0,  /* total variation, eq. (34): sum_b |P_tb - P_xb|, range [0, 2] */
+  DD_KL = 1   /* Kullback-Leibler, eq. (35): sum_b P_tb log(P_tb / P_xb), target row as reference */
+} dd_kind;
+
+/* Operand form of the batched-KL contraction (see dd_batch_distance_fields). */
+typedef enum {
+  DD_FORM_NONE = -1,   /* do not build a batched-KL operand */
+  DD_FORM_F32 = 0,     /* FP32 log-kernel, FP32 MFMA */
+  DD_FORM_F16X3 = 1    /* FP16 hi+lo split of the log-kernel and of the targets, 3 MFMA products */
+} dd_form;
+
+typedef enum {
+  DD_PATH_REACHED = 0,   /* the walk arrived at the target */
+  DD_PATH_STUCK = 1,     /* no neighbour strictly lower: a local minimum (or plateau) */
+  DD_PATH_MAX_STEPS = 2  /* max_steps moves made without arriving */
+} dd_path_status;
+
+typedef struct dd_ctx dd_ctx;
+typedef struct dd_kernel dd_kernel;
+
+/* Interior-vertex adjacency (the triangulation edges between interior
+ * vertices), CSR on the host.  Neighbour lists must be sorted ascending, hold
+ * no duplicates and no self loops.  Copied by the load call. */
+typedef struct {
+  int32_t n;               /* must equal N */
+  const int64_t* row_ptr;  /* [n+1], row_ptr[0] == 0, non-decreasing */
+  const int32_t* col;      /* [row_ptr[n]] ids in [0, n) */
+} dd_adjacency;
+
+typedef struct {
+  int32_t gemm_form;     /* dd_form built for dd_batch_distance_fields with DD_KL */
+  double tau;            /* > 0: keep only the truncation of P (CSR form); 0: dense */
+  int32_t tau_relative;  /* 1: keep P_xb >= tau * max_b P_xb; 0: keep P_xb >= tau */
+  int32_t validate;      /* 1: reject rows that are not probability vectors */
+} dd_load_opts;
+
+typedef struct {
+  double abs;
+  double rel;
+} dd_error_bound;
+
+typedef struct {
+  int32_t n;           /* N, interior rows */
+  int32_t b_in;        /* columns as loaded */
+  int32_t b;           /* columns kept (all-zero columns dropped) */
+  int32_t is_csr;      /* 1 if the handle holds the truncated (CSR) form */
+  int64_t nnz;         /* stored nonzeros of the CSR form (0 if dense) */
+  int32_t gemm_form;   /* dd_form built, or DD_FORM_NONE */
+  int32_t has_adjacency;
+  size_t hbm_bytes;    /* device memory held by the handle */
+} dd_kernel_info;
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+dd_status dd_create(int device, dd_ctx** out);
+
+/* Destroy a context.  Every kernel loaded through it must be freed first
+ * (DD_ESTATE otherwise, and the context stays valid). */
+dd_status dd_destroy(dd_ctx* ctx);
+
+/* Load a dense Poisson-kernel matrix P (N x B, row-major, row stride B).
+ *
+ * The matrix is the interior block P_IB of eq. (33): row x is the discrete
+ * harmonic measure of interior vertex x over the B boundary vertices
+ * (Section IV, "The divergence distances").
+ *   P           host or device pointer to N*B values, FP32 (p_is_f64 == 0) or
+ *               FP64 (p_is_f64 == 1); p_on_device says which memory it is.
+ *   adj         nullable; needed by the path entry points.
+ *   opts        nullable (defaults: gemm_form DD_FORM_NONE, tau 0, validate 1).
+ * Entries must be finite and >= 0; positive entries below the FP32 normal
+ * range (1.17549435e-38) are rejected.  With validate, every row sum must be
+ * 1 within 1e-5 (FP32 input) or 1e-9 (FP64 input).  All-zero columns are
+ * dropped (they contribute nothing to eqs. 34-35).  With opts->tau > 0 the
+ * handle holds the truncated matrix only (see dd_load_kernel_csr).
+ * The input is copied; the caller may free it on return.  The library owns
+ * the device copy until dd_free_kernel.  Synchronous. */
+dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P,
+                               int32_t p_is_f64, int32_t p_on_device,
+                               const dd_adjacency* adj, const dd_load_opts* opts,
+                               dd_kernel** out);
+
+/* Load a truncated (sparsified) Poisson kernel in CSR form (Section V,
+ * "Precision": small entries of each row dropped, no renormalisation).
+ *   row_ptr   host [N+1] int64; col host [nnz] int32 in [0, B), ascending per
+ *             row; val host [nnz] FP32 or FP64 (val_is_f64), all > 0.
+ *   row_max   host [N] FP64: max_b P_xb of the untruncated row x.
+ *   tau, tau_relative: the threshold the truncation used; the floor of row x
+ *             is phi_x = tau * row_max[x] (relative) or tau (absolute).
+ * Fields on this handle are the truncated ones:
+ *   TV_tau(x) = sum_b |P~_tb - P~_xb|
+ *   KL_tau(x) = sum_{b: P~_tb > 0} P~_tb (log P~_tb - log Q_xb),
+ *               Q_xb = P~_xb if stored, else phi_x.
+ * Copies its inputs.  Synchronous. */
+dd_status dd_load_kernel_csr(dd_ctx* ctx, int32_t N, int32_t B, const int64_t* row_ptr,
+                             const int32_t* col, const void* val, int32_t val_is_f64,
+                             const double* row_max, double tau, int32_t tau_relative,
+                             const dd_adjacency* adj, const dd_load_opts* opts,
+                             dd_kernel** out);
+
+/* Sizes and device memory held by a handle. */
+dd_status dd_kernel_get_info(const dd_kernel* k, dd_kernel_info* info);
+
+/* Device bytes a dense load of an N x B matrix with these options would
+ * need (admission control before loading). */
+dd_status dd_dense_footprint(int32_t N, int32_t B, int32_t p_is_f64, const dd_load_opts* opts,
+                             size_t* hbm_bytes);
+
+/* Distance field of one target (eq. 34 or 35, or the truncated forms on a
+ * CSR handle) into out_dev[N] (device FP32).  One streaming pass over the
+ * kernel rows.  bound: nullable host pointer.  Asynchronous on `stream`. */
+dd_status dd_distance_field(dd_kernel* k, int32_t target, int32_t kind, float* out_dev,
+                            dd_error_bound* bound, void* stream);
+
+/* Distance fields of T targets into out_dev[T][N] (device FP32, one field
+ * contiguous per target).  targets: host [T].  For DD_KL on a dense handle
+ * built with a gemm_form the fields come from one contraction,
+ *     d(x,t) = H_t - o_x W_t - sum_b P_tb l_xb,
+ * with l_xb = log P_xb - o_x, o_x = log max_b P_xb, H_t = sum_b P_tb log P_tb
+ * and W_t = sum_b P_tb (eq. 35 expanded).  Otherwise one streaming pass per
+ * target.  bounds: nullable host [T].  Asynchronous on `stream`. */
+dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t T,
+                                   int32_t kind, float* out_dev, dd_error_bound* bounds,
+                                   void* stream);
+
+/* Trace T steepest-descent paths on precomputed fields (Section IV, edge-based
+ * variant): from v = source[i], move to the neighbour with the smallest field
+ * value (ties: lowest id) while it is strictly below the current value.
+ * Decisions whose FP32 values are within the stated bounds of each other are
+ * re-decided in FP64 from the loaded matrix.
+ *   fields_dev   device [T][N] FP32 from the field entry points for targets[i]
+ *   bounds       host [T], the bounds those calls returned
+ *   sources, targets  host [T]
+ *   path_dev     device [T][max_steps+1] int32, vertex ids, -1 past the end
+ *   len_dev      device [T] int32 path lengths (vertices, source included)
+ *   status_dev   device [T] int32 dd_path_status
+ *   rechecks_dev device [T] int32 FP64 re-decisions, nullable
+ * Needs the adjacency.  Asynchronous on `stream`. */
+dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const int32_t* targets,
+                         int32_t kind, const float* fields_dev, const dd_error_bound* bounds,
+                         int32_t max_steps, int32_t* path_dev, int32_t* len_dev,
+                         int32_t* status_dev, int32_t* rechecks_dev, void* stream);
+
+/* Plan one path: the field of `target` (dd_distance_field) followed by the
+ * path from `source` (dd_trace_paths).  path_host must hold max_steps+1
+ * entries.  rechecks nullable.  Synchronous with respect to `stream`. */
+dd_status dd_plan_path(dd_kernel* k, int32_t source, int32_t target, int32_t kind,
+                       int32_t max_steps, int32_t* path_host, int32_t* len,
+                       int32_t* status, int32_t* rechecks, void* stream);
+
+/* Release a handle and its device memory (waits for the device first). */
+dd_status dd_free_kernel(dd_kernel* k);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* dd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DD_H */

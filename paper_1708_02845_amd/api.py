@@ -1,0 +1,216 @@
+"""Python face of libdd: argument marshalling over the C ABI.
+
+PyTorch supplies device memory (output tensors) and streams; every step of the
+computation runs in the library's HIP kernels.  There is no CPU fallback: the
+calls raise if the library is missing or the device is unavailable.
+"""
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+KINDS = {"tv": L.DD_TV, "kl": L.DD_KL, L.DD_TV: L.DD_TV, L.DD_KL: L.DD_KL}
+FORMS = {None: L.DD_FORM_NONE, "none": L.DD_FORM_NONE, "f32": L.DD_FORM_F32,
+         "f16x3": L.DD_FORM_F16X3}
+PATH_STATUS = {L.DD_PATH_REACHED: "reached", L.DD_PATH_STUCK: "stuck",
+               L.DD_PATH_MAX_STEPS: "max_steps"}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _kind(kind):
+    try:
+        return KINDS[kind.lower() if isinstance(kind, str) else kind]
+    except KeyError:
+        raise ValueError(f"unknown kind {kind!r}") from None
+
+
+def _adjacency(adj, n):
+    """(struct, keep-alive arrays) from an (row_ptr, col) pair or None."""
+    if adj is None:
+        return None, ()
+    ptr = np.ascontiguousarray(adj[0], dtype=np.int64)
+    col = np.ascontiguousarray(adj[1], dtype=np.int32)
+    s = L.dd_adjacency(int(n), ptr.ctypes.data_as(C.POINTER(C.c_int64)),
+                       col.ctypes.data_as(C.POINTER(C.c_int32)))
+    return s, (ptr, col)
+
+
+def bound_tuple(b):
+    return (b.abs, b.rel)
+
+
+class Context:
+    """A library context bound to one HIP device."""
+
+    def __init__(self, device=0):
+        self._lib = L.load()
+        self.device = int(device)
+        h = C.c_void_p()
+        L.check(self._lib.dd_create(self.device, C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            L.check(self._lib.dd_destroy(self._h))
+            self._h = None
+
+
+class Kernel:
+    """A resident Poisson-kernel matrix (dense or truncated) on the device."""
+
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        self._h = handle
+        info = L.dd_kernel_info()
+        L.check(self._lib.dd_kernel_get_info(self._h, C.byref(info)))
+        self.N, self.B_in, self.B = info.n, info.b_in, info.b
+        self.is_csr = bool(info.is_csr)
+        self.nnz = info.nnz
+        self.gemm_form = info.gemm_form
+        self.has_adjacency = bool(info.has_adjacency)
+        self.hbm_bytes = info.hbm_bytes
+
+    # ---- loading ----
+    @classmethod
+    def load_dense(cls, ctx, P, adjacency=None, gemm_form=None, tau=0.0, tau_relative=True,
+                   validate=True):
+        """Load an N x B matrix given as a numpy array or a torch tensor (any device)."""
+        torch = _torch()
+        keep = []
+        if isinstance(P, np.ndarray):
+            arr = np.ascontiguousarray(P)
+            if arr.dtype not in (np.float32, np.float64):
+                raise TypeError("P must be float32 or float64")
+            ptr, on_dev, f64 = arr.ctypes.data, 0, int(arr.dtype == np.float64)
+            keep.append(arr)
+            N, B = arr.shape
+        else:
+            t = P.contiguous()
+            if t.dtype not in (torch.float32, torch.float64):
+                raise TypeError("P must be float32 or float64")
+            ptr, on_dev, f64 = t.data_ptr(), int(t.is_cuda), int(t.dtype == torch.float64)
+            keep.append(t)
+            N, B = t.shape
+        adj, adj_keep = _adjacency(adjacency, N)
+        opts = L.dd_load_opts(FORMS[gemm_form], float(tau), int(bool(tau_relative)),
+                              int(bool(validate)))
+        h = C.c_void_p()
+        L.check(ctx._lib.dd_load_kernel_dense(ctx.handle, int(N), int(B), C.c_void_p(ptr), f64,
+                                              on_dev, C.byref(adj) if adj else None,
+                                              C.byref(opts), C.byref(h)))
+        del keep, adj_keep
+        return cls(ctx, h)
+
+    @classmethod
+    def load_csr(cls, ctx, N, B, row_ptr, col, val, row_max, tau, tau_relative=True,
+                 adjacency=None):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        vl = np.ascontiguousarray(val)
+        if vl.dtype not in (np.float32, np.float64):
+            vl = vl.astype(np.float64)
+        rm = np.ascontiguousarray(row_max, dtype=np.float64)
+        adj, adj_keep = _adjacency(adjacency, N)
+        h = C.c_void_p()
+        L.check(ctx._lib.dd_load_kernel_csr(
+            ctx.handle, int(N), int(B), C.c_void_p(rp.ctypes.data), C.c_void_p(cl.ctypes.data),
+            C.c_void_p(vl.ctypes.data), int(vl.dtype == np.float64), C.c_void_p(rm.ctypes.data),
+            float(tau), int(bool(tau_relative)), C.byref(adj) if adj else None, None, C.byref(h)))
+        del adj_keep
+        return cls(ctx, h)
+
+    @staticmethod
+    def dense_footprint(N, B, f64=False, gemm_form=None):
+        lib = L.load()
+        opts = L.dd_load_opts(FORMS[gemm_form], 0.0, 1, 1)
+        out = C.c_size_t()
+        L.check(lib.dd_dense_footprint(int(N), int(B), int(bool(f64)), C.byref(opts), C.byref(out)))
+        return out.value
+
+    def free(self):
+        if self._h:
+            L.check(self._lib.dd_free_kernel(self._h))
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    # ---- fields ----
+    def _out(self, shape, out):
+        torch = _torch()
+        if out is None:
+            return torch.empty(shape, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous() \
+                or out.numel() < int(np.prod(shape)):
+            raise ValueError("out must be a contiguous float32 CUDA tensor of the right size")
+        return out
+
+    def field(self, target, kind, out=None, stream=None):
+        """(field tensor [N], (abs, rel) error bound) for one target."""
+        out = self._out((self.N,), out)
+        b = L.dd_error_bound()
+        L.check(self._lib.dd_distance_field(self._h, int(target), _kind(kind),
+                                            C.c_void_p(out.data_ptr()), C.byref(b),
+                                            _stream_handle(stream)))
+        return out, bound_tuple(b)
+
+    def batch_fields(self, targets, kind, out=None, stream=None):
+        """(fields [T, N], list of bounds) for T targets."""
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        T = len(t)
+        out = self._out((T, self.N), out)
+        bounds = (L.dd_error_bound * max(T, 1))()
+        L.check(self._lib.dd_batch_distance_fields(self._h, C.c_void_p(t.ctypes.data), int(T),
+                                                   _kind(kind), C.c_void_p(out.data_ptr()),
+                                                   bounds, _stream_handle(stream)))
+        return out, [bound_tuple(bounds[i]) for i in range(T)]
+
+    # ---- paths ----
+    def trace_paths(self, sources, targets, kind, fields, bounds, max_steps, stream=None):
+        """Device tensors (paths [T, max_steps+1], len [T], status [T], rechecks [T])."""
+        torch = _torch()
+        s = np.ascontiguousarray(sources, dtype=np.int32)
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        T = len(s)
+        dev = f"cuda:{self.ctx.device}"
+        paths = torch.empty((T, max_steps + 1), dtype=torch.int32, device=dev)
+        info = torch.empty((3, T), dtype=torch.int32, device=dev)
+        b = (L.dd_error_bound * T)(*[L.dd_error_bound(a, r) for a, r in bounds])
+        if not fields.is_contiguous() or fields.dtype != torch.float32:
+            raise ValueError("fields must be contiguous float32")
+        L.check(self._lib.dd_trace_paths(self._h, int(T), C.c_void_p(s.ctypes.data),
+                                         C.c_void_p(t.ctypes.data), _kind(kind),
+                                         C.c_void_p(fields.data_ptr()), b, int(max_steps),
+                                         C.c_void_p(paths.data_ptr()),
+                                         C.c_void_p(info[0].data_ptr()),
+                                         C.c_void_p(info[1].data_ptr()),
+                                         C.c_void_p(info[2].data_ptr()), _stream_handle(stream)))
+        return paths, info[0], info[1], info[2]
+
+    def plan_path(self, source, target, kind, max_steps=4000, stream=None):
+        """(vertex list, status name, FP64 re-decisions) for one query; synchronous."""
+        buf = (C.c_int32 * (max_steps + 1))()
+        n, st, rc = C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(self._lib.dd_plan_path(self._h, int(source), int(target), _kind(kind),
+                                       int(max_steps), buf, C.byref(n), C.byref(st), C.byref(rc),
+                                       _stream_handle(stream)))
+        return list(buf[:n.value]), PATH_STATUS[st.value], rc.value

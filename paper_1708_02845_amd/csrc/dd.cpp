@@ -1,0 +1,752 @@
+// Host side of the C ABI declared in include/dd.h.
+#include "dd.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dd_internal.h"
+
+namespace {
+
+constexpr uint32_t kCtxMagic = 0xDD0C7A11u;
+constexpr uint32_t kKernelMagic = 0xDD0E4E11u;
+constexpr uint32_t kDead = 0xDEADDEADu;
+constexpr double kU = 5.9604644775390625e-08;   // 2^-24, FP32 unit roundoff
+constexpr int kMaxDegree = 64;
+constexpr int32_t kMaxB = 16384;                // the target row must fit in LDS
+
+thread_local std::string g_err;
+
+dd_status fail(dd_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_OR(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(DD_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),      \
+                  __FILE__, __LINE__);                                                    \
+  } while (0)
+
+// Device allocation owned by a handle.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t n) {
+    release();
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) bytes = n;
+    return e;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// Stream-ordered scratch, freed on the same stream when it goes out of scope.
+struct AsyncBuf {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  explicit AsyncBuf(hipStream_t st) : s(st) {}
+  ~AsyncBuf() {
+    if (p) hipFreeAsync(p, s);
+  }
+  hipError_t alloc(size_t n) { return hipMallocAsync(&p, n ? n : 1, s); }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+}  // namespace
+
+struct dd_ctx {
+  uint32_t magic = kCtxMagic;
+  int device = 0;
+  int live_kernels = 0;
+};
+
+struct dd_kernel {
+  uint32_t magic = kKernelMagic;
+  dd_ctx* ctx = nullptr;
+  int32_t N = 0, B_in = 0, B = 0;
+  int64_t ld = 0;
+  int is_f64 = 0;
+  int is_csr = 0;
+  int gemm_form = DD_FORM_NONE;
+  double tau = 0.0;
+  int tau_relative = 1;
+  // dense
+  DevBuf P32, P64, H;
+  std::vector<double> H_host;   // sum_b P_xb log P_xb per row (FP64)
+  std::vector<double> W_host;   // row sums
+  // batched-KL operand
+  DevBuf L32, Lhi, Llo, Off;
+  // truncated
+  DevBuf start, len, col, val, val64, phi;
+  int64_t nnz = 0;
+  std::vector<double> Ht_host, Wt_host;   // per row over the stored entries
+  // adjacency
+  DevBuf adj_ptr, adj_idx;
+  int has_adj = 0;
+
+  size_t footprint() const {
+    return P32.bytes + P64.bytes + H.bytes + L32.bytes + Lhi.bytes + Llo.bytes + Off.bytes +
+           start.bytes + len.bytes + col.bytes + val.bytes + val64.bytes + phi.bytes +
+           adj_ptr.bytes + adj_idx.bytes;
+  }
+  dd::DenseView dense() const {
+    return dd::DenseView{P32.as<const float>(), P64.as<const double>(), ld, N, B};
+  }
+  dd::CsrView csr() const {
+    return dd::CsrView{start.as<const int64_t>(), len.as<const int32_t>(),
+                       col.as<const uint16_t>(),  val.as<const float>(),
+                       val64.as<const double>(),  phi.as<const double>(), N, B};
+  }
+};
+
+namespace {
+
+bool ctx_ok(const dd_ctx* c) { return c && c->magic == kCtxMagic; }
+bool kernel_ok(const dd_kernel* k) { return k && k->magic == kKernelMagic && ctx_ok(k->ctx); }
+
+dd_load_opts default_opts() {
+  dd_load_opts o;
+  o.gemm_form = DD_FORM_NONE;
+  o.tau = 0.0;
+  o.tau_relative = 1;
+  o.validate = 1;
+  return o;
+}
+
+dd_status check_adjacency(int32_t N, const dd_adjacency* adj) {
+  if (!adj) return DD_OK;
+  if (adj->n != N) return fail(DD_EINVAL, "adjacency has n=%d, kernel has N=%d", adj->n, N);
+  if (!adj->row_ptr || (!adj->col && adj->row_ptr[N] > 0))
+    return fail(DD_EINVAL, "adjacency arrays are null");
+  if (adj->row_ptr[0] != 0) return fail(DD_EINVAL, "adjacency row_ptr[0] != 0");
+  for (int32_t v = 0; v < N; ++v) {
+    const int64_t b = adj->row_ptr[v], e = adj->row_ptr[v + 1];
+    if (e < b) return fail(DD_EINVAL, "adjacency row_ptr decreases at %d", v);
+    if (e - b > kMaxDegree)
+      return fail(DD_EINVAL, "vertex %d has %lld neighbours (max %d)", v, (long long)(e - b),
+                  kMaxDegree);
+    for (int64_t i = b; i < e; ++i) {
+      const int32_t u = adj->col[i];
+      if (u < 0 || u >= N) return fail(DD_EINVAL, "neighbour id %d of %d out of range", u, v);
+      if (u == v) return fail(DD_EINVAL, "self loop at %d", v);
+      if (i > b && adj->col[i - 1] >= u)
+        return fail(DD_EINVAL, "neighbours of %d not strictly ascending", v);
+    }
+  }
+  return DD_OK;
+}
+
+dd_status upload_adjacency(dd_kernel* k, const dd_adjacency* adj) {
+  if (!adj) return DD_OK;
+  const int64_t nnz = adj->row_ptr[k->N];
+  HIP_OR(k->adj_ptr.alloc(sizeof(int64_t) * (size_t)(k->N + 1)));
+  HIP_OR(k->adj_idx.alloc(sizeof(int32_t) * (size_t)nnz));
+  HIP_OR(hipMemcpy(k->adj_ptr.p, adj->row_ptr, sizeof(int64_t) * (size_t)(k->N + 1),
+                   hipMemcpyHostToDevice));
+  if (nnz > 0)
+    HIP_OR(hipMemcpy(k->adj_idx.p, adj->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice));
+  k->has_adj = 1;
+  return DD_OK;
+}
+
+size_t dense_bytes(int64_t N, int64_t B, int is_f64, const dd_load_opts& o) {
+  const int64_t ld = (B + 3) & ~int64_t(3);
+  size_t b = (size_t)(N * ld * 4) + (size_t)N * 8;
+  if (is_f64) b += (size_t)(N * B * 8);
+  if (o.gemm_form == DD_FORM_F32) b += (size_t)(N * ld * 4) + (size_t)N * 4;
+  if (o.gemm_form == DD_FORM_F16X3) b += (size_t)(N * ld * 4) + (size_t)N * 4;
+  return b;
+}
+
+dd_status check_free(size_t need) {
+  size_t free_b = 0, total_b = 0;
+  HIP_OR(hipMemGetInfo(&free_b, &total_b));
+  if (need > free_b)
+    return fail(DD_ENOMEM, "needs %zu bytes of device memory, %zu free", need, free_b);
+  return DD_OK;
+}
+
+// Error bound of a field, in the sense of include/dd.h.  u is the FP32 unit
+// roundoff; hardware log2 is taken to be within 4u*|log2 y| + 4u of log2 y.
+dd_error_bound field_bound(const dd_kernel* k, int kind, int32_t t) {
+  dd_error_bound b;
+  if (!k->is_csr) {
+    const double H = std::fabs(k->H_host[t]);
+    const double W = k->W_host[t];
+    if (kind == DD_TV) {
+      b.rel = 6.0 * kU;
+      b.abs = (k->is_f64 ? 2.0 * kU * (1.0 + W) : 0.0) + 1e-300;
+    } else {
+      b.rel = 11.0 * kU;
+      b.abs = 18.0 * kU * H + 6.0 * kU * W + (k->is_f64 ? kU * (W + 2.0 * H) : 0.0);
+    }
+  } else {
+    const double H = std::fabs(k->Ht_host[t]);
+    const double W = k->Wt_host[t];
+    if (kind == DD_TV) {
+      b.rel = 6.0 * kU;
+      b.abs = 4.0 * kU * W + 1e-300;
+    } else {
+      b.rel = 11.0 * kU;
+      b.abs = 40.0 * kU * H + 12.0 * kU * W;
+    }
+  }
+  // FP64 accumulation over B terms: negligible next to the FP32 terms, kept
+  // for completeness.
+  b.rel += 1e-15 * (double)k->B;
+  b.abs *= 2.0;   // safety factor on the analytic estimate
+  b.rel *= 2.0;
+  return b;
+}
+
+// Shared tail of both load paths: truncate the dense view into CSR.
+dd_status build_csr_from_dense(dd_kernel* k, dd::DenseView dv, const DevBuf& row_max) {
+  const int32_t N = k->N;
+  DevBuf thr, counts;
+  HIP_OR(thr.alloc(sizeof(double) * (size_t)N));
+  {
+    std::vector<double> mx(N), th(N);
+    HIP_OR(hipMemcpy(mx.data(), row_max.p, sizeof(double) * N, hipMemcpyDeviceToHost));
+    for (int32_t x = 0; x < N; ++x) th[x] = k->tau_relative ? k->tau * mx[x] : k->tau;
+    HIP_OR(hipMemcpy(thr.p, th.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+  }
+  HIP_OR(counts.alloc(sizeof(int32_t) * (size_t)N));
+  HIP_OR(dd::launch_trunc_count(dv, thr.as<const double>(), counts.as<int32_t>(), nullptr));
+  std::vector<int32_t> cnt(N);
+  HIP_OR(hipMemcpy(cnt.data(), counts.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+  std::vector<int64_t> st(N);
+  int64_t pos = 0, nnz = 0;
+  for (int32_t x = 0; x < N; ++x) {
+    st[x] = pos;
+    pos += (cnt[x] + 3) & ~3;
+    nnz += cnt[x];
+    if (cnt[x] == 0) return fail(DD_EINVAL, "row %d keeps no entry after truncation", x);
+  }
+  if (dd_status s = check_free((size_t)pos * (4 + 2 + (k->is_f64 ? 8 : 0)) + (size_t)N * 20))
+    return s;
+  HIP_OR(k->start.alloc(sizeof(int64_t) * N));
+  HIP_OR(k->len.alloc(sizeof(int32_t) * N));
+  HIP_OR(k->col.alloc(sizeof(uint16_t) * (size_t)pos));
+  HIP_OR(k->val.alloc(sizeof(float) * (size_t)pos));
+  if (k->is_f64) HIP_OR(k->val64.alloc(sizeof(double) * (size_t)pos));
+  HIP_OR(hipMemset(k->col.p, 0, sizeof(uint16_t) * (size_t)pos));
+  HIP_OR(hipMemset(k->val.p, 0, sizeof(float) * (size_t)pos));
+  if (k->is_f64) HIP_OR(hipMemset(k->val64.p, 0, sizeof(double) * (size_t)pos));
+  HIP_OR(hipMemcpy(k->start.p, st.data(), sizeof(int64_t) * N, hipMemcpyHostToDevice));
+  HIP_OR(hipMemcpy(k->len.p, cnt.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice));
+  HIP_OR(dd::launch_trunc_fill(dv, thr.as<const double>(), k->start.as<const int64_t>(),
+                               k->col.as<uint16_t>(), k->val.as<float>(),
+                               k->is_f64 ? k->val64.as<double>() : nullptr, nullptr));
+  HIP_OR(hipDeviceSynchronize());
+  k->phi.p = thr.p;
+  k->phi.bytes = thr.bytes;
+  thr.p = nullptr;
+  thr.bytes = 0;
+  k->nnz = nnz;
+  k->is_csr = 1;
+  return DD_OK;
+}
+
+// Per-row W and H over the stored entries of a CSR handle (host copies).
+dd_status csr_row_constants(dd_kernel* k) {
+  const int32_t N = k->N;
+  std::vector<int64_t> st(N);
+  std::vector<int32_t> ln(N);
+  HIP_OR(hipMemcpy(st.data(), k->start.p, sizeof(int64_t) * N, hipMemcpyDeviceToHost));
+  HIP_OR(hipMemcpy(ln.data(), k->len.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+  const size_t total = k->val.bytes / sizeof(float);
+  std::vector<double> v(total);
+  if (k->is_f64) {
+    HIP_OR(hipMemcpy(v.data(), k->val64.p, sizeof(double) * total, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> f(total);
+    HIP_OR(hipMemcpy(f.data(), k->val.p, sizeof(float) * total, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < total; ++i) v[i] = f[i];
+  }
+  k->Ht_host.assign(N, 0.0);
+  k->Wt_host.assign(N, 0.0);
+  for (int32_t x = 0; x < N; ++x) {
+    double w = 0.0, h = 0.0;
+    for (int32_t i = 0; i < ln[x]; ++i) {
+      const double p = v[st[x] + i];
+      w += p;
+      if (p > 0.0) h += p * std::log(p);
+    }
+    k->Wt_host[x] = w;
+    k->Ht_host[x] = h;
+  }
+  return DD_OK;
+}
+
+dd_status finish_handle(dd_kernel* k, dd_ctx* ctx, dd_kernel** out) {
+  ctx->live_kernels++;
+  *out = k;
+  return DD_OK;
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+const char* dd_last_error(void) { return g_err.c_str(); }
+
+dd_status dd_create(int device, dd_ctx** out) {
+  if (!out) return fail(DD_EINVAL, "out is null");
+  int n = 0;
+  HIP_OR(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(DD_EINVAL, "device %d of %d", device, n);
+  HIP_OR(hipSetDevice(device));
+  dd_ctx* c = new (std::nothrow) dd_ctx;
+  if (!c) return fail(DD_ENOMEM, "host allocation failed");
+  c->device = device;
+  *out = c;
+  return DD_OK;
+}
+
+dd_status dd_destroy(dd_ctx* ctx) {
+  if (!ctx_ok(ctx)) return fail(DD_ESTATE, "not a live context");
+  if (ctx->live_kernels > 0)
+    return fail(DD_ESTATE, "%d kernels still loaded in this context", ctx->live_kernels);
+  ctx->magic = kDead;
+  delete ctx;
+  return DD_OK;
+}
+
+dd_status dd_dense_footprint(int32_t N, int32_t B, int32_t p_is_f64, const dd_load_opts* opts,
+                             size_t* hbm_bytes) {
+  if (N <= 0 || B <= 0 || !hbm_bytes) return fail(DD_EINVAL, "bad sizes or null output");
+  const dd_load_opts o = opts ? *opts : default_opts();
+  *hbm_bytes = dense_bytes(N, B, p_is_f64, o);
+  return DD_OK;
+}
+
+dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P, int32_t p_is_f64,
+                               int32_t p_on_device, const dd_adjacency* adj,
+                               const dd_load_opts* opts, dd_kernel** out) {
+  if (!ctx_ok(ctx)) return fail(DD_ESTATE, "not a live context");
+  if (!out || !P) return fail(DD_EINVAL, "null argument");
+  if (N <= 0 || B <= 0) return fail(DD_EINVAL, "N=%d B=%d must be positive", N, B);
+  if (B > kMaxB) return fail(DD_EINVAL, "B=%d exceeds the supported %d columns", B, kMaxB);
+  const dd_load_opts o = opts ? *opts : default_opts();
+  if (o.gemm_form != DD_FORM_NONE && o.gemm_form != DD_FORM_F32 && o.gemm_form != DD_FORM_F16X3)
+    return fail(DD_EINVAL, "unknown gemm_form %d", o.gemm_form);
+  if (!(o.tau >= 0.0) || !std::isfinite(o.tau) || o.tau > 1.0)
+    return fail(DD_EINVAL, "tau must be in [0, 1]");
+  if (o.tau > 0.0 && o.gemm_form != DD_FORM_NONE)
+    return fail(DD_EINVAL, "a truncated load has no batched-KL operand");
+  if (dd_status s = check_adjacency(N, adj)) return s;
+  HIP_OR(hipSetDevice(ctx->device));
+
+  const size_t elt = p_is_f64 ? 8 : 4;
+  const size_t raw_bytes = (size_t)N * (size_t)B * elt;
+  if (dd_status s = check_free(dense_bytes(N, B, p_is_f64, o) + (p_on_device ? 0 : raw_bytes)))
+    return s;
+
+  dd_kernel* k = new (std::nothrow) dd_kernel;
+  if (!k) return fail(DD_ENOMEM, "host allocation failed");
+  k->ctx = ctx;
+  k->N = N;
+  k->B_in = B;
+  k->is_f64 = p_is_f64 ? 1 : 0;
+  k->tau = o.tau;
+  k->tau_relative = o.tau_relative ? 1 : 0;
+
+  auto bail = [&](dd_status s) {
+    delete k;
+    return s;
+  };
+
+  DevBuf raw_own;
+  const void* raw = P;
+  if (!p_on_device) {
+    if (hipError_t e = raw_own.alloc(raw_bytes))
+      return bail(fail(DD_EDEVICE, "hipMalloc(%zu): %s", raw_bytes, hipGetErrorString(e)));
+    if (hipError_t e = hipMemcpy(raw_own.p, P, raw_bytes, hipMemcpyHostToDevice))
+      return bail(fail(DD_EDEVICE, "upload: %s", hipGetErrorString(e)));
+    raw = raw_own.p;
+  }
+
+  // row checks, row sums, row maxima, non-zero columns
+  DevBuf rsum, rmax, bad, flags;
+  {
+    hipError_t e = rsum.alloc(8 * (size_t)N);
+    if (!e) e = rmax.alloc(8 * (size_t)N);
+    if (!e) e = bad.alloc(4);
+    if (!e) e = flags.alloc(4 * (size_t)B);
+    if (!e) e = hipMemset(bad.p, 0, 4);
+    if (!e) e = hipMemset(flags.p, 0, 4 * (size_t)B);
+    if (!e) e = dd::launch_row_stats(raw, k->is_f64, N, B, rsum.as<double>(), rmax.as<double>(),
+                                     bad.as<int32_t>(), nullptr);
+    if (!e) e = dd::launch_col_nonzero(raw, k->is_f64, N, B, flags.as<int32_t>(), nullptr);
+    if (!e) e = hipDeviceSynchronize();
+    if (e) return bail(fail(DD_EDEVICE, "row statistics: %s", hipGetErrorString(e)));
+  }
+  int32_t nbad = 0;
+  std::vector<int32_t> fl(B);
+  k->W_host.assign(N, 0.0);
+  if (hipMemcpy(&nbad, bad.p, 4, hipMemcpyDeviceToHost) ||
+      hipMemcpy(fl.data(), flags.p, 4 * (size_t)B, hipMemcpyDeviceToHost) ||
+      hipMemcpy(k->W_host.data(), rsum.p, 8 * (size_t)N, hipMemcpyDeviceToHost))
+    return bail(fail(DD_EDEVICE, "copy of row statistics failed"));
+  if (nbad > 0)
+    return bail(fail(DD_EINVAL,
+                     "%d rows hold entries that are negative, not finite, or positive below "
+                     "the FP32 normal range",
+                     nbad));
+  if (o.validate) {
+    const double tol = k->is_f64 ? 1e-9 : 1e-5;
+    for (int32_t x = 0; x < N; ++x)
+      if (!(std::fabs(k->W_host[x] - 1.0) <= tol))
+        return bail(fail(DD_EINVAL, "row %d sums to %.17g, not 1", x, k->W_host[x]));
+  }
+  std::vector<int32_t> kept;
+  for (int32_t b = 0; b < B; ++b)
+    if (fl[b]) kept.push_back(b);
+  if (kept.empty()) return bail(fail(DD_EINVAL, "every column is zero"));
+  k->B = (int32_t)kept.size();
+  k->ld = ((int64_t)k->B + 3) & ~int64_t(3);
+
+  // compact the kept columns into padded FP32 rows (+ FP64 master)
+  {
+    DevBuf kept_d;
+    hipError_t e = kept_d.alloc(4 * kept.size());
+    if (!e) e = hipMemcpy(kept_d.p, kept.data(), 4 * kept.size(), hipMemcpyHostToDevice);
+    if (!e) e = k->P32.alloc(4 * (size_t)N * (size_t)k->ld);
+    if (!e && k->is_f64) e = k->P64.alloc(8 * (size_t)N * (size_t)k->B);
+    if (!e) e = dd::launch_gather_cols(raw, k->is_f64, N, B, kept_d.as<const int32_t>(), k->B,
+                                       k->ld, k->P32.as<float>(),
+                                       k->is_f64 ? k->P64.as<double>() : nullptr, nullptr);
+    if (!e) e = hipDeviceSynchronize();
+    if (e) return bail(fail(DD_EDEVICE, "column compaction: %s", hipGetErrorString(e)));
+  }
+  raw_own.release();
+
+  if (o.tau > 0.0) {
+    if (k->B > 65535) return bail(fail(DD_EINVAL, "CSR columns are 16-bit: B=%d", k->B));
+    if (dd_status s = build_csr_from_dense(k, k->dense(), rmax)) return bail(s);
+    if (dd_status s = csr_row_constants(k)) return bail(s);
+    k->P32.release();
+    k->P64.release();
+  } else {
+    hipError_t e = k->H.alloc(8 * (size_t)N);
+    if (!e) e = dd::launch_row_entropy(k->dense(), k->H.as<double>(), nullptr);
+    if (!e) e = hipDeviceSynchronize();
+    k->H_host.assign(N, 0.0);
+    if (!e) e = hipMemcpy(k->H_host.data(), k->H.p, 8 * (size_t)N, hipMemcpyDeviceToHost);
+    if (e) return bail(fail(DD_EDEVICE, "row entropy: %s", hipGetErrorString(e)));
+    if (o.gemm_form != DD_FORM_NONE) {
+      std::vector<double> mx(N);
+      if (hipMemcpy(mx.data(), rmax.p, 8 * (size_t)N, hipMemcpyDeviceToHost))
+        return bail(fail(DD_EDEVICE, "copy of row maxima failed"));
+      e = k->Off.alloc(4 * (size_t)N);
+      if (!e && o.gemm_form == DD_FORM_F32) e = k->L32.alloc(4 * (size_t)N * (size_t)k->ld);
+      if (!e && o.gemm_form == DD_FORM_F16X3) {
+        e = k->Lhi.alloc(2 * (size_t)N * (size_t)k->ld);
+        if (!e) e = k->Llo.alloc(2 * (size_t)N * (size_t)k->ld);
+      }
+      if (!e) e = dd::launch_log_forms(k->dense(), o.gemm_form, k->L32.as<float>(),
+                                       k->Lhi.as<uint16_t>(), k->Llo.as<uint16_t>(),
+                                       k->Off.as<float>(), nullptr);
+      if (!e) e = hipDeviceSynchronize();
+      if (e) return bail(fail(DD_EDEVICE, "log-kernel operand: %s", hipGetErrorString(e)));
+      k->gemm_form = o.gemm_form;
+    }
+  }
+  if (dd_status s = upload_adjacency(k, adj)) return bail(s);
+  return finish_handle(k, ctx, out);
+}
+
+dd_status dd_load_kernel_csr(dd_ctx* ctx, int32_t N, int32_t B, const int64_t* row_ptr,
+                             const int32_t* col, const void* val, int32_t val_is_f64,
+                             const double* row_max, double tau, int32_t tau_relative,
+                             const dd_adjacency* adj, const dd_load_opts* opts,
+                             dd_kernel** out) {
+  if (!ctx_ok(ctx)) return fail(DD_ESTATE, "not a live context");
+  if (!out || !row_ptr || !col || !val || !row_max) return fail(DD_EINVAL, "null argument");
+  if (N <= 0 || B <= 0) return fail(DD_EINVAL, "N=%d B=%d must be positive", N, B);
+  if (B > kMaxB) return fail(DD_EINVAL, "B=%d exceeds the supported %d columns", B, kMaxB);
+  if (!(tau > 0.0) || !(tau <= 1.0)) return fail(DD_EINVAL, "tau must be in (0, 1]");
+  const dd_load_opts o = opts ? *opts : default_opts();
+  if (o.gemm_form != DD_FORM_NONE)
+    return fail(DD_EINVAL, "a truncated load has no batched-KL operand");
+  if (dd_status s = check_adjacency(N, adj)) return s;
+  if (row_ptr[0] != 0) return fail(DD_EINVAL, "row_ptr[0] != 0");
+  std::vector<int64_t> st(N);
+  std::vector<int32_t> ln(N);
+  int64_t pos = 0;
+  for (int32_t x = 0; x < N; ++x) {
+    const int64_t b = row_ptr[x], e = row_ptr[x + 1];
+    if (e <= b) return fail(DD_EINVAL, "row %d is empty or row_ptr decreases", x);
+    if (!(row_max[x] > 0.0) || !std::isfinite(row_max[x]))
+      return fail(DD_EINVAL, "row_max[%d] must be positive and finite", x);
+    for (int64_t i = b; i < e; ++i) {
+      const int32_t c = col[i];
+      const double v = val_is_f64 ? static_cast<const double*>(val)[i]
+                                  : (double)static_cast<const float*>(val)[i];
+      if (c < 0 || c >= B) return fail(DD_EINVAL, "column %d of row %d out of range", c, x);
+      if (i > b && col[i - 1] >= c)
+        return fail(DD_EINVAL, "columns of row %d not strictly ascending", x);
+      if (!(v > 0.0) || !std::isfinite(v) || v < 1.17549435e-38)
+        return fail(DD_EINVAL, "stored value of row %d must be positive, finite, FP32-normal", x);
+    }
+    st[x] = pos;
+    ln[x] = (int32_t)(e - b);
+    pos += (ln[x] + 3) & ~3;
+  }
+  HIP_OR(hipSetDevice(ctx->device));
+  if (dd_status s = check_free((size_t)pos * (6 + (val_is_f64 ? 8 : 0)) + (size_t)N * 20))
+    return s;
+  dd_kernel* k = new (std::nothrow) dd_kernel;
+  if (!k) return fail(DD_ENOMEM, "host allocation failed");
+  k->ctx = ctx;
+  k->N = N;
+  k->B_in = B;
+  k->B = B;
+  k->is_f64 = val_is_f64 ? 1 : 0;
+  k->is_csr = 1;
+  k->tau = tau;
+  k->tau_relative = tau_relative ? 1 : 0;
+  k->nnz = row_ptr[N];
+  std::vector<uint16_t> colp((size_t)pos, 0);
+  std::vector<float> valp((size_t)pos, 0.f);
+  std::vector<double> val64p(val_is_f64 ? (size_t)pos : 0, 0.0);
+  std::vector<double> phi(N);
+  k->Ht_host.assign(N, 0.0);
+  k->Wt_host.assign(N, 0.0);
+  for (int32_t x = 0; x < N; ++x) {
+    double w = 0.0, h = 0.0;
+    for (int32_t i = 0; i < ln[x]; ++i) {
+      const int64_t src = row_ptr[x] + i;
+      const double v = val_is_f64 ? static_cast<const double*>(val)[src]
+                                  : (double)static_cast<const float*>(val)[src];
+      colp[st[x] + i] = (uint16_t)col[src];
+      valp[st[x] + i] = (float)v;
+      if (val_is_f64) val64p[st[x] + i] = v;
+      w += v;
+      h += v * std::log(v);
+    }
+    k->Wt_host[x] = w;
+    k->Ht_host[x] = h;
+    phi[x] = tau_relative ? tau * row_max[x] : tau;
+  }
+  auto bail = [&](dd_status s) {
+    delete k;
+    return s;
+  };
+  hipError_t e = k->start.alloc(8 * (size_t)N);
+  if (!e) e = k->len.alloc(4 * (size_t)N);
+  if (!e) e = k->col.alloc(2 * (size_t)pos);
+  if (!e) e = k->val.alloc(4 * (size_t)pos);
+  if (!e && val_is_f64) e = k->val64.alloc(8 * (size_t)pos);
+  if (!e) e = k->phi.alloc(8 * (size_t)N);
+  if (!e) e = hipMemcpy(k->start.p, st.data(), 8 * (size_t)N, hipMemcpyHostToDevice);
+  if (!e) e = hipMemcpy(k->len.p, ln.data(), 4 * (size_t)N, hipMemcpyHostToDevice);
+  if (!e) e = hipMemcpy(k->col.p, colp.data(), 2 * (size_t)pos, hipMemcpyHostToDevice);
+  if (!e) e = hipMemcpy(k->val.p, valp.data(), 4 * (size_t)pos, hipMemcpyHostToDevice);
+  if (!e && val_is_f64) e = hipMemcpy(k->val64.p, val64p.data(), 8 * (size_t)pos, hipMemcpyHostToDevice);
+  if (!e) e = hipMemcpy(k->phi.p, phi.data(), 8 * (size_t)N, hipMemcpyHostToDevice);
+  if (e) return bail(fail(DD_EDEVICE, "CSR upload: %s", hipGetErrorString(e)));
+  if (dd_status s = upload_adjacency(k, adj)) return bail(s);
+  return finish_handle(k, ctx, out);
+}
+
+dd_status dd_kernel_get_info(const dd_kernel* k, dd_kernel_info* info) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (!info) return fail(DD_EINVAL, "info is null");
+  info->n = k->N;
+  info->b_in = k->B_in;
+  info->b = k->B;
+  info->is_csr = k->is_csr;
+  info->nnz = k->nnz;
+  info->gemm_form = k->gemm_form;
+  info->has_adjacency = k->has_adj;
+  info->hbm_bytes = k->footprint();
+  return DD_OK;
+}
+
+dd_status dd_distance_field(dd_kernel* k, int32_t target, int32_t kind, float* out_dev,
+                            dd_error_bound* bound, void* stream) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (kind != DD_TV && kind != DD_KL) return fail(DD_EINVAL, "unknown kind %d", kind);
+  if (target < 0 || target >= k->N) return fail(DD_EINVAL, "target %d not in [0, %d)", target, k->N);
+  if (!out_dev) return fail(DD_EINVAL, "out_dev is null");
+  HIP_OR(hipSetDevice(k->ctx->device));
+  if (k->is_csr)
+    HIP_OR(dd::launch_csr_field(k->csr(), target, kind, out_dev, as_stream(stream)));
+  else
+    HIP_OR(dd::launch_dense_field(k->dense(), target, kind, out_dev, as_stream(stream)));
+  if (bound) *bound = field_bound(k, kind, target);
+  return DD_OK;
+}
+
+dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t T, int32_t kind,
+                                   float* out_dev, dd_error_bound* bounds, void* stream) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (kind != DD_TV && kind != DD_KL) return fail(DD_EINVAL, "unknown kind %d", kind);
+  if (T <= 0 || !targets || !out_dev) return fail(DD_EINVAL, "T=%d, targets or out_dev null", T);
+  for (int32_t i = 0; i < T; ++i)
+    if (targets[i] < 0 || targets[i] >= k->N)
+      return fail(DD_EINVAL, "targets[%d]=%d not in [0, %d)", i, targets[i], k->N);
+  HIP_OR(hipSetDevice(k->ctx->device));
+  hipStream_t s = as_stream(stream);
+  if (kind == DD_KL && !k->is_csr && k->gemm_form != DD_FORM_NONE) {
+    dd::GemmView gv{k->L32.as<const float>(), k->Lhi.as<const uint16_t>(),
+                    k->Llo.as<const uint16_t>(), k->Off.as<const float>(),
+                    k->ld, k->N, k->B, k->gemm_form};
+    AsyncBuf tdev(s), ws(s);
+    const size_t wsb = dd::batch_kl_workspace(gv, T);
+    HIP_OR(tdev.alloc(4 * (size_t)T));
+    HIP_OR(ws.alloc(wsb));
+    HIP_OR(hipMemcpyAsync(tdev.p, targets, 4 * (size_t)T, hipMemcpyHostToDevice, s));
+    HIP_OR(dd::launch_batch_kl(k->dense(), gv, tdev.as<const int32_t>(), T, ws.p, wsb, out_dev, s));
+    if (bounds)
+      for (int32_t i = 0; i < T; ++i) bounds[i] = field_bound(k, kind, targets[i]);
+    return DD_OK;
+  }
+  for (int32_t i = 0; i < T; ++i) {
+    float* o = out_dev + (int64_t)i * k->N;
+    if (k->is_csr)
+      HIP_OR(dd::launch_csr_field(k->csr(), targets[i], kind, o, s));
+    else
+      HIP_OR(dd::launch_dense_field(k->dense(), targets[i], kind, o, s));
+    if (bounds) bounds[i] = field_bound(k, kind, targets[i]);
+  }
+  return DD_OK;
+}
+
+dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const int32_t* targets,
+                         int32_t kind, const float* fields_dev, const dd_error_bound* bounds,
+                         int32_t max_steps, int32_t* path_dev, int32_t* len_dev,
+                         int32_t* status_dev, int32_t* rechecks_dev, void* stream) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (!k->has_adj) return fail(DD_EINVAL, "kernel was loaded without adjacency");
+  if (kind != DD_TV && kind != DD_KL) return fail(DD_EINVAL, "unknown kind %d", kind);
+  if (T <= 0 || !sources || !targets || !fields_dev || !bounds || !path_dev || !len_dev ||
+      !status_dev)
+    return fail(DD_EINVAL, "T=%d or a required pointer is null", T);
+  if (max_steps < 0) return fail(DD_EINVAL, "max_steps=%d", max_steps);
+  for (int32_t i = 0; i < T; ++i) {
+    if (sources[i] < 0 || sources[i] >= k->N || targets[i] < 0 || targets[i] >= k->N)
+      return fail(DD_EINVAL, "path %d: source %d / target %d not in [0, %d)", i, sources[i],
+                  targets[i], k->N);
+    if (!(bounds[i].abs >= 0.0) || !(bounds[i].rel >= 0.0))
+      return fail(DD_EINVAL, "bound %d is negative or NaN", i);
+  }
+  HIP_OR(hipSetDevice(k->ctx->device));
+  hipStream_t s = as_stream(stream);
+  // one scratch block: sources, targets, bounds, target rows, target constants
+  const size_t o_src = 0, o_tgt = o_src + 4 * (size_t)T;
+  const size_t o_bnd = (o_tgt + 4 * (size_t)T + 15) & ~size_t(15);
+  const size_t o_row = o_bnd + sizeof(dd::Bound) * (size_t)T;
+  const size_t o_con = o_row + 8 * (size_t)T * (size_t)k->B;
+  const size_t total = o_con + 32 * (size_t)T;
+  std::vector<unsigned char> host(o_row);
+  std::memcpy(host.data() + o_src, sources, 4 * (size_t)T);
+  std::memcpy(host.data() + o_tgt, targets, 4 * (size_t)T);
+  for (int32_t i = 0; i < T; ++i) {
+    dd::Bound b{bounds[i].abs, bounds[i].rel};
+    std::memcpy(host.data() + o_bnd + sizeof(dd::Bound) * i, &b, sizeof b);
+  }
+  AsyncBuf ws(s);
+  HIP_OR(ws.alloc(total));
+  unsigned char* base = ws.as<unsigned char>();
+  HIP_OR(hipMemcpyAsync(base, host.data(), o_row, hipMemcpyHostToDevice, s));
+  const int32_t* tdev = reinterpret_cast<const int32_t*>(base + o_tgt);
+  double* trow = reinterpret_cast<double*>(base + o_row);
+  double* tcon = reinterpret_cast<double*>(base + o_con);
+  HIP_OR(dd::launch_target_rows(k->dense(), k->csr(), k->is_csr, tdev, T, trow, tcon, s));
+  dd::PathArgs a;
+  a.adj_ptr = k->adj_ptr.as<const int64_t>();
+  a.adj_idx = k->adj_idx.as<const int32_t>();
+  a.fields = fields_dev;
+  a.bounds = reinterpret_cast<const dd::Bound*>(base + o_bnd);
+  a.sources = reinterpret_cast<const int32_t*>(base + o_src);
+  a.targets = tdev;
+  a.trow = trow;
+  a.tconst = tcon;
+  a.path = path_dev;
+  a.len = len_dev;
+  a.status = status_dev;
+  a.rechecks = rechecks_dev;
+  a.T = T;
+  a.max_steps = max_steps;
+  a.kind = kind;
+  a.is_csr = k->is_csr;
+  HIP_OR(dd::launch_paths(k->dense(), k->csr(), a, s));
+  return DD_OK;
+}
+
+dd_status dd_plan_path(dd_kernel* k, int32_t source, int32_t target, int32_t kind,
+                       int32_t max_steps, int32_t* path_host, int32_t* len, int32_t* status,
+                       int32_t* rechecks, void* stream) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (!k->has_adj) return fail(DD_EINVAL, "kernel was loaded without adjacency");
+  if (!path_host || !len || !status) return fail(DD_EINVAL, "null output");
+  if (max_steps < 0) return fail(DD_EINVAL, "max_steps=%d", max_steps);
+  if (source < 0 || source >= k->N || target < 0 || target >= k->N)
+    return fail(DD_EINVAL, "source %d / target %d not in [0, %d)", source, target, k->N);
+  if (kind != DD_TV && kind != DD_KL) return fail(DD_EINVAL, "unknown kind %d", kind);
+  HIP_OR(hipSetDevice(k->ctx->device));
+  hipStream_t s = as_stream(stream);
+  AsyncBuf field(s), pbuf(s);
+  HIP_OR(field.alloc(4 * (size_t)k->N));
+  HIP_OR(pbuf.alloc(4 * ((size_t)max_steps + 1 + 3)));
+  dd_error_bound b;
+  if (dd_status st = dd_distance_field(k, target, kind, field.as<float>(), &b, stream)) return st;
+  int32_t* pd = pbuf.as<int32_t>();
+  int32_t* tail = pd + max_steps + 1;
+  if (dd_status st = dd_trace_paths(k, 1, &source, &target, kind, field.as<const float>(), &b,
+                                    max_steps, pd, tail, tail + 1, tail + 2, stream))
+    return st;
+  int32_t info[3];
+  HIP_OR(hipMemcpyAsync(path_host, pd, 4 * ((size_t)max_steps + 1), hipMemcpyDeviceToHost, s));
+  HIP_OR(hipMemcpyAsync(info, tail, sizeof info, hipMemcpyDeviceToHost, s));
+  HIP_OR(hipStreamSynchronize(s));
+  *len = info[0];
+  *status = info[1];
+  if (rechecks) *rechecks = info[2];
+  return DD_OK;
+}
+
+dd_status dd_free_kernel(dd_kernel* k) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  hipSetDevice(k->ctx->device);
+  hipDeviceSynchronize();
+  k->ctx->live_kernels--;
+  k->magic = kDead;
+  delete k;
+  return DD_OK;
+}
+
+}  // extern "C"

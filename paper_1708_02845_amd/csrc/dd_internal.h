@@ -1,0 +1,91 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dd {
+
+constexpr int kWave = 64;
+
+// Dense resident form: FP32 rows of the kept columns, row stride `ld`
+// (a multiple of 4 floats, zero padded), plus an optional FP64 master when
+// the matrix was loaded in FP64.
+struct DenseView {
+  const float* P;      // [N][ld]
+  const double* P64;   // [N][B] or nullptr (then P is the master)
+  int64_t ld;
+  int32_t N, B;
+};
+
+// Truncated resident form.  Row x occupies [start[x], start[x] + len[x]) of
+// col/val; start[x] is a multiple of 4.  Padding slots hold col 0, val 0.
+struct CsrView {
+  const int64_t* start;  // [N]
+  const int32_t* len;    // [N]
+  const uint16_t* col;   // [nnz_padded]
+  const float* val;      // [nnz_padded]
+  const double* val64;   // [nnz_padded] or nullptr
+  const double* phi;     // [N] floor of each row (the truncation threshold)
+  int32_t N, B;
+};
+
+struct Bound {
+  double abs, rel;
+};
+
+// ---- load-time conversion (convert.hip) ----
+hipError_t launch_row_stats(const void* raw, int is_f64, int32_t N, int32_t B, double* row_sum,
+                            double* row_max, int32_t* bad_rows, hipStream_t s);
+hipError_t launch_col_nonzero(const void* raw, int is_f64, int32_t N, int32_t B, int32_t* flags,
+                              hipStream_t s);
+hipError_t launch_gather_cols(const void* raw, int is_f64, int32_t N, int32_t B,
+                              const int32_t* kept, int32_t Bk, int64_t ld, float* out32,
+                              double* out64, hipStream_t s);
+hipError_t launch_row_entropy(DenseView v, double* H, hipStream_t s);
+hipError_t launch_trunc_count(DenseView v, const double* thr, int32_t* counts, hipStream_t s);
+hipError_t launch_trunc_fill(DenseView v, const double* thr, const int64_t* start, uint16_t* col,
+                             float* val, double* val64, hipStream_t s);
+hipError_t launch_log_forms(DenseView v, int form, float* l32, uint16_t* lhi, uint16_t* llo,
+                            float* offset, hipStream_t s);
+
+// ---- streaming fields (stream.hip) ----
+hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out, hipStream_t s);
+hipError_t launch_csr_field(CsrView v, int32_t target, int kind, float* out, hipStream_t s);
+
+// ---- batched KL contraction (gemm.hip) ----
+struct GemmView {
+  const float* l32;      // [N][ld] log P - o_x  (form F32)
+  const uint16_t* lhi;   // [N][ld] FP16 bits    (form F16X3)
+  const uint16_t* llo;
+  const float* offset;   // [N] o_x
+  int64_t ld;
+  int32_t N, B, form;
+};
+hipError_t launch_batch_kl(DenseView dv, GemmView gv, const int32_t* targets_dev, int32_t T,
+                           void* workspace, size_t ws_bytes, float* out, hipStream_t s);
+size_t batch_kl_workspace(GemmView gv, int32_t T);
+
+// ---- paths (path.hip) ----
+struct PathArgs {
+  const int64_t* adj_ptr;
+  const int32_t* adj_idx;
+  const float* fields;      // [T][N]
+  const Bound* bounds;      // [T] device
+  const int32_t* sources;   // [T]
+  const int32_t* targets;   // [T]
+  const double* trow;       // [T][B] FP64 target rows (dense or truncated)
+  const double* tconst;     // [T][4]: W_t, H_t (natural log), |S_t|, unused
+  int32_t* path;            // [T][max_steps+1]
+  int32_t* len;             // [T]
+  int32_t* status;          // [T]
+  int32_t* rechecks;        // [T] or nullptr
+  int32_t T, max_steps, kind, is_csr;
+};
+hipError_t launch_target_rows(DenseView dv, CsrView cv, int is_csr, const int32_t* targets,
+                              int32_t T, double* trow, double* tconst, hipStream_t s);
+hipError_t launch_paths(DenseView dv, CsrView cv, PathArgs a, hipStream_t s);
+
+int num_cus();
+
+}  // namespace dd

@@ -1,0 +1,279 @@
+// Streaming distance fields: one pass over the kernel rows for one target.
+//
+// TV (Section IV, eq. 34):  d(x) = sum_b |p_b - q_b|
+// KL (Section IV, eq. 35):  d(x) = sum_b p_b log(p_b / q_b), p = target row
+//
+// Mapping (gfx950): a group of LPR lanes (16, 32 or 64) owns one row x and
+// sweeps it with 16-byte loads, UNROLL loads in flight per lane; the target
+// row p (and log2 p for KL) sits in LDS, staged once per workgroup; the group
+// then reduces its FP64 partial sums with cross-lane shuffles.  Workgroups
+// stride over rows, so the grid is sized to the machine, not to N.
+//
+// KL evaluates each term as p_b * (log2 p_b - log2 q_b) with the hardware
+// log2 (v_log_f32) applied to both operands, so the target's own row gives
+// exactly 0; the ln 2 factor is applied once per row in FP64.  Four FP32
+// terms are summed in FP32, then carried in FP64.
+#include "dd_internal.h"
+
+namespace dd {
+
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
+// 16-byte streaming load (non-temporal: the rows are read once per field).
+__device__ __forceinline__ float4 ld_stream(const float4* p) {
+  const vf4 v = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ float kl_term(float p, float lp, float q) {
+  return p > 0.f ? p * (lp - hw_log2(q)) : 0.f;
+}
+
+template <int LPR, int KIND, int UNROLL>
+__global__ __launch_bounds__(256) void dense_field_kernel(const float* __restrict__ P, int64_t ld,
+                                                          int32_t N, int32_t target,
+                                                          float* __restrict__ out) {
+  extern __shared__ float4 smem4[];
+  const int nv = (int)(ld >> 2);
+  float4* sp = smem4;
+  float4* sl = smem4 + nv;
+  const float4* trow = reinterpret_cast<const float4*>(P + (int64_t)target * ld);
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    float4 p = trow[i];
+    sp[i] = p;
+    if (KIND == 1) {
+      float4 l;
+      l.x = p.x > 0.f ? hw_log2(p.x) : 0.f;
+      l.y = p.y > 0.f ? hw_log2(p.y) : 0.f;
+      l.z = p.z > 0.f ? hw_log2(p.z) : 0.f;
+      l.w = p.w > 0.f ? hw_log2(p.w) : 0.f;
+      sl[i] = l;
+    }
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & (LPR - 1);
+  const int grp = threadIdx.x / LPR;
+  const int gpb = blockDim.x / LPR;
+  for (int64_t row = (int64_t)blockIdx.x * gpb + grp; row < N; row += (int64_t)gridDim.x * gpb) {
+    const float4* q = reinterpret_cast<const float4*>(P + row * ld);
+    double acc = 0.0;
+    for (int base = lane; base < nv; base += LPR * UNROLL) {
+      float4 v[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const int i = base + u * LPR;
+        v[u] = i < nv ? ld_stream(q + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const int i = base + u * LPR;
+        if (i < nv) {
+          const float4 p = sp[i];
+          float s;
+          if (KIND == 0) {
+            s = (fabsf(p.x - v[u].x) + fabsf(p.y - v[u].y)) +
+                (fabsf(p.z - v[u].z) + fabsf(p.w - v[u].w));
+          } else {
+            const float4 l = sl[i];
+            s = (kl_term(p.x, l.x, v[u].x) + kl_term(p.y, l.y, v[u].y)) +
+                (kl_term(p.z, l.z, v[u].z) + kl_term(p.w, l.w, v[u].w));
+          }
+          acc += (double)s;
+        }
+      }
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
+    if (lane == 0) out[row] = (float)(KIND == 1 ? acc * 0.69314718055994530942 : acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Truncated (CSR) rows.  The truncated target row p~ is scattered into LDS as
+// a dense vector (zeros where dropped).  For row x with stored support S_x:
+//   TV_tau(x) = sum_{b in S_x} |q_b - p~_b| + sum_{b in S_t \ S_x} p~_b
+//   KL_tau(x) = sum_{b in S_x} p~_b (log p~_b - log q_b)
+//             + sum_{b in S_t \ S_x} p~_b (log p~_b - log phi_x)
+// The S_t \ S_x sums are W_t - A_x and (Hb_t - E_x) - log2 phi_x (W_t - A_x),
+// with A_x, E_x the sums of p~_b and p~_b log2 p~_b over S_x; they are exactly
+// 0 when every b of S_t is stored in row x (counted, not inferred from FP64).
+template <int LPR, int KIND>
+__global__ __launch_bounds__(256) void csr_field_kernel(CsrView v, int32_t target,
+                                                        float* __restrict__ out) {
+  extern __shared__ float smemf[];
+  const int Bp = (v.B + 3) & ~3;
+  float* sp = smemf;
+  float* sl = smemf + Bp;
+  __shared__ double red[3][8];
+  __shared__ int redc[8];
+  for (int i = threadIdx.x; i < Bp; i += blockDim.x) {
+    sp[i] = 0.f;
+    sl[i] = 0.f;
+  }
+  __syncthreads();
+  const int64_t ts = v.start[target];
+  const int tl = v.len[target];
+  double w = 0.0, hb = 0.0;
+  int cnt = 0;
+  for (int i = threadIdx.x; i < tl; i += blockDim.x) {
+    const int b = v.col[ts + i];
+    const float p = v.val[ts + i];
+    const float l = hw_log2(p);
+    sp[b] = p;
+    sl[b] = l;
+    w += (double)p;
+    hb += (double)(p * l);
+    cnt += 1;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    w += __shfl_xor(w, off);
+    hb += __shfl_xor(hb, off);
+    cnt += __shfl_xor(cnt, off);
+  }
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wid] = w;
+    red[1][wid] = hb;
+    redc[wid] = cnt;
+  }
+  __syncthreads();
+  double Wt = 0.0, Hbt = 0.0;
+  int St = 0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+    Wt += red[0][i];
+    Hbt += red[1][i];
+    St += redc[i];
+  }
+
+  const int lane = threadIdx.x & (LPR - 1);
+  const int grp = threadIdx.x / LPR;
+  const int gpb = blockDim.x / LPR;
+  for (int64_t row = (int64_t)blockIdx.x * gpb + grp; row < v.N; row += (int64_t)gridDim.x * gpb) {
+    const int64_t s = v.start[row];
+    const int n = v.len[row];
+    const float4* val4 = reinterpret_cast<const float4*>(v.val + s);
+    const ushort4* col4 = reinterpret_cast<const ushort4*>(v.col + s);
+    const int nv = (n + 3) >> 2;
+    double acc = 0.0, A = 0.0, E = 0.0;
+    int c = 0;
+    for (int i = lane; i < nv; i += LPR) {
+      const float4 q = ld_stream(val4 + i);
+      const ushort4 cb = col4[i];
+      const int rem = n - 4 * i;
+      float qv[4] = {q.x, q.y, q.z, q.w};
+      int bv[4] = {cb.x, cb.y, cb.z, cb.w};
+      float ts4 = 0.f, as4 = 0.f, es4 = 0.f;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (e < rem) {
+          const float p = sp[bv[e]];
+          as4 += p;
+          c += p > 0.f;
+          if (KIND == 0) {
+            ts4 += fabsf(qv[e] - p);
+          } else {
+            const float l = sl[bv[e]];
+            ts4 += kl_term(p, l, qv[e]);
+            es4 += p * l;
+          }
+        }
+      }
+      acc += (double)ts4;
+      A += (double)as4;
+      if (KIND == 1) E += (double)es4;
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+      acc += __shfl_xor(acc, off, LPR);
+      A += __shfl_xor(A, off, LPR);
+      if (KIND == 1) E += __shfl_xor(E, off, LPR);
+      c += __shfl_xor(c, off, LPR);
+    }
+    if (lane == 0) {
+      double d;
+      const bool complete = (c == St);
+      if (KIND == 0) {
+        d = acc + (complete ? 0.0 : (Wt - A));
+      } else {
+        const double miss = complete ? 0.0 : (Hbt - E) - log2(v.phi[row]) * (Wt - A);
+        d = (acc + miss) * 0.69314718055994530942;
+      }
+      out[row] = (float)d;
+    }
+  }
+}
+
+int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    if (n <= 0) n = 256;
+  }
+  return n;
+}
+
+template <typename K>
+static hipError_t allow_lds(K kern, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+static int grid_for(int64_t groups_needed, int gpb, size_t lds) {
+  const int64_t need = (groups_needed + gpb - 1) / gpb;
+  int per_cu = lds > 0 ? (int)((160 * 1024) / (lds + 1024)) : 8;
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 8) per_cu = 8;
+  const int64_t cap = (int64_t)num_cus() * per_cu;
+  return (int)(need < cap ? (need > 0 ? need : 1) : cap);
+}
+
+template <int LPR, int KIND>
+static hipError_t dense_launch(DenseView v, int32_t target, float* out, hipStream_t s) {
+  constexpr int UNROLL = (LPR == 64) ? 4 : (LPR == 32 ? 4 : 4);
+  auto kern = dense_field_kernel<LPR, KIND, UNROLL>;
+  const size_t lds = (size_t)v.ld * sizeof(float) * (KIND == 1 ? 2 : 1);
+  hipError_t e = allow_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  const int threads = 256;
+  const int grid = grid_for(v.N, threads / LPR, lds);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v.P, v.ld, v.N, target, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out, hipStream_t s) {
+  const int64_t nv = v.ld / 4;
+  if (kind == 0) {
+    if (nv >= 256) return dense_launch<64, 0>(v, target, out, s);
+    if (nv >= 128) return dense_launch<32, 0>(v, target, out, s);
+    return dense_launch<16, 0>(v, target, out, s);
+  }
+  if (nv >= 256) return dense_launch<64, 1>(v, target, out, s);
+  if (nv >= 128) return dense_launch<32, 1>(v, target, out, s);
+  return dense_launch<16, 1>(v, target, out, s);
+}
+
+template <int LPR, int KIND>
+static hipError_t csr_launch(CsrView v, int32_t target, float* out, hipStream_t s) {
+  auto kern = csr_field_kernel<LPR, KIND>;
+  const size_t lds = (size_t)((v.B + 3) & ~3) * sizeof(float) * 2;
+  hipError_t e = allow_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  const int threads = 256;
+  const int grid = grid_for(v.N, threads / LPR, lds);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v, target, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_field(CsrView v, int32_t target, int kind, float* out, hipStream_t s) {
+  // lanes per row from the mean stored row length
+  if (kind == 0) return csr_launch<64, 0>(v, target, out, s);
+  return csr_launch<64, 1>(v, target, out, s);
+}
+
+}  // namespace dd

@@ -1,0 +1,187 @@
+"""GPU parity of the streaming TV/KL fields (eqs. 34, 35) against the FP64 oracle.
+
+Gate: normwise error max|d_hat - d| / max|d| <= 1e-5 and every entry inside
+the bound the library states for that field.
+"""
+
+import numpy as np
+import pytest
+
+from conftest import normwise, within_bound
+from oracle import divergence as dv
+from workloads import build_config, grid_domain
+from workloads.seeds import targets_sources
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def random_kernel(N, B, seed):
+    g = np.random.default_rng(seed)
+    P = g.random((N, B)) ** 2 + 1e-3
+    P /= P.sum(axis=1, keepdims=True)
+    return P.astype(np.float32)
+
+
+def oracle_field(P, t, kind):
+    P64 = np.asarray(P, dtype=np.float64)
+    return dv.tv_field(P64, t) if kind == "tv" else dv.kl_field(P64, t)
+
+
+def run_field(kern, t, kind):
+    d, b = kern.field(t, kind)
+    return d.cpu().numpy(), b
+
+
+@pytest.mark.parametrize("B", [1, 3, 5, 63, 64, 65, 255, 256, 257, 511, 1023, 1024, 1025, 4099])
+@pytest.mark.parametrize("kind", ["tv", "kl"])
+def test_ragged_widths(gpu_ctx, B, kind):
+    from paper_1708_02845_amd import Kernel
+    N = 37
+    P = random_kernel(N, B, seed=B)
+    k = Kernel.load_dense(gpu_ctx, P)
+    try:
+        for t in (0, 5, N - 1):
+            d, b = run_field(k, t, kind)
+            ref = oracle_field(P, t, kind)
+            assert d[t] == 0.0
+            assert normwise(d, ref) <= TOL
+            assert within_bound(d, ref, b)
+    finally:
+        k.free()
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 17, 1000, 4097])
+def test_ragged_row_counts(gpu_ctx, N):
+    from paper_1708_02845_amd import Kernel
+    P = random_kernel(N, 300, seed=N)
+    k = Kernel.load_dense(gpu_ctx, P)
+    try:
+        for kind in ("tv", "kl"):
+            d, b = run_field(k, N // 2, kind)
+            ref = oracle_field(P, N // 2, kind)
+            assert normwise(d, ref) <= TOL and within_bound(d, ref, b)
+    finally:
+        k.free()
+
+
+@pytest.fixture(scope="module")
+def disk_kernel(gpu_ctx):
+    from paper_1708_02845_amd import Kernel
+    inst = build_config("c1")
+    k = Kernel.load_dense(gpu_ctx, inst.P, adjacency=(inst.adj_ptr, inst.adj_idx))
+    yield inst, k
+    k.free()
+
+
+@pytest.mark.parametrize("kind", ["tv", "kl"])
+def test_unit_disk_fp64_input(disk_kernel, kind):
+    inst, k = disk_kernel
+    assert (k.N, k.B) == (4096, 256)
+    targets, _ = targets_sources(0, inst.N, 4)
+    for t in targets:
+        d, b = run_field(k, int(t), kind)
+        ref = oracle_field(inst.P, int(t), kind)
+        assert d[t] == 0.0
+        assert normwise(d, ref) <= TOL
+        assert within_bound(d, ref, b)
+
+
+@pytest.fixture(scope="module")
+def grid65(gpu_ctx):
+    from paper_1708_02845_amd import Kernel
+    g = grid_domain(65, 2, (0.1, 0.3), config_id=21)
+    P = g.poisson_kernel().astype(np.float32)
+    k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
+    yield g, P, k
+    k.free()
+
+
+def test_zero_columns_are_dropped(grid65):
+    g, P, k = grid65
+    assert k.B_in == g.K and k.B == g.K - 4
+
+
+@pytest.mark.parametrize("kind", ["tv", "kl"])
+def test_small_grid_fields(grid65, kind):
+    g, P, k = grid65
+    for t in (0, 123, g.N - 1):
+        d, b = run_field(k, t, kind)
+        ref = oracle_field(P, t, kind)
+        assert normwise(d, ref) <= TOL and within_bound(d, ref, b)
+
+
+def test_runs_are_bitwise_deterministic(grid65):
+    g, P, k = grid65
+    a, _ = run_field(k, 77, "kl")
+    b, _ = run_field(k, 77, "kl")
+    assert np.array_equal(a, b)
+
+
+def test_streaming_batch_equals_single_fields(grid65):
+    g, P, k = grid65
+    ts = [3, 77, 900, 3]
+    for kind in ("tv", "kl"):
+        D, bounds = k.batch_fields(ts, kind)
+        D = D.cpu().numpy()
+        for i, t in enumerate(ts):
+            d, b = run_field(k, t, kind)
+            assert np.array_equal(D[i], d)
+            assert bounds[i] == b
+
+
+def test_device_resident_input_matches_host_input(gpu_ctx, grid65):
+    import torch
+    from paper_1708_02845_amd import Kernel
+    g, P, k = grid65
+    kd = Kernel.load_dense(gpu_ctx, torch.from_numpy(P).cuda())
+    try:
+        for kind in ("tv", "kl"):
+            assert np.array_equal(run_field(kd, 200, kind)[0], run_field(k, 200, kind)[0])
+    finally:
+        kd.free()
+
+
+def test_invalid_inputs_are_rejected(gpu_ctx, grid65):
+    from paper_1708_02845_amd import DDError, Kernel
+    g, P, k = grid65
+    bad = random_kernel(10, 20, 1)
+    for mutate in (lambda a: a.__setitem__((3, 4), -1e-3),
+                   lambda a: a.__setitem__((3, 4), np.nan),
+                   lambda a: a.__setitem__((3, 4), a[3, 4] + 0.01),
+                   lambda a: a.__setitem__((2, 2), 1e-40)):
+        a = bad.copy()
+        mutate(a)
+        with pytest.raises(DDError, match="DD_EINVAL"):
+            Kernel.load_dense(gpu_ctx, a)
+    with pytest.raises(DDError, match="DD_EINVAL"):
+        k.field(g.N, "kl")
+    with pytest.raises(DDError, match="DD_EINVAL"):
+        k.field(-1, "tv")
+    with pytest.raises(ValueError):
+        k.field(0, "hellinger")
+    with pytest.raises(DDError, match="DD_EINVAL"):
+        Kernel.load_dense(gpu_ctx, np.zeros((4, 8), dtype=np.float32), validate=False)
+
+
+@pytest.fixture(scope="module")
+def grid257(gpu_ctx):
+    """The 257x257, 3-obstacle workload at its full size (FP32 dense)."""
+    from paper_1708_02845_amd import Kernel
+    g = build_config("c2")
+    P = g.poisson_kernel(dtype=np.float32)
+    k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
+    yield g, P, k
+    k.free()
+
+
+@pytest.mark.parametrize("kind", ["tv", "kl"])
+def test_grid257_full_size(grid257, kind):
+    g, P, k = grid257
+    t = int(targets_sources(1, g.N, 1)[0][0])
+    d, b = run_field(k, t, kind)
+    ref = oracle_field(P, t, kind)
+    assert d[t] == 0.0
+    assert normwise(d, ref) <= TOL
+    assert within_bound(d, ref, b)
