@@ -35,6 +35,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--max-steps", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--setup-workers", type=int, default=None,
+                    help="processes that build the kernel matrix (1 = in-process; use 1 "
+                         "under a profiler that initialises the GPU before main)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain 1 GiB device copy first (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -78,10 +83,17 @@ def main():
 
     tau = 1e-6
     g = build_config("c2")
-    P = g.poisson_kernel(dtype=np.float32)
+    P = g.poisson_kernel(dtype=np.float32, workers=args.setup_workers)
     t_arr, s_arr = targets_sources(1, g.N, 1)
     t, s = int(t_arr[0]), int(s_arr[0])
     adj = (g.adj_ptr, g.adj_idx)
+
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ctx = Context(0)
     kd = Kernel.load_dense(ctx, P, adjacency=adj)
@@ -146,6 +158,7 @@ def main():
                                "frac": round(gbs / HBM_PEAK_GBS, 4)})
     dom = max(traffic, key=lambda n: avg_us[n])
     path_len = int(res_kl[1][0].item())
+    rechecks = [int(res_kl[3][0].item()), int(res_tv[3][0].item())]
     entries_per_step = 4 * N * B
     value = entries_per_step / (ms_per_step * 1e-3)
 
@@ -165,7 +178,8 @@ def main():
         "config": {"workload": "grid 257x257, 3 rectangular obstacles, dense + CSR tau=1e-6, "
                                "1 target: TV, KL, TV_tau, KL_tau fields + 2 paths",
                    "N": N, "B": B, "csr_nnz": nnz, "targets": 1, "fields_per_step": 4,
-                   "kl_path_vertices": path_len, "cache": "warm (no flush between steps)"},
+                   "kl_path_vertices": path_len, "fp64_rechecks_kl_tv": rechecks,
+                   "cache": "warm (no flush between steps)"},
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": round(traffic[dom] / (avg_us[dom] * 1e-6) / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -110,13 +110,14 @@ struct dd_kernel {
   int64_t nnz = 0;
   std::vector<double> Ht_host, Wt_host;   // per row over the stored entries
   // adjacency
-  DevBuf adj_ptr, adj_idx;
+  DevBuf adj;          // [N][adj_w] int32, -1 padded
+  int32_t adj_w = 0;
   int has_adj = 0;
 
   size_t footprint() const {
     return P32.bytes + P64.bytes + H.bytes + L32.bytes + Lhi.bytes + Llo.bytes + Off.bytes +
            start.bytes + len.bytes + col.bytes + val.bytes + val64.bytes + phi.bytes +
-           adj_ptr.bytes + adj_idx.bytes;
+           adj.bytes;
   }
   dd::DenseView dense() const {
     return dd::DenseView{P32.as<const float>(), P64.as<const double>(), ld, N, B};
@@ -165,15 +166,20 @@ dd_status check_adjacency(int32_t N, const dd_adjacency* adj) {
   return DD_OK;
 }
 
+// The path kernel reads a vertex's neighbours as one padded row (fewer
+// dependent loads per step than row_ptr + col).
 dd_status upload_adjacency(dd_kernel* k, const dd_adjacency* adj) {
   if (!adj) return DD_OK;
-  const int64_t nnz = adj->row_ptr[k->N];
-  HIP_OR(k->adj_ptr.alloc(sizeof(int64_t) * (size_t)(k->N + 1)));
-  HIP_OR(k->adj_idx.alloc(sizeof(int32_t) * (size_t)nnz));
-  HIP_OR(hipMemcpy(k->adj_ptr.p, adj->row_ptr, sizeof(int64_t) * (size_t)(k->N + 1),
-                   hipMemcpyHostToDevice));
-  if (nnz > 0)
-    HIP_OR(hipMemcpy(k->adj_idx.p, adj->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice));
+  int32_t w = 1;
+  for (int32_t v = 0; v < k->N; ++v)
+    w = std::max<int32_t>(w, (int32_t)(adj->row_ptr[v + 1] - adj->row_ptr[v]));
+  std::vector<int32_t> pad((size_t)k->N * (size_t)w, -1);
+  for (int32_t v = 0; v < k->N; ++v)
+    for (int64_t i = adj->row_ptr[v]; i < adj->row_ptr[v + 1]; ++i)
+      pad[(size_t)v * w + (size_t)(i - adj->row_ptr[v])] = adj->col[i];
+  HIP_OR(k->adj.alloc(sizeof(int32_t) * pad.size()));
+  HIP_OR(hipMemcpy(k->adj.p, pad.data(), sizeof(int32_t) * pad.size(), hipMemcpyHostToDevice));
+  k->adj_w = w;
   k->has_adj = 1;
   return DD_OK;
 }
@@ -665,36 +671,11 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
   }
   HIP_OR(hipSetDevice(k->ctx->device));
   hipStream_t s = as_stream(stream);
-  // one scratch block: sources, targets, bounds, target rows, target constants
-  const size_t o_src = 0, o_tgt = o_src + 4 * (size_t)T;
-  const size_t o_bnd = (o_tgt + 4 * (size_t)T + 15) & ~size_t(15);
-  const size_t o_row = o_bnd + sizeof(dd::Bound) * (size_t)T;
-  const size_t o_con = o_row + 8 * (size_t)T * (size_t)k->B;
-  const size_t total = o_con + 32 * (size_t)T;
-  std::vector<unsigned char> host(o_row);
-  std::memcpy(host.data() + o_src, sources, 4 * (size_t)T);
-  std::memcpy(host.data() + o_tgt, targets, 4 * (size_t)T);
-  for (int32_t i = 0; i < T; ++i) {
-    dd::Bound b{bounds[i].abs, bounds[i].rel};
-    std::memcpy(host.data() + o_bnd + sizeof(dd::Bound) * i, &b, sizeof b);
-  }
-  AsyncBuf ws(s);
-  HIP_OR(ws.alloc(total));
-  unsigned char* base = ws.as<unsigned char>();
-  HIP_OR(hipMemcpyAsync(base, host.data(), o_row, hipMemcpyHostToDevice, s));
-  const int32_t* tdev = reinterpret_cast<const int32_t*>(base + o_tgt);
-  double* trow = reinterpret_cast<double*>(base + o_row);
-  double* tcon = reinterpret_cast<double*>(base + o_con);
-  HIP_OR(dd::launch_target_rows(k->dense(), k->csr(), k->is_csr, tdev, T, trow, tcon, s));
   dd::PathArgs a;
-  a.adj_ptr = k->adj_ptr.as<const int64_t>();
-  a.adj_idx = k->adj_idx.as<const int32_t>();
+  std::memset(&a, 0, sizeof a);
+  a.adj = k->adj.as<const int32_t>();
+  a.adj_w = k->adj_w;
   a.fields = fields_dev;
-  a.bounds = reinterpret_cast<const dd::Bound*>(base + o_bnd);
-  a.sources = reinterpret_cast<const int32_t*>(base + o_src);
-  a.targets = tdev;
-  a.trow = trow;
-  a.tconst = tcon;
   a.path = path_dev;
   a.len = len_dev;
   a.status = status_dev;
@@ -703,6 +684,50 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
   a.max_steps = max_steps;
   a.kind = kind;
   a.is_csr = k->is_csr;
+  // scratch: [sources, targets, bounds when T is large] [csr target rows] [neighbour values]
+  const bool inl = T <= dd::kInlinePaths;
+  const size_t o_small = 0;
+  const size_t n_small = inl ? 0 : ((8 * (size_t)T + 15) & ~size_t(15)) + sizeof(dd::Bound) * T;
+  const size_t o_row = (o_small + n_small + 255) & ~size_t(255);
+  const size_t n_row = k->is_csr ? 8 * (size_t)T * (size_t)k->B + 32 * (size_t)T : 0;
+  const size_t o_nv = (o_row + n_row + 255) & ~size_t(255);
+  const size_t n_nv = 4 * (size_t)T * (size_t)k->N * (size_t)k->adj_w;
+  AsyncBuf ws(s);
+  HIP_OR(ws.alloc(o_nv + n_nv));
+  unsigned char* base = ws.as<unsigned char>();
+  std::vector<unsigned char> host;
+  if (inl) {
+    for (int32_t i = 0; i < T; ++i) {
+      a.small.src[i] = sources[i];
+      a.small.tgt[i] = targets[i];
+      a.small.babs[i] = bounds[i].abs;
+      a.small.brel[i] = bounds[i].rel;
+    }
+  } else {
+    const size_t o_bnd = (8 * (size_t)T + 15) & ~size_t(15);
+    host.resize(n_small);
+    std::memcpy(host.data(), sources, 4 * (size_t)T);
+    std::memcpy(host.data() + 4 * (size_t)T, targets, 4 * (size_t)T);
+    for (int32_t i = 0; i < T; ++i) {
+      dd::Bound b{bounds[i].abs, bounds[i].rel};
+      std::memcpy(host.data() + o_bnd + sizeof(dd::Bound) * i, &b, sizeof b);
+    }
+    // pageable source: the copy is staged before hipMemcpyAsync returns
+    HIP_OR(hipMemcpyAsync(base, host.data(), n_small, hipMemcpyHostToDevice, s));
+    a.sources = reinterpret_cast<const int32_t*>(base);
+    a.targets = reinterpret_cast<const int32_t*>(base + 4 * (size_t)T);
+    a.bounds = reinterpret_cast<const dd::Bound*>(base + o_bnd);
+  }
+  if (k->is_csr) {
+    double* trow = reinterpret_cast<double*>(base + o_row);
+    double* tcon = trow + (size_t)T * (size_t)k->B;
+    HIP_OR(dd::launch_target_rows(k->csr(), a, trow, tcon, s));
+    a.trow = trow;
+    a.tconst = tcon;
+  }
+  float* nv = reinterpret_cast<float*>(base + o_nv);
+  HIP_OR(dd::launch_neighbor_values(a, k->N, nv, s));
+  a.nv = nv;
   HIP_OR(dd::launch_paths(k->dense(), k->csr(), a, s));
   return DD_OK;
 }

@@ -67,23 +67,35 @@ hipError_t launch_batch_kl(DenseView dv, GemmView gv, const int32_t* targets_dev
 size_t batch_kl_workspace(GemmView gv, int32_t T);
 
 // ---- paths (path.hip) ----
+// Up to kInlinePaths paths carry their sources, targets and bounds in the
+// kernel arguments (no host-to-device copy per call).
+constexpr int kInlinePaths = 16;
+struct PathSmall {
+  int32_t src[kInlinePaths];
+  int32_t tgt[kInlinePaths];
+  double babs[kInlinePaths];
+  double brel[kInlinePaths];
+};
 struct PathArgs {
-  const int64_t* adj_ptr;
-  const int32_t* adj_idx;
+  const int32_t* adj;       // [N][adj_w] neighbour ids, -1 padded
+  int32_t adj_w;
   const float* fields;      // [T][N]
-  const Bound* bounds;      // [T] device
-  const int32_t* sources;   // [T]
-  const int32_t* targets;   // [T]
-  const double* trow;       // [T][B] FP64 target rows (dense or truncated)
-  const double* tconst;     // [T][4]: W_t, H_t (natural log), |S_t|, unused
+  const float* nv;          // [T][N][adj_w] field value of each neighbour slot (+inf pad)
+  const Bound* bounds;      // [T] device, or nullptr when inline
+  const int32_t* sources;   // [T] device, or nullptr when inline
+  const int32_t* targets;   // [T] device, or nullptr when inline
+  PathSmall small;
+  const double* trow;       // [T][B] FP64 truncated target rows (CSR handles only)
+  const double* tconst;     // [T][4]: W_t, H_t (natural log), |S_t|, unused (CSR only)
   int32_t* path;            // [T][max_steps+1]
   int32_t* len;             // [T]
   int32_t* status;          // [T]
   int32_t* rechecks;        // [T] or nullptr
   int32_t T, max_steps, kind, is_csr;
 };
-hipError_t launch_target_rows(DenseView dv, CsrView cv, int is_csr, const int32_t* targets,
-                              int32_t T, double* trow, double* tconst, hipStream_t s);
+hipError_t launch_target_rows(CsrView cv, PathArgs a, double* trow, double* tconst,
+                              hipStream_t s);
+hipError_t launch_neighbor_values(PathArgs a, int32_t N, float* nv, hipStream_t s);
 hipError_t launch_paths(DenseView dv, CsrView cv, PathArgs a, hipStream_t s);
 
 int num_cus();

@@ -100,19 +100,16 @@ __global__ __launch_bounds__(256) void dense_field_kernel(const float* __restric
 // The S_t \ S_x sums are W_t - A_x and (Hb_t - E_x) - log2 phi_x (W_t - A_x),
 // with A_x, E_x the sums of p~_b and p~_b log2 p~_b over S_x; they are exactly
 // 0 when every b of S_t is stored in row x (counted, not inferred from FP64).
-template <int LPR, int KIND>
+template <int LPR, int KIND, int UNROLL>
 __global__ __launch_bounds__(256) void csr_field_kernel(CsrView v, int32_t target,
                                                         float* __restrict__ out) {
-  extern __shared__ float smemf[];
+  // LDS: the truncated target row as (p, log2 p) pairs, zeros where dropped
+  extern __shared__ float2 smem2[];
   const int Bp = (v.B + 3) & ~3;
-  float* sp = smemf;
-  float* sl = smemf + Bp;
+  float2* spl = smem2;
   __shared__ double red[3][8];
   __shared__ int redc[8];
-  for (int i = threadIdx.x; i < Bp; i += blockDim.x) {
-    sp[i] = 0.f;
-    sl[i] = 0.f;
-  }
+  for (int i = threadIdx.x; i < Bp; i += blockDim.x) spl[i] = make_float2(0.f, 0.f);
   __syncthreads();
   const int64_t ts = v.start[target];
   const int tl = v.len[target];
@@ -122,8 +119,7 @@ __global__ __launch_bounds__(256) void csr_field_kernel(CsrView v, int32_t targe
     const int b = v.col[ts + i];
     const float p = v.val[ts + i];
     const float l = hw_log2(p);
-    sp[b] = p;
-    sl[b] = l;
+    spl[b] = make_float2(p, l);
     w += (double)p;
     hb += (double)(p * l);
     cnt += 1;
@@ -159,31 +155,44 @@ __global__ __launch_bounds__(256) void csr_field_kernel(CsrView v, int32_t targe
     const int nv = (n + 3) >> 2;
     double acc = 0.0, A = 0.0, E = 0.0;
     int c = 0;
-    for (int i = lane; i < nv; i += LPR) {
-      const float4 q = ld_stream(val4 + i);
-      const ushort4 cb = col4[i];
-      const int rem = n - 4 * i;
-      float qv[4] = {q.x, q.y, q.z, q.w};
-      int bv[4] = {cb.x, cb.y, cb.z, cb.w};
-      float ts4 = 0.f, as4 = 0.f, es4 = 0.f;
+    for (int base = lane; base < nv; base += LPR * UNROLL) {
+      float4 q[UNROLL];
+      ushort4 cb[UNROLL];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (e < rem) {
-          const float p = sp[bv[e]];
-          as4 += p;
-          c += p > 0.f;
-          if (KIND == 0) {
-            ts4 += fabsf(qv[e] - p);
-          } else {
-            const float l = sl[bv[e]];
-            ts4 += kl_term(p, l, qv[e]);
-            es4 += p * l;
-          }
+      for (int u = 0; u < UNROLL; ++u) {
+        const int i = base + u * LPR;
+        if (i < nv) {
+          q[u] = ld_stream(val4 + i);
+          cb[u] = col4[i];
         }
       }
-      acc += (double)ts4;
-      A += (double)as4;
-      if (KIND == 1) E += (double)es4;
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const int i = base + u * LPR;
+        if (i < nv) {
+          const int rem = n - 4 * i;
+          const float qv[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+          const int bv[4] = {cb[u].x, cb[u].y, cb[u].z, cb[u].w};
+          float ts4 = 0.f, as4 = 0.f, es4 = 0.f;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (e < rem) {
+              const float2 pl = spl[bv[e]];
+              as4 += pl.x;
+              c += pl.x > 0.f;
+              if (KIND == 0) {
+                ts4 += fabsf(qv[e] - pl.x);
+              } else {
+                ts4 += kl_term(pl.x, pl.y, qv[e]);
+                es4 += pl.x * pl.y;
+              }
+            }
+          }
+          acc += (double)ts4;
+          A += (double)as4;
+          if (KIND == 1) E += (double)es4;
+        }
+      }
     }
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1) {
@@ -260,7 +269,7 @@ hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out,
 
 template <int LPR, int KIND>
 static hipError_t csr_launch(CsrView v, int32_t target, float* out, hipStream_t s) {
-  auto kern = csr_field_kernel<LPR, KIND>;
+  auto kern = csr_field_kernel<LPR, KIND, 2>;
   const size_t lds = (size_t)((v.B + 3) & ~3) * sizeof(float) * 2;
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
