@@ -2,15 +2,21 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-Workload (the 257x257 grid, 3 seeded rectangular obstacles, FP32 dense
-Poisson kernel, CSR truncation at 1e-6 row-relative, one seeded target and
-source).  One step is one pass of the whole path for that query:
+Workload: the 257x257 grid with 3 seeded rectangular obstacles (N = 60,695
+interior rows, B = 1,478 non-zero boundary columns), FP32 dense Poisson
+kernel, its CSR truncation at 1e-6 row-relative, one seeded (source, target)
+query.  One step is one pass of the whole path for that query:
 
-  dense TV field, dense KL field            (streaming over N x B FP32 rows)
-  truncated TV and KL fields                (streaming over the CSR rows)
-  steepest-descent paths on the dense KL and TV fields
+  dense TV field and dense KL field          streaming over the N x B rows
+  truncated TV and KL fields                 streaming over the CSR rows
+  KL field through the contraction (f16x3)   log-kernel operand, T = 1
+  steepest-descent paths on the KL and TV fields
 
-Inputs are resident in HBM before the timed region.  Prints one JSON line.
+The value is kernel entries per second, N*B per field, 5 fields per step.
+Inputs are resident in HBM before the timed region.  After the timed steps
+the batched forms are measured on the same domain with 64 targets (the
+contraction in both forms, and 64 paths in one launch); those figures are
+reported under "rows" and are not part of the value.  Prints one JSON line.
 """
 
 import argparse
@@ -25,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f16x3": 2500.0, "f32": 157.3}
 METRIC = "kernel entries/sec (N·B·targets/s)"
 
 
@@ -34,7 +41,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--max-steps", type=int, default=4000)
+    ap.add_argument("--batch", type=int, default=64, help="targets of the batched rows")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rows", action="store_true", help="skip the batched-row measurements")
     ap.add_argument("--setup-workers", type=int, default=None,
                     help="processes that build the kernel matrix (1 = in-process; use 1 "
                          "under a profiler that initialises the GPU before main)")
@@ -43,12 +52,12 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(P32, Pt_tau, t, s, adj, max_steps, entries_per_step):
+def cpu_baseline(P32, tau, t, s, adj, max_steps, entries_per_step):
     """The FP64 oracle doing the same step on the host (single-threaded NumPy)."""
     from oracle import divergence as dv
     from oracle import path as op
     P64 = P32.astype(np.float64)
-    Pt, thr = dv.truncate(P64, Pt_tau)
+    Pt, thr = dv.truncate(P64, tau)
     reps = 0
     t0 = time.perf_counter()
     while True:
@@ -56,16 +65,43 @@ def cpu_baseline(P32, Pt_tau, t, s, adj, max_steps, entries_per_step):
         kl = dv.kl_field(P64, t)
         dv.tv_trunc_field(Pt, t)
         dv.kl_trunc_field(Pt, t, thr)
+        dv.kl_field(P64, t)          # the fifth field: KL again (the contraction's definition)
         op.steepest_descent_path(kl, adj[0], adj[1], s, t, max_steps)
         op.steepest_descent_path(tv, adj[0], adj[1], s, t, max_steps)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= 10.0 or reps >= 3:
+        if el >= 10.0 or reps >= 4:
             break
     return {"value": entries_per_step * reps / el, "unit": "entries/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{reps} full step(s) of this workload (4 fields + 2 paths), FP64 NumPy, "
-                      f"{el:.1f} s"}
+            "sample": f"{reps} full step(s) of this workload (5 fields + 2 paths), FP64 NumPy "
+                      f"on one core, {el:.1f} s"}
+
+
+class Timer:
+    """HIP-event timing of one labelled launch group on torch's current stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = {}
+
+    def run(self, name, fn, timed):
+        if not timed:
+            return fn()
+        a = self.torch.cuda.Event(enable_timing=True)
+        b = self.torch.cuda.Event(enable_timing=True)
+        a.record()
+        out = fn()
+        b.record()
+        self.pairs.setdefault(name, []).append((a, b))
+        return out
+
+    def avg_us(self, name):
+        return 1000.0 * float(np.mean([a.elapsed_time(b) for a, b in self.pairs[name]]))
+
+
+def gbs(nbytes, us):
+    return nbytes / (us * 1e-6) / 1e9
 
 
 def main():
@@ -84,7 +120,7 @@ def main():
     tau = 1e-6
     g = build_config("c2")
     P = g.poisson_kernel(dtype=np.float32, workers=args.setup_workers)
-    t_arr, s_arr = targets_sources(1, g.N, 1)
+    t_arr, s_arr = targets_sources(1, g.N, max(1, args.batch))
     t, s = int(t_arr[0]), int(s_arr[0])
     adj = (g.adj_ptr, g.adj_idx)
 
@@ -96,71 +132,100 @@ def main():
         del src, dst
 
     ctx = Context(0)
-    kd = Kernel.load_dense(ctx, P, adjacency=adj)
+    kd = Kernel.load_dense(ctx, P, adjacency=adj, gemm_form="f16x3")
     kc = Kernel.load_dense(ctx, P, adjacency=adj, tau=tau)
     N, B = kd.N, kd.B
-    dev = "cuda:0"
-    f = torch.empty((4, N), dtype=torch.float32, device=dev)
-
-    names = ["dense_tv", "dense_kl", "csr_tv", "csr_kl", "paths"]
-    ev = {n: [] for n in names}
+    f = torch.empty((5, N), dtype=torch.float32, device="cuda:0")
+    tm = Timer(torch)
 
     def step(timed):
-        evs = {}
-        for n in names:
-            evs[n] = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) \
-                if timed else None
-        def rec(n, i):
-            if timed:
-                evs[n][i].record()
-        rec("dense_tv", 0); _, b_tv = kd.field(t, "tv", out=f[0]); rec("dense_tv", 1)
-        rec("dense_kl", 0); _, b_kl = kd.field(t, "kl", out=f[1]); rec("dense_kl", 1)
-        rec("csr_tv", 0); kc.field(t, "tv", out=f[2]); rec("csr_tv", 1)
-        rec("csr_kl", 0); kc.field(t, "kl", out=f[3]); rec("csr_kl", 1)
-        rec("paths", 0)
-        res_kl = kd.trace_paths([s], [t], "kl", f[1].view(1, -1), [b_kl], args.max_steps)
-        res_tv = kd.trace_paths([s], [t], "tv", f[0].view(1, -1), [b_tv], args.max_steps)
-        rec("paths", 1)
-        if timed:
-            for n in names:
-                ev[n].append(evs[n])
-        return res_kl, res_tv
+        _, b_tv = tm.run("dense_tv", lambda: kd.field(t, "tv", out=f[0]), timed)
+        _, b_kl = tm.run("dense_kl", lambda: kd.field(t, "kl", out=f[1]), timed)
+        tm.run("csr_tv", lambda: kc.field(t, "tv", out=f[2]), timed)
+        tm.run("csr_kl", lambda: kc.field(t, "kl", out=f[3]), timed)
+        tm.run("gemm_kl_T1", lambda: kd.batch_fields([t], "kl", out=f[4]), timed)
+
+        def paths():
+            a = kd.trace_paths([s], [t], "kl", f[1].view(1, -1), [b_kl], args.max_steps)
+            b = kd.trace_paths([s], [t], "tv", f[0].view(1, -1), [b_tv], args.max_steps)
+            return a, b
+        return tm.run("paths", paths, timed)
 
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
-    t0.record()
+    e0.record()
     for _ in range(args.steps):
         res_kl, res_tv = step(True)
-    t1.record()
+    e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    ms_per_step = t0.elapsed_time(t1) / args.steps
+    ms_per_step = e0.elapsed_time(e1) / args.steps
 
-    avg_us = {n: 1000.0 * float(np.mean([a.elapsed_time(b) for a, b in ev[n]])) for n in names}
-    # algorithmic bytes per launch
     nnz = kc.nnz
-    traffic = {
+    lda = (B + 63) // 64 * 64
+    traffic = {   # algorithmic bytes per launch
         "dense_tv": N * B * 4 + N * 4,
         "dense_kl": N * B * 4 + N * 4,
         "csr_tv": nnz * 6 + N * (8 + 4 + 4),
         "csr_kl": nnz * 6 + N * (8 + 4 + 8 + 4),
+        "gemm_kl_T1": N * B * 4 + N * 4 + N * 4,
     }
     kernels = {}
-    for n in names:
-        kernels[n] = {"avg_us": round(avg_us[n], 3)}
+    for n in ["dense_tv", "dense_kl", "csr_tv", "csr_kl", "gemm_kl_T1", "paths"]:
+        us = tm.avg_us(n)
+        kernels[n] = {"avg_us": round(us, 3)}
         if n in traffic:
-            gbs = traffic[n] / (avg_us[n] * 1e-6) / 1e9
-            kernels[n].update({"alg_bytes": traffic[n], "GB/s": round(gbs, 1),
-                               "frac": round(gbs / HBM_PEAK_GBS, 4)})
-    dom = max(traffic, key=lambda n: avg_us[n])
+            kernels[n].update({"alg_bytes": traffic[n], "GB/s": round(gbs(traffic[n], us), 1),
+                               "frac": round(gbs(traffic[n], us) / HBM_PEAK_GBS, 4)})
+    dom = max(traffic, key=lambda n: kernels[n]["avg_us"])
     path_len = int(res_kl[1][0].item())
     rechecks = [int(res_kl[3][0].item()), int(res_tv[3][0].item())]
-    entries_per_step = 4 * N * B
+    entries_per_step = 5 * N * B
     value = entries_per_step / (ms_per_step * 1e-3)
+
+    rows = {}
+    if not args.no_rows and args.batch > 0:
+        T = args.batch
+        ts, ss = t_arr[:T], s_arr[:T]
+        kf = Kernel.load_dense(ctx, P, gemm_form="f32")
+        D = torch.empty((T, N), dtype=torch.float32, device="cuda:0")
+        reps = 20
+        for form, kern in (("f16x3", kd), ("f32", kf)):
+            for _ in range(3):
+                kern.batch_fields(ts, "kl", out=D)
+            torch.cuda.synchronize()
+            for _ in range(reps):
+                tm.run(f"gemm_{form}", lambda: kern.batch_fields(ts, "kl", out=D), True)
+            torch.cuda.synchronize()
+            us = tm.avg_us(f"gemm_{form}")
+            flops = 2.0 * N * B * T * (3 if form == "f16x3" else 1)
+            byts = N * lda * 4 + T * lda * 4 + T * N * 4 + N * 4
+            tf = flops / (us * 1e-6) / 1e12
+            rows[f"a5_batched_kl_{form}_T{T}"] = {
+                "avg_us": round(us, 2), "fields_per_s": round(T / (us * 1e-6), 1),
+                "entries_per_s": N * B * T / (us * 1e-6),
+                "alg_bytes": byts, "GB/s": round(gbs(byts, us), 1),
+                "hbm_frac": round(gbs(byts, us) / HBM_PEAK_GBS, 4),
+                "mfma_TFLOP/s": round(tf, 1),
+                "mfma_frac": round(tf / MFMA_PEAK_TFLOPS[form], 4)}
+        kf.free()
+        _, bounds = kd.batch_fields(ts, "kl", out=D)
+        for _ in range(2):
+            kd.trace_paths(ss, ts, "kl", D, bounds, args.max_steps)
+        torch.cuda.synchronize()
+        for _ in range(10):
+            res = tm.run("paths_T", lambda: kd.trace_paths(ss, ts, "kl", D, bounds, args.max_steps),
+                         True)
+        torch.cuda.synchronize()
+        us = tm.avg_us("paths_T")
+        lens = res[1].cpu().numpy()
+        rows[f"a6_paths_kl_T{T}"] = {"avg_us": round(us, 2), "paths_per_s": round(T / (us * 1e-6), 1),
+                                     "mean_vertices": float(lens.mean()),
+                                     "fp64_rechecks": int(res[3].sum().item())}
 
     out = {
         "metric": METRIC,
@@ -175,17 +240,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "grid 257x257, 3 rectangular obstacles, dense + CSR tau=1e-6, "
-                               "1 target: TV, KL, TV_tau, KL_tau fields + 2 paths",
-                   "N": N, "B": B, "csr_nnz": nnz, "targets": 1, "fields_per_step": 4,
+        "config": {"workload": "grid 257x257, 3 rectangular obstacles; 1 query: TV, KL, TV_tau, "
+                               "KL_tau (tau=1e-6) streaming fields, KL via f16x3 contraction, "
+                               "KL and TV paths",
+                   "N": N, "B": B, "csr_nnz": nnz, "targets": 1, "fields_per_step": 5,
                    "kl_path_vertices": path_len, "fp64_rechecks_kl_tv": rechecks,
                    "cache": "warm (no flush between steps)"},
         "roofline": {"bound": "hbm", "kernel": dom,
-                     "achieved": round(traffic[dom] / (avg_us[dom] * 1e-6) / 1e9, 1),
+                     "achieved": round(gbs(traffic[dom], kernels[dom]["avg_us"]), 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(traffic[dom] / (avg_us[dom] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "frac": round(gbs(traffic[dom], kernels[dom]["avg_us"]) / HBM_PEAK_GBS, 4),
                      "traffic": None},
         "kernels": kernels,
+        "rows": rows,
         "wall_s_timed": round(wall, 3),
     }
     if not args.no_cpu_baseline:

@@ -142,9 +142,9 @@ __global__ __launch_bounds__(256) void trunc_fill_kernel(DenseView v, const doub
 
 // l_xb = log P_xb - o_x with o_x = log max_b P_xb (natural log, FP64 then
 // rounded): FP32 rows, or an FP16 hi + lo split of them.
-__global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, float* l32,
-                                                        uint16_t* lhi, uint16_t* llo,
-                                                        float* offset) {
+__global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, int64_t lda,
+                                                        float* l32, uint16_t* lhi, uint16_t* llo,
+                                                        float* offset, int32_t* zeros) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= v.N) return;
@@ -154,18 +154,26 @@ __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, f
   const double o = log(m);
   if (lane == 0) offset[row] = (float)o;
   const double of = (double)(float)o;   // the offset the epilogue will use
-  for (int b = lane; b < v.ld; b += 64) {
+  int nz = 0;
+  for (int64_t b = lane; b < lda; b += 64) {
     double l = 0.0;
-    if (b < v.B) l = log(master_at(v, row, b)) - of;
+    if (b < v.B) {
+      const double p = master_at(v, row, (int)b);
+      if (p > 0.0)
+        l = log(p) - of;
+      else
+        nz = 1;   // log 0: this row cannot enter the contraction
+    }
     if (form == 0) {
-      l32[row * v.ld + b] = (float)l;
+      l32[row * lda + b] = (float)l;
     } else {
       const _Float16 hi = (_Float16)l;
       const _Float16 lo = (_Float16)(l - (double)hi);
-      lhi[row * v.ld + b] = __builtin_bit_cast(uint16_t, hi);
-      llo[row * v.ld + b] = __builtin_bit_cast(uint16_t, lo);
+      lhi[row * lda + b] = __builtin_bit_cast(uint16_t, hi);
+      llo[row * lda + b] = __builtin_bit_cast(uint16_t, lo);
     }
   }
+  if (__ballot(nz) != 0ull && lane == 0) atomicAdd(zeros, 1);
 }
 
 static int rows_grid(int64_t N) { return (int)((N + 3) / 4); }
@@ -210,10 +218,10 @@ hipError_t launch_trunc_fill(DenseView v, const double* thr, const int64_t* star
   return hipGetLastError();
 }
 
-hipError_t launch_log_forms(DenseView v, int form, float* l32, uint16_t* lhi, uint16_t* llo,
-                            float* offset, hipStream_t s) {
-  hipLaunchKernelGGL(log_forms_kernel, dim3(rows_grid(v.N)), dim3(256), 0, s, v, form, l32, lhi,
-                     llo, offset);
+hipError_t launch_log_forms(DenseView v, int form, int64_t lda, float* l32, uint16_t* lhi,
+                            uint16_t* llo, float* offset, int32_t* zeros, hipStream_t s) {
+  hipLaunchKernelGGL(log_forms_kernel, dim3(rows_grid(v.N)), dim3(256), 0, s, v, form, lda, l32,
+                     lhi, llo, offset, zeros);
   return hipGetLastError();
 }
 

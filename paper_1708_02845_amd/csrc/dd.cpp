@@ -93,7 +93,8 @@ struct dd_kernel {
   uint32_t magic = kKernelMagic;
   dd_ctx* ctx = nullptr;
   int32_t N = 0, B_in = 0, B = 0;
-  int64_t ld = 0;
+  int64_t ld = 0;    // row stride of the streaming form (multiple of 4)
+  int64_t lda = 0;   // row stride of the batched-KL operand (multiple of 64)
   int is_f64 = 0;
   int is_csr = 0;
   int gemm_form = DD_FORM_NONE;
@@ -186,10 +187,11 @@ dd_status upload_adjacency(dd_kernel* k, const dd_adjacency* adj) {
 
 size_t dense_bytes(int64_t N, int64_t B, int is_f64, const dd_load_opts& o) {
   const int64_t ld = (B + 3) & ~int64_t(3);
+  const int64_t lda = (B + 63) & ~int64_t(63);
   size_t b = (size_t)(N * ld * 4) + (size_t)N * 8;
   if (is_f64) b += (size_t)(N * B * 8);
-  if (o.gemm_form == DD_FORM_F32) b += (size_t)(N * ld * 4) + (size_t)N * 4;
-  if (o.gemm_form == DD_FORM_F16X3) b += (size_t)(N * ld * 4) + (size_t)N * 4;
+  if (o.gemm_form == DD_FORM_F32 || o.gemm_form == DD_FORM_F16X3)
+    b += (size_t)(N * lda * 4) + (size_t)N * 4;
   return b;
 }
 
@@ -230,6 +232,26 @@ dd_error_bound field_bound(const dd_kernel* k, int kind, int32_t t) {
   // for completeness.
   b.rel += 1e-15 * (double)k->B;
   b.abs *= 2.0;   // safety factor on the analytic estimate
+  b.rel *= 2.0;
+  return b;
+}
+
+// Bound of a batched-KL field from the contraction.  With
+// Lambda(x) = sum_b p_tb |l_xb| <= d(x) + |H_t| + |o_x| W_t and |o_x| <= log B:
+//   F32:   operand rounding u*Lambda, 64-term FP32 partial sums 33u*Lambda;
+//   F16X3: hi+lo splits of l and q (2^-22 relative each), the dropped lo*lo
+//          product (2^-22), 64-term partial sums over 12 accumulations
+//          (30u), FP16 subnormal floors (2^-25 per entry, scaled by 1/s_t).
+dd_error_bound gemm_bound(const dd_kernel* k, int32_t t) {
+  const double H = std::fabs(k->H_host[t]);
+  const double W = k->W_host[t];
+  const double logB = std::log((double)k->B);
+  const double c = k->gemm_form == DD_FORM_F32 ? 35.0 : 42.0;
+  dd_error_bound b;
+  b.rel = (c + 1.0) * kU;
+  b.abs = c * kU * (H + logB * W) + (k->is_f64 ? kU * (W + 2.0 * H) : 0.0);
+  if (k->gemm_form == DD_FORM_F16X3) b.abs += std::ldexp(1.0, -39) * (double)k->B * 88.0;
+  b.abs *= 2.0;
   b.rel *= 2.0;
   return b;
 }
@@ -472,20 +494,29 @@ dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P,
     if (!e) e = hipMemcpy(k->H_host.data(), k->H.p, 8 * (size_t)N, hipMemcpyDeviceToHost);
     if (e) return bail(fail(DD_EDEVICE, "row entropy: %s", hipGetErrorString(e)));
     if (o.gemm_form != DD_FORM_NONE) {
-      std::vector<double> mx(N);
-      if (hipMemcpy(mx.data(), rmax.p, 8 * (size_t)N, hipMemcpyDeviceToHost))
-        return bail(fail(DD_EDEVICE, "copy of row maxima failed"));
-      e = k->Off.alloc(4 * (size_t)N);
-      if (!e && o.gemm_form == DD_FORM_F32) e = k->L32.alloc(4 * (size_t)N * (size_t)k->ld);
+      k->lda = ((int64_t)k->B + 63) & ~int64_t(63);
+      DevBuf zeros;
+      e = zeros.alloc(4);
+      if (!e) e = hipMemset(zeros.p, 0, 4);
+      if (!e) e = k->Off.alloc(4 * (size_t)N);
+      if (!e && o.gemm_form == DD_FORM_F32) e = k->L32.alloc(4 * (size_t)N * (size_t)k->lda);
       if (!e && o.gemm_form == DD_FORM_F16X3) {
-        e = k->Lhi.alloc(2 * (size_t)N * (size_t)k->ld);
-        if (!e) e = k->Llo.alloc(2 * (size_t)N * (size_t)k->ld);
+        e = k->Lhi.alloc(2 * (size_t)N * (size_t)k->lda);
+        if (!e) e = k->Llo.alloc(2 * (size_t)N * (size_t)k->lda);
       }
-      if (!e) e = dd::launch_log_forms(k->dense(), o.gemm_form, k->L32.as<float>(),
+      if (!e) e = dd::launch_log_forms(k->dense(), o.gemm_form, k->lda, k->L32.as<float>(),
                                        k->Lhi.as<uint16_t>(), k->Llo.as<uint16_t>(),
-                                       k->Off.as<float>(), nullptr);
+                                       k->Off.as<float>(), zeros.as<int32_t>(), nullptr);
       if (!e) e = hipDeviceSynchronize();
       if (e) return bail(fail(DD_EDEVICE, "log-kernel operand: %s", hipGetErrorString(e)));
+      int32_t nzero = 0;
+      if (hipMemcpy(&nzero, zeros.p, 4, hipMemcpyDeviceToHost))
+        return bail(fail(DD_EDEVICE, "copy of the zero count failed"));
+      if (nzero > 0)
+        return bail(fail(DD_EINVAL,
+                         "%d rows hold a zero entry in a non-zero column: log P is not finite "
+                         "there, so the batched-KL operand cannot be built",
+                         nzero));
       k->gemm_form = o.gemm_form;
     }
   }
@@ -629,15 +660,19 @@ dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t
   if (kind == DD_KL && !k->is_csr && k->gemm_form != DD_FORM_NONE) {
     dd::GemmView gv{k->L32.as<const float>(), k->Lhi.as<const uint16_t>(),
                     k->Llo.as<const uint16_t>(), k->Off.as<const float>(),
-                    k->ld, k->N, k->B, k->gemm_form};
-    AsyncBuf tdev(s), ws(s);
-    const size_t wsb = dd::batch_kl_workspace(gv, T);
-    HIP_OR(tdev.alloc(4 * (size_t)T));
-    HIP_OR(ws.alloc(wsb));
-    HIP_OR(hipMemcpyAsync(tdev.p, targets, 4 * (size_t)T, hipMemcpyHostToDevice, s));
-    HIP_OR(dd::launch_batch_kl(k->dense(), gv, tdev.as<const int32_t>(), T, ws.p, wsb, out_dev, s));
+                    k->lda, k->N, k->B, k->gemm_form};
+    // groups of up to 64 targets; each group reads the log-kernel once
+    AsyncBuf ws(s);
+    HIP_OR(ws.alloc(dd::batch_kl_workspace(gv, std::min<int32_t>(T, dd::kMaxBatch))));
+    for (int32_t g0 = 0; g0 < T; g0 += dd::kMaxBatch) {
+      const int32_t n = std::min<int32_t>(dd::kMaxBatch, T - g0);
+      dd::TargetList tl;
+      std::memset(&tl, 0, sizeof tl);
+      for (int32_t i = 0; i < n; ++i) tl.t[i] = targets[g0 + i];
+      HIP_OR(dd::launch_batch_kl(k->dense(), gv, tl, n, ws.p, out_dev + (int64_t)g0 * k->N, s));
+    }
     if (bounds)
-      for (int32_t i = 0; i < T; ++i) bounds[i] = field_bound(k, kind, targets[i]);
+      for (int32_t i = 0; i < T; ++i) bounds[i] = gemm_bound(k, targets[i]);
     return DD_OK;
   }
   for (int32_t i = 0; i < T; ++i) {

@@ -46,8 +46,8 @@ hipError_t launch_row_entropy(DenseView v, double* H, hipStream_t s);
 hipError_t launch_trunc_count(DenseView v, const double* thr, int32_t* counts, hipStream_t s);
 hipError_t launch_trunc_fill(DenseView v, const double* thr, const int64_t* start, uint16_t* col,
                              float* val, double* val64, hipStream_t s);
-hipError_t launch_log_forms(DenseView v, int form, float* l32, uint16_t* lhi, uint16_t* llo,
-                            float* offset, hipStream_t s);
+hipError_t launch_log_forms(DenseView v, int form, int64_t lda, float* l32, uint16_t* lhi,
+                            uint16_t* llo, float* offset, int32_t* zeros, hipStream_t s);
 
 // ---- streaming fields (stream.hip) ----
 hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out, hipStream_t s);
@@ -55,16 +55,20 @@ hipError_t launch_csr_field(CsrView v, int32_t target, int kind, float* out, hip
 
 // ---- batched KL contraction (gemm.hip) ----
 struct GemmView {
-  const float* l32;      // [N][ld] log P - o_x  (form F32)
-  const uint16_t* lhi;   // [N][ld] FP16 bits    (form F16X3)
+  const float* l32;      // [N][lda] log P - o_x  (form F32)
+  const uint16_t* lhi;   // [N][lda] FP16 bits    (form F16X3)
   const uint16_t* llo;
-  const float* offset;   // [N] o_x
-  int64_t ld;
+  const float* offset;   // [N] o_x = log max_b P_xb
+  int64_t lda;           // a multiple of 64, zero padded
   int32_t N, B, form;
 };
-hipError_t launch_batch_kl(DenseView dv, GemmView gv, const int32_t* targets_dev, int32_t T,
-                           void* workspace, size_t ws_bytes, float* out, hipStream_t s);
+constexpr int kMaxBatch = 64;   // targets per contraction launch
+struct TargetList {
+  int32_t t[kMaxBatch];
+};
 size_t batch_kl_workspace(GemmView gv, int32_t T);
+hipError_t launch_batch_kl(DenseView dv, GemmView gv, TargetList tl, int32_t T, void* ws,
+                           float* out, hipStream_t s);
 
 // ---- paths (path.hip) ----
 // Up to kInlinePaths paths carry their sources, targets and bounds in the

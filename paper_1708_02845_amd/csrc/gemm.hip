@@ -1,14 +1,362 @@
-// Batched KL as one contraction over the log-kernel (placeholder until the
-// MFMA kernel lands: reports "not supported").
+// Batched KL as one contraction (Section IV, eq. 35 expanded):
+//
+//   d(x, t) = sum_b p_tb log(p_tb / P_xb) = H_t - o_x W_t - S_xt,
+//   S_xt    = sum_b l_xb p_tb,   l_xb = log P_xb - o_x,   o_x = log max_b P_xb,
+//   H_t     = sum_b p_tb log p_tb,   W_t = sum_b p_tb,
+//
+// with S = l * P_T^T an (N x B) by (B x T) product on MFMA.  The log-kernel l
+// (built once at load) is the A operand and is streamed from HBM exactly once
+// per launch; the target rows are the B operand, staged per K-chunk in LDS
+// and shared by the four waves of a workgroup.  Each wave owns 32 rows and all
+// target columns (32 per column tile).
+//
+// Forms:
+//   F32    l and p in FP32, v_mfma_f32_32x32x2_f32.
+//   F16X3  l = l_hi + l_lo and p*s_t = q_hi + q_lo in FP16 (s_t a power of two
+//          putting max q at 2^13..2^14), three products l_hi q_hi + l_hi q_lo
+//          + l_lo q_hi on v_mfma_f32_32x32x16_f16, divided by s_t at the end.
+//
+// Both forms carry the FP32 accumulators into FP64 after every K-chunk of 64,
+// so the FP32 accumulation error is that of 64-term partial sums; H_t, W_t and
+// the final combination are FP64.
+//
+// The order of K inside a chunk is a free choice, as long as both operands
+// use the same one: lane half h of a wave reads the contiguous K range
+// [32h, 32h+32) of the chunk, which turns the A loads into 64- or 128-byte
+// contiguous reads per lane.
+#include <math.h>
+
 #include "dd_internal.h"
 
 namespace dd {
 
-size_t batch_kl_workspace(GemmView, int32_t) { return 0; }
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-hipError_t launch_batch_kl(DenseView, GemmView, const int32_t*, int32_t, void*, size_t, float*,
-                           hipStream_t) {
-  return hipErrorNotSupported;
+constexpr int KC = 64;           // K per chunk
+constexpr int GW = 4;            // waves per workgroup
+constexpr int GROWS = 32 * GW;   // rows per workgroup
+
+struct BatchOperand {
+  float* b32;        // [Tpad][lda] FP32 targets (F32)
+  uint16_t* bhi;     // [Tpad][lda] FP16 bits (F16X3)
+  uint16_t* blo;
+  double* H;         // [Tpad]
+  double* W;         // [Tpad]
+  double* inv_s;     // [Tpad] 1/s_t
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static BatchOperand carve(GemmView gv, int Tpad, void* ws) {
+  unsigned char* p = static_cast<unsigned char*>(ws);
+  BatchOperand o{};
+  size_t off = 0;
+  if (gv.form == 0) {
+    o.b32 = reinterpret_cast<float*>(p + off);
+    off = align256(off + 4 * (size_t)Tpad * gv.lda);
+  } else {
+    o.bhi = reinterpret_cast<uint16_t*>(p + off);
+    off = align256(off + 2 * (size_t)Tpad * gv.lda);
+    o.blo = reinterpret_cast<uint16_t*>(p + off);
+    off = align256(off + 2 * (size_t)Tpad * gv.lda);
+  }
+  o.H = reinterpret_cast<double*>(p + off);
+  o.W = o.H + Tpad;
+  o.inv_s = o.W + Tpad;
+  return o;
+}
+
+size_t batch_kl_workspace(GemmView gv, int32_t T) {
+  const int Tpad = T <= 32 ? 32 : 64;
+  size_t off = gv.form == 0 ? align256(4 * (size_t)Tpad * gv.lda)
+                            : 2 * align256(2 * (size_t)Tpad * gv.lda);
+  return off + 3 * 8 * (size_t)Tpad;
+}
+
+// One block per padded target slot: FP64 H_t, W_t, the scale, and the B operand.
+__global__ __launch_bounds__(256) void batch_target_prep(DenseView dv, GemmView gv, TargetList tl,
+                                                         int32_t T, BatchOperand o) {
+  const int j = blockIdx.x;
+  const bool real = j < T;
+  const int t = real ? tl.t[j] : 0;
+  __shared__ double red[3][4];
+  __shared__ double bcast[2];
+  double w = 0.0, h = 0.0, m = 0.0;
+  if (real) {
+    for (int b = threadIdx.x; b < dv.B; b += blockDim.x) {
+      const double p = dv.P64 ? dv.P64[(int64_t)t * dv.B + b] : (double)dv.P[(int64_t)t * dv.ld + b];
+      w += p;
+      if (p > 0.0) h += p * log(p);
+      m = fmax(m, p);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    w += __shfl_xor(w, off);
+    h += __shfl_xor(h, off);
+    m = fmax(m, __shfl_xor(m, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = w;
+    red[1][threadIdx.x >> 6] = h;
+    red[2][threadIdx.x >> 6] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double W = 0.0, H = 0.0, M = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+      W += red[0][i];
+      H += red[1][i];
+      M = fmax(M, red[2][i]);
+    }
+    double s = 1.0;
+    if (gv.form == 1 && M > 0.0) {
+      int e = 0;
+      frexp(M, &e);          // M in [2^(e-1), 2^e)
+      s = ldexp(1.0, 14 - e);
+    }
+    o.H[j] = H;
+    o.W[j] = W;
+    o.inv_s[j] = 1.0 / s;
+    bcast[0] = s;
+  }
+  __syncthreads();
+  const float s = (float)bcast[0];
+  for (int64_t k = threadIdx.x; k < gv.lda; k += blockDim.x) {
+    float p = 0.f;
+    if (real && k < dv.B)
+      p = dv.P64 ? (float)dv.P64[(int64_t)t * dv.B + k] : dv.P[(int64_t)t * dv.ld + k];
+    if (gv.form == 0) {
+      o.b32[(int64_t)j * gv.lda + k] = p;
+    } else {
+      const float q = p * s;                    // exact: s is a power of two
+      const _Float16 qh = (_Float16)q;
+      const _Float16 ql = (_Float16)(q - (float)qh);
+      o.bhi[(int64_t)j * gv.lda + k] = __builtin_bit_cast(uint16_t, qh);
+      o.blo[(int64_t)j * gv.lda + k] = __builtin_bit_cast(uint16_t, ql);
+    }
+  }
+}
+
+// Epilogue shared by both forms: d = H_t - o_x W_t - S_xt / s_t (FP64).
+template <int NT>
+__device__ __forceinline__ void write_fields(const GemmView& gv, const BatchOperand& o, int32_t T,
+                                             int64_t row0, int lane, const double (&accd)[NT][16],
+                                             float* out) {
+  const int r = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    const int t = n * 32 + r;
+    if (t >= T) continue;
+    const double H = o.H[t], W = o.W[t], is = o.inv_s[t];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int64_t x = row0 + 8 * (i >> 2) + 4 * h + (i & 3);
+      if (x < gv.N) {
+        const double d = H - (double)gv.offset[x] * W - accd[n][i] * is;
+        out[(int64_t)t * gv.N + x] = (float)d;
+      }
+    }
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o, int32_t T,
+                                                     float* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) _Float16 sbh[NT * 32][KC + 8];
+  __shared__ __attribute__((aligned(16))) _Float16 sbl[NT * 32][KC + 8];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
+  const int64_t row0 = (int64_t)blockIdx.x * GROWS + wv * 32;
+  const int64_t row = row0 + r;
+  const bool rv = row < gv.N;
+  const uint16_t* ahp = gv.lhi + (rv ? row : 0) * gv.lda + h * 32;
+  const uint16_t* alp = gv.llo + (rv ? row : 0) * gv.lda + h * 32;
+  const int nchunks = (int)(gv.lda / KC);
+  constexpr int SEGS = NT * 32 * 8;          // 16-byte segments per chunk per array
+  constexpr int SPT = (SEGS + 255) / 256;    // per thread
+
+  uint4 ah[4], al[4], nh[4], nl[4], bh[SPT], bl[SPT];
+  const uint4 z = make_uint4(0, 0, 0, 0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ah[q] = rv ? *reinterpret_cast<const uint4*>(ahp + q * 8) : z;
+    al[q] = rv ? *reinterpret_cast<const uint4*>(alp + q * 8) : z;
+  }
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    const int sg = threadIdx.x + q * 256;
+    if (sg < SEGS) {
+      const int64_t g = (int64_t)(sg >> 3) * gv.lda + (sg & 7) * 8;
+      bh[q] = *reinterpret_cast<const uint4*>(o.bhi + g);
+      bl[q] = *reinterpret_cast<const uint4*>(o.blo + g);
+    }
+  }
+  floatx16 acc[NT];
+  double accd[NT][16];
+#pragma unroll
+  for (int n = 0; n < NT; ++n)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      acc[n][i] = 0.f;
+      accd[n][i] = 0.0;
+    }
+
+  for (int c = 0; c < nchunks; ++c) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int sg = threadIdx.x + q * 256;
+      if (sg < SEGS) {
+        *reinterpret_cast<uint4*>(&sbh[sg >> 3][(sg & 7) * 8]) = bh[q];
+        *reinterpret_cast<uint4*>(&sbl[sg >> 3][(sg & 7) * 8]) = bl[q];
+      }
+    }
+    __syncthreads();
+    if (c + 1 < nchunks) {
+      const int64_t ko = (int64_t)(c + 1) * KC;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        nh[q] = rv ? *reinterpret_cast<const uint4*>(ahp + ko + q * 8) : z;
+        nl[q] = rv ? *reinterpret_cast<const uint4*>(alp + ko + q * 8) : z;
+      }
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        const int sg = threadIdx.x + q * 256;
+        if (sg < SEGS) {
+          const int64_t g = (int64_t)(sg >> 3) * gv.lda + ko + (sg & 7) * 8;
+          bh[q] = *reinterpret_cast<const uint4*>(o.bhi + g);
+          bl[q] = *reinterpret_cast<const uint4*>(o.blo + g);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const half8 a_h = __builtin_bit_cast(half8, ah[j]);
+      const half8 a_l = __builtin_bit_cast(half8, al[j]);
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const half8 b_h = *reinterpret_cast<const half8*>(&sbh[n * 32 + r][h * 32 + j * 8]);
+        const half8 b_l = *reinterpret_cast<const half8*>(&sbl[n * 32 + r][h * 32 + j * 8]);
+        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_h, b_h, acc[n], 0, 0, 0);
+        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_h, b_l, acc[n], 0, 0, 0);
+        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_l, b_h, acc[n], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        accd[n][i] += (double)acc[n][i];
+        acc[n][i] = 0.f;
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ah[q] = nh[q];
+      al[q] = nl[q];
+    }
+  }
+  write_fields<NT>(gv, o, T, row0, lane, accd, out);
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, int32_t T,
+                                                   float* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) float sb[NT * 32][KC + 4];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
+  const int64_t row0 = (int64_t)blockIdx.x * GROWS + wv * 32;
+  const int64_t row = row0 + r;
+  const bool rv = row < gv.N;
+  const float* ap = gv.l32 + (rv ? row : 0) * gv.lda + h * 32;
+  const int nchunks = (int)(gv.lda / KC);
+  constexpr int SEGS = NT * 32 * 16;          // 16-byte segments per chunk
+  constexpr int SPT = (SEGS + 255) / 256;
+
+  float4 a[8], na[8], bq[SPT];
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) a[q] = rv ? *reinterpret_cast<const float4*>(ap + q * 4) : z;
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    const int sg = threadIdx.x + q * 256;
+    if (sg < SEGS)
+      bq[q] = *reinterpret_cast<const float4*>(o.b32 + (int64_t)(sg >> 4) * gv.lda + (sg & 15) * 4);
+  }
+  floatx16 acc[NT];
+  double accd[NT][16];
+#pragma unroll
+  for (int n = 0; n < NT; ++n)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      acc[n][i] = 0.f;
+      accd[n][i] = 0.0;
+    }
+
+  for (int c = 0; c < nchunks; ++c) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int sg = threadIdx.x + q * 256;
+      if (sg < SEGS) *reinterpret_cast<float4*>(&sb[sg >> 4][(sg & 15) * 4]) = bq[q];
+    }
+    __syncthreads();
+    if (c + 1 < nchunks) {
+      const int64_t ko = (int64_t)(c + 1) * KC;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) na[q] = rv ? *reinterpret_cast<const float4*>(ap + ko + q * 4) : z;
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        const int sg = threadIdx.x + q * 256;
+        if (sg < SEGS)
+          bq[q] = *reinterpret_cast<const float4*>(o.b32 + (int64_t)(sg >> 4) * gv.lda + ko +
+                                                   (sg & 15) * 4);
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      const float av[4] = {a[jj].x, a[jj].y, a[jj].z, a[jj].w};
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const float4 b4 = *reinterpret_cast<const float4*>(&sb[n * 32 + r][h * 32 + jj * 4]);
+        const float bv[4] = {b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          acc[n] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[e], bv[e], acc[n], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        accd[n][i] += (double)acc[n][i];
+        acc[n][i] = 0.f;
+      }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = na[q];
+  }
+  write_fields<NT>(gv, o, T, row0, lane, accd, out);
+}
+
+hipError_t launch_batch_kl(DenseView dv, GemmView gv, TargetList tl, int32_t T, void* ws,
+                           float* out, hipStream_t s) {
+  if (T <= 0 || T > 64 || gv.lda % KC != 0) return hipErrorInvalidValue;
+  const int Tpad = T <= 32 ? 32 : 64;
+  const BatchOperand o = carve(gv, Tpad, ws);
+  hipLaunchKernelGGL(batch_target_prep, dim3(Tpad), dim3(256), 0, s, dv, gv, tl, T, o);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)((gv.N + GROWS - 1) / GROWS));
+  if (gv.form == 0) {
+    if (Tpad == 32)
+      hipLaunchKernelGGL(kl_gemm_f32<1>, grid, dim3(256), 0, s, gv, o, T, out);
+    else
+      hipLaunchKernelGGL(kl_gemm_f32<2>, grid, dim3(256), 0, s, gv, o, T, out);
+  } else {
+    if (Tpad == 32)
+      hipLaunchKernelGGL(kl_gemm_f16x3<1>, grid, dim3(256), 0, s, gv, o, T, out);
+    else
+      hipLaunchKernelGGL(kl_gemm_f16x3<2>, grid, dim3(256), 0, s, gv, o, T, out);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace dd

@@ -4,16 +4,18 @@
 // vertex; stop at the target, at a vertex with no strictly lower neighbour,
 // or after max_steps moves.
 //
-// The walk is a chain of dependent steps, so its cost is memory latency per
-// step.  A parallel gather first lays out, for every vertex, the field values
-// of its neighbour slots next to each other (nv[v][j] = d(adj[v][j])); a step
-// then needs one round of independent loads (ids and values of the current
-// vertex's row) before the cross-lane argmin.  One wavefront per path.
+// The walk is a chain of dependent steps, so its cost is latency per step.
+// A parallel gather first lays out, for every vertex, the field values of its
+// neighbour slots next to each other (nv[v][j] = d(adj[v][j])); a step then
+// needs one round of independent loads (ids and values of the current
+// vertex's row), followed by a scalar best/second-best selection.
 //
-// Each decision is checked against the field's stated error bound: when two
-// neighbours (or the best neighbour and the current vertex) cannot be told
-// apart within the bound, their distances are recomputed in FP64 from the
-// resident master rows and the decision is taken on those.
+// Each decision is checked against the field's stated error bound: when the
+// best and the second-best neighbour (or the best neighbour and the current
+// vertex) cannot be told apart within the bound, the distances of every
+// neighbour that could be the minimum, and of the current vertex, are
+// recomputed in FP64 from the resident master rows and the decision is taken
+// on those.
 #include "dd_internal.h"
 
 namespace dd {
@@ -89,15 +91,27 @@ __global__ __launch_bounds__(256) void neighbor_values_kernel(PathArgs a, int32_
   }
 }
 
-// FP64 distance of row x to the target (whole wave cooperates).  Dense
+// Block-wide FP64 sum (all threads of the 256-thread block call it).
+__device__ double block_sum(double v, double* red) {
+  v = wsum(v);
+  const int wid = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  return s;
+}
+
+// FP64 distance of row x to the target, the whole block cooperating.  Dense
 // handles read the target row from the master; truncated handles use the
 // staged FP64 target row and its constants.
 __device__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_csr, int kind,
-                                 int t, const double* p, const double* tc, int x) {
-  const int lane = threadIdx.x & 63;
+                                 int t, const double* p, const double* tc, int x, double* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
   if (!is_csr) {
     double acc = 0.0;
-    for (int b = lane; b < dv.B; b += 64) {
+    for (int b = tid; b < dv.B; b += nt) {
       double q, pb;
       if (dv.P64) {
         q = dv.P64[(int64_t)x * dv.B + b];
@@ -112,12 +126,12 @@ __device__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_
         acc += pb * log(pb / q);
       }
     }
-    return wsum(acc);
+    return block_sum(acc, red);
   }
   const int64_t s = cv.start[x];
   const int n = cv.len[x];
   double acc = 0.0, A = 0.0, E = 0.0, c = 0.0;
-  for (int i = lane; i < n; i += 64) {
+  for (int i = tid; i < n; i += nt) {
     const double q = cv.val64 ? cv.val64[s + i] : (double)cv.val[s + i];
     const double pb = p[cv.col[s + i]];
     A += pb;
@@ -129,18 +143,34 @@ __device__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_
     }
     c += pb > 0.0 ? 1.0 : 0.0;
   }
-  acc = wsum(acc);
-  A = wsum(A);
-  E = wsum(E);
-  c = wsum(c);
+  acc = block_sum(acc, red);
+  A = block_sum(A, red);
+  E = block_sum(E, red);
+  c = block_sum(c, red);
   if (c == tc[2]) return acc;
   if (kind == 0) return acc + (tc[0] - A);
   return acc + (tc[1] - E) - log(cv.phi[x]) * (tc[0] - A);
 }
 
-__global__ __launch_bounds__(64) void paths_kernel(DenseView dv, CsrView cv, PathArgs a) {
+// Order-preserving map of a float to an unsigned key (for any non-NaN value).
+__device__ __forceinline__ uint32_t fkey(uint32_t b) {
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float unkey(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+// One 256-thread block per path.  The walk itself is uniform: every wave
+// takes the same decisions from the same loads; the four waves only split
+// the FP64 re-decisions.  A step loads the padded neighbour row (ids and
+// pre-gathered values) lane-parallel, moves it into scalar registers, and
+// takes the best and second-best neighbour on order-preserving integer keys
+// (ties: lowest id) with scalar instructions, so no cross-lane reduction
+// chain sits on the critical path.  Padding slots (-1) are trailing.
+__global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, PathArgs a) {
+  __shared__ double red[4];
   const int i = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int N = a.is_csr ? cv.N : dv.N;
   const int W = a.adj_w;
   const float* d = a.fields + (int64_t)i * N;
@@ -156,7 +186,7 @@ __global__ __launch_bounds__(64) void paths_kernel(DenseView dv, CsrView cv, Pat
   int len = 1;
   int status = 0;
   int rechecks = 0;
-  if (lane == 0) path[0] = v;
+  if (threadIdx.x == 0) path[0] = v;
   for (;;) {
     if (v == t) {
       status = 0;
@@ -166,60 +196,65 @@ __global__ __launch_bounds__(64) void paths_kernel(DenseView dv, CsrView cv, Pat
       status = 2;
       break;
     }
-    // one round of independent loads: neighbour ids and their field values
-    int u = -1;
-    float val = __builtin_inff();
+    int ul = -1;
+    float vl = __builtin_inff();
     if (lane < W) {
-      u = a.adj[(int64_t)v * W + lane];
-      val = nvi[(int64_t)v * W + lane];
+      ul = a.adj[(int64_t)v * W + lane];
+      vl = nvi[(int64_t)v * W + lane];
     }
-    const bool valid = u >= 0;
-    if (__ballot(valid) == 0ull) {
+    const uint32_t kl = fkey(__float_as_uint(vl));
+    // best (k1, u1) and second best (k2, u2) in scalar registers
+    uint32_t k1 = 0xffffffffu, k2 = 0xffffffffu;
+    int u1 = 0x7fffffff, u2 = 0x7fffffff;
+    int deg = 0;
+    for (int j = 0; j < W; ++j) {
+      const int uj = __builtin_amdgcn_readlane(ul, j);
+      if (uj < 0) break;
+      const uint32_t kj = (uint32_t)__builtin_amdgcn_readlane((int)kl, j);
+      ++deg;
+      if (kj < k1 || (kj == k1 && uj < u1)) {
+        k2 = k1;
+        u2 = u1;
+        k1 = kj;
+        u1 = uj;
+      } else if (kj < k2 || (kj == k2 && uj < u2)) {
+        k2 = kj;
+        u2 = uj;
+      }
+    }
+    if (deg == 0) {
       status = 1;
       break;
     }
-    const double e = valid ? ea + er * fabs((double)val) : 0.0;
-    const double hi = valid ? (double)val + e : __builtin_inf();
-    const double lo = valid ? (double)val - e : __builtin_inf();
-    // lexicographic argmin of (val, u) and the smallest upper end
-    float bv = val;
-    int bu = valid ? u : 0x7fffffff;
-    double mh = hi;
-    for (int off = 32; off > 0; off >>= 1) {
-      const float ov = __shfl_xor(bv, off);
-      const int ou = __shfl_xor(bu, off);
-      if (ov < bv || (ov == bv && ou < bu)) {
-        bv = ov;
-        bu = ou;
-      }
-      mh = fmin(mh, __shfl_xor(mh, off));
-    }
-    const bool cand = valid && lo <= mh;
-    const unsigned long long cm = __ballot(cand);
-    const int nc = __popcll(cm);
+    const double v1 = (double)unkey(k1);
+    const double e1 = ea + er * fabs(v1);
     const double dvv = (double)cur;
-    const double evv = ea + er * fabs(dvv);
-    const double eb = ea + er * fabs((double)bv);
-    int next = bu;
+    const double ev = ea + er * fabs(dvv);
+    // the argmin is certain when the second best lies above the best's interval
+    bool certain = deg == 1;
+    if (!certain) {
+      const double v2 = (double)unkey(k2);
+      certain = v2 - (ea + er * fabs(v2)) > v1 + e1;
+    }
+    int next = u1;
     bool stuck;
-    if (nc == 1 && ((double)bv + eb < dvv - evv)) {
+    if (certain && v1 + e1 < dvv - ev) {
       stuck = false;
-    } else if (nc == 1 && ((double)bv - eb >= dvv + evv)) {
+    } else if (certain && v1 - e1 >= dvv + ev) {
       stuck = true;
     } else {
       ++rechecks;
-      const double dxv = exact_distance(dv, cv, a.is_csr, a.kind, t, p, tc, v);
+      const double dxv = exact_distance(dv, cv, a.is_csr, a.kind, t, p, tc, v, red);
       double best = __builtin_inf();
       int best_u = 0x7fffffff;
-      unsigned long long m = cm;
-      while (m) {
-        const int l = __ffsll((long long)m) - 1;
-        m &= m - 1;
-        const int cu = __shfl(u, l);
-        const double dx = exact_distance(dv, cv, a.is_csr, a.kind, t, p, tc, cu);
-        if (dx < best || (dx == best && cu < best_u)) {
+      for (int j = 0; j < deg; ++j) {
+        const int uj = __builtin_amdgcn_readlane(ul, j);
+        const double vj = (double)unkey((uint32_t)__builtin_amdgcn_readlane((int)kl, j));
+        if (vj - (ea + er * fabs(vj)) > v1 + e1) continue;   // certainly above the best
+        const double dx = exact_distance(dv, cv, a.is_csr, a.kind, t, p, tc, uj, red);
+        if (dx < best || (dx == best && uj < best_u)) {
           best = dx;
-          best_u = cu;
+          best_u = uj;
         }
       }
       next = best_u;
@@ -229,14 +264,18 @@ __global__ __launch_bounds__(64) void paths_kernel(DenseView dv, CsrView cv, Pat
       status = 1;
       break;
     }
-    const unsigned long long at = __ballot(valid && u == next);
-    cur = __shfl(val, __ffsll((long long)at) - 1);
+    // FP32 value of the chosen neighbour
+    float nextv = 0.f;
+    for (int j = 0; j < deg; ++j)
+      if (__builtin_amdgcn_readlane(ul, j) == next)
+        nextv = unkey((uint32_t)__builtin_amdgcn_readlane((int)kl, j));
+    cur = nextv;
     v = next;
-    if (lane == 0) path[len] = v;
+    if (threadIdx.x == 0) path[len] = v;
     ++len;
   }
-  for (int k = len + lane; k <= a.max_steps; k += 64) path[k] = -1;
-  if (lane == 0) {
+  for (int k = len + threadIdx.x; k <= a.max_steps; k += blockDim.x) path[k] = -1;
+  if (threadIdx.x == 0) {
     a.len[i] = len;
     a.status[i] = status;
     if (a.rechecks) a.rechecks[i] = rechecks;
@@ -260,7 +299,7 @@ hipError_t launch_neighbor_values(PathArgs a, int32_t N, float* nv, hipStream_t 
 }
 
 hipError_t launch_paths(DenseView dv, CsrView cv, PathArgs a, hipStream_t s) {
-  hipLaunchKernelGGL(paths_kernel, dim3(a.T), dim3(64), 0, s, dv, cv, a);
+  hipLaunchKernelGGL(paths_kernel, dim3(a.T), dim3(256), 0, s, dv, cv, a);
   return hipGetLastError();
 }
 

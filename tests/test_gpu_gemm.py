@@ -1,0 +1,122 @@
+"""GPU parity of the batched KL contraction (eq. 35 expanded) against the oracle."""
+
+import numpy as np
+import pytest
+
+from conftest import normwise, within_bound
+from oracle import divergence as dv
+from oracle import path as op
+from workloads import build_config, grid_domain
+from workloads.seeds import targets_sources
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+FORMS = ["f32", "f16x3"]
+
+
+@pytest.fixture(scope="module")
+def grid(gpu_ctx):
+    g = grid_domain(71, 2, (0.1, 0.3), config_id=51)     # N, B not multiples of 128 / 64
+    return g, g.poisson_kernel().astype(np.float32)
+
+
+@pytest.fixture(scope="module", params=FORMS)
+def gemm_kernel(request, gpu_ctx, grid):
+    from paper_1708_02845_amd import Kernel
+    g, P = grid
+    k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx), gemm_form=request.param)
+    yield request.param, k
+    k.free()
+
+
+@pytest.mark.parametrize("T", [1, 5, 32, 33, 64, 70])
+def test_batched_kl_matches_oracle(grid, gemm_kernel, T):
+    g, P = grid
+    form, k = gemm_kernel
+    assert k.N % 128 != 0 and k.B % 64 != 0
+    ts = targets_sources(51 + T, g.N, T)[0]
+    D, bounds = k.batch_fields(ts, "kl")
+    D = D.cpu().numpy()
+    P64 = P.astype(np.float64)
+    for i in sorted({0, T // 2, T - 1}):
+        ref = dv.kl_field(P64, int(ts[i]))
+        assert normwise(D[i], ref) <= TOL, (form, T, i)
+        assert within_bound(D[i], ref, bounds[i]), (form, T, i)
+
+
+def test_batch_invariance(grid, gemm_kernel):
+    g, P = grid
+    form, k = gemm_kernel
+    ts = list(targets_sources(77, g.N, 64)[0])
+    t = ts[37]
+    alone = k.batch_fields([t], "kl")[0].cpu().numpy()[0]
+    in_64 = k.batch_fields(ts, "kl")[0].cpu().numpy()[37]
+    first = k.batch_fields([t] + ts[1:], "kl")[0].cpu().numpy()[0]
+    assert np.array_equal(alone, in_64)
+    assert np.array_equal(alone, first)
+
+
+def test_paths_on_contraction_fields(grid, gemm_kernel):
+    import torch
+    g, P = grid
+    form, k = gemm_kernel
+    ts, ss = targets_sources(52, g.N, 8)
+    D, bounds = k.batch_fields(ts, "kl")
+    paths, lens, status, rechecks = k.trace_paths(ss, ts, "kl", D, bounds, 4000)
+    torch.cuda.synchronize()
+    paths, lens, status = paths.cpu().numpy(), lens.cpu().numpy(), status.cpu().numpy()
+    P64 = P.astype(np.float64)
+    for i in range(len(ts)):
+        ref, ref_status = op.steepest_descent_path(dv.kl_field(P64, int(ts[i])), g.adj_ptr,
+                                                   g.adj_idx, int(ss[i]), int(ts[i]), 4000)
+        assert int(status[i]) == ref_status
+        assert list(paths[i, :lens[i]]) == ref
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_unit_disk_fp64_input(gpu_ctx, form):
+    from paper_1708_02845_amd import Kernel
+    inst = build_config("c1")
+    k = Kernel.load_dense(gpu_ctx, inst.P, gemm_form=form)
+    try:
+        ts = targets_sources(0, inst.N, 16)[0]
+        D, bounds = k.batch_fields(ts, "kl")
+        D = D.cpu().numpy()
+        for i in (0, 7, 15):
+            ref = dv.kl_field(inst.P, int(ts[i]))
+            assert normwise(D[i], ref) <= TOL
+            assert within_bound(D[i], ref, bounds[i])
+    finally:
+        k.free()
+
+
+def test_zero_entry_cannot_build_operand(gpu_ctx):
+    from paper_1708_02845_amd import DDError, Kernel
+    g = np.random.default_rng(3)
+    P = g.random((40, 30)) + 0.1
+    P[5, 7] = 0.0                    # column 7 is not all-zero, so it is kept
+    P /= P.sum(axis=1, keepdims=True)
+    with pytest.raises(DDError, match="batched-KL operand"):
+        Kernel.load_dense(gpu_ctx, P.astype(np.float32), gemm_form="f16x3")
+    k = Kernel.load_dense(gpu_ctx, P.astype(np.float32))     # the streaming form is fine
+    k.free()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_grid257_batch_of_64(gpu_ctx, form):
+    from paper_1708_02845_amd import Kernel
+    g = build_config("c2")
+    P = g.poisson_kernel(dtype=np.float32)
+    k = Kernel.load_dense(gpu_ctx, P, gemm_form=form)
+    try:
+        ts = targets_sources(1, g.N, 64)[0]
+        D, bounds = k.batch_fields(ts, "kl")
+        D = D.cpu().numpy()
+        P64 = P.astype(np.float64)
+        for i in (0, 63):
+            ref = dv.kl_field(P64, int(ts[i]))
+            assert normwise(D[i], ref) <= TOL
+            assert within_bound(D[i], ref, bounds[i])
+    finally:
+        k.free()
