@@ -107,7 +107,7 @@ struct dd_kernel {
   // batched-KL operand
   DevBuf L32, Lhi, Llo, Off;
   // truncated
-  DevBuf start, len, col, val, val64, phi;
+  DevBuf start, len, col, val, val64, phi, lphi;
   int64_t nnz = 0;
   std::vector<double> Ht_host, Wt_host;   // per row over the stored entries
   // adjacency
@@ -117,7 +117,7 @@ struct dd_kernel {
 
   size_t footprint() const {
     return P32.bytes + P64.bytes + H.bytes + L32.bytes + Lhi.bytes + Llo.bytes + Off.bytes +
-           start.bytes + len.bytes + col.bytes + val.bytes + val64.bytes + phi.bytes +
+           start.bytes + len.bytes + col.bytes + val.bytes + val64.bytes + phi.bytes + lphi.bytes +
            adj.bytes;
   }
   dd::DenseView dense() const {
@@ -126,7 +126,8 @@ struct dd_kernel {
   dd::CsrView csr() const {
     return dd::CsrView{start.as<const int64_t>(), len.as<const int32_t>(),
                        col.as<const uint16_t>(),  val.as<const float>(),
-                       val64.as<const double>(),  phi.as<const double>(), N, B};
+                       val64.as<const double>(),  phi.as<const double>(),
+                       lphi.as<const double>(),   N, B};
   }
 };
 
@@ -256,6 +257,15 @@ dd_error_bound gemm_bound(const dd_kernel* k, int32_t t) {
   return b;
 }
 
+// log2 of each row's floor, for the streaming kernel's missing-support term.
+dd_status upload_log2_floor(dd_kernel* k, const std::vector<double>& phi) {
+  std::vector<double> l(phi.size());
+  for (size_t i = 0; i < phi.size(); ++i) l[i] = std::log2(phi[i]);
+  HIP_OR(k->lphi.alloc(8 * l.size()));
+  HIP_OR(hipMemcpy(k->lphi.p, l.data(), 8 * l.size(), hipMemcpyHostToDevice));
+  return DD_OK;
+}
+
 // Shared tail of both load paths: truncate the dense view into CSR.
 dd_status build_csr_from_dense(dd_kernel* k, dd::DenseView dv, const DevBuf& row_max) {
   const int32_t N = k->N;
@@ -266,6 +276,7 @@ dd_status build_csr_from_dense(dd_kernel* k, dd::DenseView dv, const DevBuf& row
     HIP_OR(hipMemcpy(mx.data(), row_max.p, sizeof(double) * N, hipMemcpyDeviceToHost));
     for (int32_t x = 0; x < N; ++x) th[x] = k->tau_relative ? k->tau * mx[x] : k->tau;
     HIP_OR(hipMemcpy(thr.p, th.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+    if (dd_status s = upload_log2_floor(k, th)) return s;
   }
   HIP_OR(counts.alloc(sizeof(int32_t) * (size_t)N));
   HIP_OR(dd::launch_trunc_count(dv, thr.as<const double>(), counts.as<int32_t>(), nullptr));
@@ -614,6 +625,7 @@ dd_status dd_load_kernel_csr(dd_ctx* ctx, int32_t N, int32_t B, const int64_t* r
   if (!e && val_is_f64) e = hipMemcpy(k->val64.p, val64p.data(), 8 * (size_t)pos, hipMemcpyHostToDevice);
   if (!e) e = hipMemcpy(k->phi.p, phi.data(), 8 * (size_t)N, hipMemcpyHostToDevice);
   if (e) return bail(fail(DD_EDEVICE, "CSR upload: %s", hipGetErrorString(e)));
+  if (dd_status st = upload_log2_floor(k, phi)) return bail(st);
   if (dd_status s = upload_adjacency(k, adj)) return bail(s);
   return finish_handle(k, ctx, out);
 }

@@ -27,6 +27,7 @@ struct CsrView {
   const float* val;      // [nnz_padded]
   const double* val64;   // [nnz_padded] or nullptr
   const double* phi;     // [N] floor of each row (the truncation threshold)
+  const double* lphi;    // [N] log2 of the floor
   int32_t N, B;
 };
 

@@ -138,33 +138,52 @@ __global__ __launch_bounds__(256) void batch_target_prep(DenseView dv, GemmView 
   }
 }
 
-// Epilogue shared by both forms: d = H_t - o_x W_t - S_xt / s_t (FP64).
+// Epilogue shared by both forms: d = H_t - o_x W_t - S_xt / s_t (FP64),
+// rounded to FP32.  Each 32x32 column tile of a wave is transposed through
+// LDS (stride 33 floats) so that one store instruction writes two full
+// 128-byte row segments of two target fields.  `stage` is 4 x 32 x 33 floats.
 template <int NT>
 __device__ __forceinline__ void write_fields(const GemmView& gv, const BatchOperand& o, int32_t T,
                                              int64_t row0, int lane, const double (&accd)[NT][16],
-                                             float* out) {
+                                             float* stage, float* out) {
   const int r = lane & 31, h = lane >> 5;
+  float* tile = stage + (threadIdx.x >> 6) * (32 * 33);
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
     const int t = n * 32 + r;
-    if (t >= T) continue;
-    const double H = o.H[t], W = o.W[t], is = o.inv_s[t];
+    const bool tv = t < T;
+    const double H = tv ? o.H[t] : 0.0, W = tv ? o.W[t] : 0.0, is = tv ? o.inv_s[t] : 0.0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int64_t x = row0 + 8 * (i >> 2) + 4 * h + (i & 3);
-      if (x < gv.N) {
-        const double d = H - (double)gv.offset[x] * W - accd[n][i] * is;
-        out[(int64_t)t * gv.N + x] = (float)d;
-      }
+      const int xl = 8 * (i >> 2) + 4 * h + (i & 3);
+      const int64_t x = row0 + xl;
+      float d = 0.f;
+      if (tv && x < gv.N) d = (float)(H - (double)gv.offset[x] * W - accd[n][i] * is);
+      tile[r * 33 + xl] = d;
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int tl = 2 * q + h;
+      const int tt = n * 32 + tl;
+      const int64_t x = row0 + r;
+      if (tt < T && x < gv.N) out[(int64_t)tt * gv.N + x] = tile[tl * 33 + r];
+    }
+    __syncthreads();
   }
 }
 
 template <int NT>
 __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o, int32_t T,
                                                      float* __restrict__ out) {
-  __shared__ __attribute__((aligned(16))) _Float16 sbh[NT * 32][KC + 8];
-  __shared__ __attribute__((aligned(16))) _Float16 sbl[NT * 32][KC + 8];
+  // target tiles (hi, lo) in one LDS buffer, reused by the epilogue as a
+  // 4 x 32 x 33-float stage
+  constexpr int TILE_BYTES = 2 * NT * 32 * (KC + 8) * 2;
+  constexpr int STAGE_BYTES = 4 * 32 * 33 * 4;
+  __shared__ __attribute__((aligned(16)))
+      unsigned char lds[TILE_BYTES > STAGE_BYTES ? TILE_BYTES : STAGE_BYTES];
+  _Float16 (*sbh)[KC + 8] = reinterpret_cast<_Float16 (*)[KC + 8]>(lds);
+  _Float16 (*sbl)[KC + 8] = sbh + NT * 32;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
   const int64_t row0 = (int64_t)blockIdx.x * GROWS + wv * 32;
   const int64_t row = row0 + r;
@@ -255,13 +274,16 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
       al[q] = nl[q];
     }
   }
-  write_fields<NT>(gv, o, T, row0, lane, accd, out);
+  __syncthreads();   // every wave is done with the staged target tiles
+  write_fields<NT>(gv, o, T, row0, lane, accd, reinterpret_cast<float*>(lds), out);
 }
 
 template <int NT>
 __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, int32_t T,
                                                    float* __restrict__ out) {
-  __shared__ __attribute__((aligned(16))) float sb[NT * 32][KC + 4];
+  // target tile, reused by the epilogue as a 4 x 32 x 33-float stage
+  // (at least 64 rows of 68 floats = 17,408 bytes >= 16,896)
+  __shared__ __attribute__((aligned(16))) float sb[(NT == 1 ? 2 : NT) * 32][KC + 4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
   const int64_t row0 = (int64_t)blockIdx.x * GROWS + wv * 32;
   const int64_t row = row0 + r;
@@ -333,7 +355,8 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
 #pragma unroll
     for (int q = 0; q < 8; ++q) a[q] = na[q];
   }
-  write_fields<NT>(gv, o, T, row0, lane, accd, out);
+  __syncthreads();
+  write_fields<NT>(gv, o, T, row0, lane, accd, &sb[0][0], out);
 }
 
 hipError_t launch_batch_kl(DenseView dv, GemmView gv, TargetList tl, int32_t T, void* ws,

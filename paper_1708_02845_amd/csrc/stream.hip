@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void csr_field_kernel(CsrView v, int32_t targe
       if (KIND == 0) {
         d = acc + (complete ? 0.0 : (Wt - A));
       } else {
-        const double miss = complete ? 0.0 : (Hbt - E) - log2(v.phi[row]) * (Wt - A);
+        const double miss = complete ? 0.0 : (Hbt - E) - v.lphi[row] * (Wt - A);
         d = (acc + miss) * 0.69314718055994530942;
       }
       out[row] = (float)d;

@@ -1,0 +1,222 @@
+"""Continuous-batching service for path queries over several resident domains.
+
+A query is (domain, source, target): the KL distance field of the target and
+the steepest-descent path from the source.  The server keeps each domain's
+kernel resident (admitted by its HBM footprint), queues queries per domain, and
+whenever a domain has a free batch slot it launches the pending queries as one
+batch: one KL contraction for all their targets, then one path launch for all
+of them, then an asynchronous copy of the paths to pinned host memory, all on
+that slot's stream.  Queries that arrive while a batch is on the GPU go into the
+next batch as soon as a slot (and device memory for its fields) frees up;
+batches of different domains and slots overlap on the device.  Completion is
+observed by polling stream events; latency is arrival to completion on the host
+clock.
+
+The distance fields stay on the device; with ``keep_fields`` each finished
+query keeps a device view of its own field (``Query.field``).
+"""
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .api import Kernel
+
+_STATUS = {0: "reached", 1: "stuck", 2: "max_steps"}
+
+
+@dataclass
+class Query:
+    qid: int
+    domain: str
+    source: int
+    target: int
+    arrival: float                # host clock (perf_counter seconds)
+    done: float = None
+    path: list = None
+    status: str = None
+    rechecks: int = 0
+    batch_size: int = 0
+    field: object = field(default=None, repr=False)   # device view of its field
+
+    @property
+    def latency(self):
+        return None if self.done is None else self.done - self.arrival
+
+
+class _Slot:
+    def __init__(self, torch, max_batch, max_steps):
+        self.stream = torch.cuda.Stream()      # default priority
+        self.busy = False
+        self.queries = []
+        self.event = None
+        self.fields = None
+        self.host_paths = torch.empty((max_batch, max_steps + 1), dtype=torch.int32,
+                                      pin_memory=True)
+        self.host_info = torch.empty((3, max_batch), dtype=torch.int32, pin_memory=True)
+
+
+class _Domain:
+    def __init__(self, name, kernel, slots):
+        self.name = name
+        self.kernel = kernel
+        self.queue = collections.deque()
+        self.slots = slots
+
+
+class Server:
+    """Resident domains, per-domain queues and continuous batching."""
+
+    def __init__(self, ctx, max_batch=64, slots_per_domain=2, max_steps=4000,
+                 hbm_budget=None, gemm_form="f16x3", field_reserve=2, keep_fields=False):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+        self.max_batch = int(max_batch)
+        self.slots_per_domain = int(slots_per_domain)
+        self.max_steps = int(max_steps)
+        self.gemm_form = gemm_form
+        self.field_reserve = field_reserve
+        self.keep_fields = keep_fields
+        free, _ = torch.cuda.mem_get_info(ctx.device)
+        self.hbm_budget = int(free * 0.9) if hbm_budget is None else int(hbm_budget)
+        self.hbm_used = 0
+        self.domains = {}
+        self.refused = []
+        self.completed = []
+        self.batch_sizes = collections.Counter()
+        self._next_id = 0
+
+    # ---- admission ----
+    def domain_footprint(self, N, B):
+        """Resident bytes of a domain plus the field memory of its batch slots."""
+        resident = Kernel.dense_footprint(N, B, gemm_form=self.gemm_form)
+        fields = self.slots_per_domain * self.max_batch * N * 4
+        return resident + fields
+
+    def add_domain(self, name, P, adjacency):
+        """Load a domain if its footprint fits the HBM budget; False if refused."""
+        N, B = P.shape
+        need = self.domain_footprint(N, B)
+        if self.hbm_used + need > self.hbm_budget:
+            self.refused.append((name, need))
+            return False
+        k = Kernel.load_dense(self.ctx, P, adjacency=adjacency, gemm_form=self.gemm_form)
+        slots = [_Slot(self.torch, self.max_batch, self.max_steps)
+                 for _ in range(self.slots_per_domain)]
+        self.domains[name] = _Domain(name, k, slots)
+        self.hbm_used += need
+        return True
+
+    def close(self):
+        self.torch.cuda.synchronize()
+        for d in self.domains.values():
+            d.kernel.free()
+        self.domains.clear()
+
+    # ---- queries ----
+    def submit(self, domain, source, target, arrival=None):
+        d = self.domains[domain]
+        if not (0 <= source < d.kernel.N and 0 <= target < d.kernel.N):
+            raise ValueError("source/target out of range")
+        q = Query(self._next_id, domain, int(source), int(target),
+                  time.perf_counter() if arrival is None else arrival)
+        self._next_id += 1
+        d.queue.append(q)
+        return q
+
+    def pending(self):
+        return sum(len(d.queue) for d in self.domains.values()) + \
+            sum(1 for d in self.domains.values() for s in d.slots if s.busy)
+
+    def _launch(self, d, slot):
+        torch = self.torch
+        n = min(self.max_batch, len(d.queue))
+        N = d.kernel.N
+        free, _ = torch.cuda.mem_get_info(self.ctx.device)
+        if free < self.field_reserve * n * N * 4:
+            return False                              # wait for memory to free up
+        qs = [d.queue.popleft() for _ in range(n)]
+        ts = np.array([q.target for q in qs], dtype=np.int32)
+        ss = np.array([q.source for q in qs], dtype=np.int32)
+        with torch.cuda.stream(slot.stream):
+            fields = torch.empty((n, N), dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+            _, bounds = d.kernel.batch_fields(ts, "kl", out=fields, stream=slot.stream)
+            paths, lens, status, rechecks = d.kernel.trace_paths(
+                ss, ts, "kl", fields, bounds, self.max_steps, stream=slot.stream)
+            slot.host_paths[:n].copy_(paths, non_blocking=True)
+            slot.host_info[0, :n].copy_(lens, non_blocking=True)
+            slot.host_info[1, :n].copy_(status, non_blocking=True)
+            slot.host_info[2, :n].copy_(rechecks, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(slot.stream)
+        slot.busy, slot.queries, slot.event, slot.fields = True, qs, ev, fields
+        self.batch_sizes[n] += 1
+        return True
+
+    def _finish(self, slot):
+        now = time.perf_counter()
+        info = slot.host_info.numpy()
+        paths = slot.host_paths.numpy()
+        for i, q in enumerate(slot.queries):
+            q.path = paths[i, :info[0, i]].tolist()
+            q.status = _STATUS[int(info[1, i])]
+            q.rechecks = int(info[2, i])
+            q.batch_size = len(slot.queries)
+            if self.keep_fields:
+                q.field = slot.fields[i]
+            q.done = now
+            self.completed.append(q)
+        slot.busy, slot.queries, slot.event = False, [], None
+
+    def poll(self):
+        """Finish completed batches, then launch into every free slot."""
+        progressed = False
+        for d in self.domains.values():
+            for slot in d.slots:
+                if slot.busy and slot.event.query():
+                    self._finish(slot)
+                    progressed = True
+            for slot in d.slots:
+                if not slot.busy and d.queue:
+                    progressed |= self._launch(d, slot)
+        return progressed
+
+    def drain(self, timeout=600.0):
+        t0 = time.perf_counter()
+        while self.pending():
+            if not self.poll():
+                time.sleep(0)
+            if time.perf_counter() - t0 > timeout:
+                raise TimeoutError("queries still pending")
+
+    # ---- open-loop driver ----
+    def run_open_loop(self, arrivals, timeout=600.0):
+        """``arrivals``: list of (offset_s, domain, source, target), offsets ascending.
+
+        Queries are submitted at their scheduled times (the arrival time used
+        for latency is the scheduled one, so a slow loop cannot hide queueing).
+        """
+        t0 = time.perf_counter()
+        i = 0
+        out = []
+        while i < len(arrivals) or self.pending():
+            now = time.perf_counter()
+            while i < len(arrivals) and t0 + arrivals[i][0] <= now:
+                off, dom, s, t = arrivals[i]
+                out.append(self.submit(dom, s, t, arrival=t0 + off))
+                i += 1
+            if not self.poll():
+                time.sleep(0)
+            if now - t0 > timeout:
+                raise TimeoutError("open-loop run did not finish")
+        return out
+
+
+def latency_summary(queries):
+    lat = np.array([q.latency for q in queries]) * 1e3
+    return {"queries": len(lat), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
+            "mean_ms": float(lat.mean())}

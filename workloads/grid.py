@@ -58,9 +58,9 @@ class GridDomain:
         g = np.arange(self.G * self.G)
         return np.column_stack([(g % self.G) * self.h, (g // self.G) * self.h])
 
-    def poisson_kernel(self, dtype=np.float64, workers=None):
+    def poisson_kernel(self, dtype=np.float64, workers=None, progress=None):
         if self._P is None or self._P.dtype != dtype:
-            self._P = harmonic_measure_5pt(self, dtype=dtype, workers=workers)
+            self._P = harmonic_measure_5pt(self, dtype=dtype, workers=workers, progress=progress)
         return self._P
 
 
@@ -196,8 +196,13 @@ def _solve_chunk(args):
     return hi - lo
 
 
-def harmonic_measure_5pt(dom, dtype=np.float64, workers=None, chunk=128):
-    """Dense [N, K] matrix: row v = harmonic measure of interior vertex v."""
+def harmonic_measure_5pt(dom, dtype=np.float64, workers=None, chunk=128, progress=None):
+    """Dense [N, K] matrix: row v = harmonic measure of interior vertex v.
+
+    With several workers the columns are solved in forked processes into a
+    shared memory-mapped file, which is returned mapped (no final copy).
+    ``progress(done_columns, K)`` is called as chunks finish.
+    """
     A, R = _five_point_system(dom)
     n, k = dom.N, dom.K
     if workers is None:
@@ -210,6 +215,8 @@ def harmonic_measure_5pt(dom, dtype=np.float64, workers=None, chunk=128):
             X = lu.solve(R[:, lo:hi].toarray())
             np.maximum(X, 0.0, out=X)
             P[:, lo:hi] = X
+            if progress:
+                progress(hi, k)
         return P
     import multiprocessing as mp
     import tempfile
@@ -220,10 +227,14 @@ def harmonic_measure_5pt(dom, dtype=np.float64, workers=None, chunk=128):
         out = np.memmap(name, dtype=dtype, mode="w+", shape=(n, k))
         del out
         _WORK.update(A=A, R=R, lu=None, name=name, shape=(n, k), dtype=dtype)
+        done = 0
         with mp.get_context("fork").Pool(workers) as pool:
-            list(pool.imap_unordered(_solve_chunk, work))
-        P = np.array(np.memmap(name, dtype=dtype, mode="r", shape=(n, k)))
+            for m in pool.imap_unordered(_solve_chunk, work):
+                done += m
+                if progress:
+                    progress(done, k)
+        P = np.memmap(name, dtype=dtype, mode="r+", shape=(n, k))
     finally:
         _WORK.clear()
-        os.unlink(name)
+        os.unlink(name)      # the mapping stays valid until P is released
     return P
