@@ -49,7 +49,14 @@ def parse():
                          "under a profiler that initialises the GPU before main)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (calibrates HBM byte counters)")
-    ap.add_argument("--workload", default="grid257", choices=["grid257", "grid1025"],
+    ap.add_argument("--kernel-cache", default=None,
+                    help=".npy path: load the kernel matrix from it if present, else build and "
+                         "save it there (lets a profiled run skip the build)")
+    ap.add_argument("--qps", type=float, default=200.0, help="serving: arrival rate")
+    ap.add_argument("--duration", type=float, default=30.0, help="serving: seconds of arrivals")
+    ap.add_argument("--serving-grids", default="129,257,513,1025",
+                    help="serving: grid sizes of the resident domains")
+    ap.add_argument("--workload", default="grid257", choices=["grid257", "grid1025", "serving"],
                     help="grid1025: the 1025x1025, 20-obstacle domain (32 GB kernel), batched KL "
                          "at 64 targets and single-target streaming, sampled parity")
     return ap.parse_args()
@@ -57,6 +64,21 @@ def parse():
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_matrix(g, args, progress=None):
+    """FP32 kernel matrix of a grid workload, optionally through an .npy cache."""
+    path = args.kernel_cache
+    if path and os.path.exists(path):
+        P = np.load(path, mmap_mode="r")
+        if P.shape == (g.N, g.K) and P.dtype == np.float32:
+            log(f"kernel matrix from {path}")
+            return P
+    P = g.poisson_kernel(dtype=np.float32, workers=args.setup_workers, progress=progress)
+    if path:
+        np.save(path, P)
+        log(f"kernel matrix saved to {path}")
+    return P
 
 
 def run_grid1025(args):
@@ -81,7 +103,7 @@ def run_grid1025(args):
         if time.perf_counter() - last[0] > 10 or done == k:
             last[0] = time.perf_counter()
             log(f"kernel matrix: {done}/{k} columns, {last[0] - t0:.0f} s")
-    P = g.poisson_kernel(dtype=np.float32, workers=args.setup_workers, progress=prog)
+    P = kernel_matrix(g, args, progress=prog)
     build_s = time.perf_counter() - t0
     T = 64
     ts = targets_sources(2, g.N, T)[0]
@@ -221,6 +243,75 @@ def gbs(nbytes, us):
     return nbytes / (us * 1e-6) / 1e9
 
 
+def run_serving(args):
+    """Open-loop serving over resident grid domains (2/5/10/20 obstacles)."""
+    import torch
+
+    from paper_1708_02845_amd import Context
+    from paper_1708_02845_amd.serve import Server, latency_summary
+    from workloads import CONFIGS, grid_domain
+    from workloads.serving import poisson_arrivals
+
+    c = CONFIGS["c4"]
+    sizes = [int(x) for x in args.serving_grids.split(",")]
+    ctx = Context(0)
+    srv = Server(ctx, max_batch=c["max_batch"], slots_per_domain=2, max_steps=c["max_steps"])
+    doms = []
+    for (G, k, sides) in c["domains"]:
+        if G not in sizes:
+            continue
+        g = grid_domain(G, k, sides, config_id=c["config_id"] + G)
+        log(f"serving: building {G}x{G} ({g.N} x {g.K})")
+        t0 = time.perf_counter()
+        last = [0.0]
+
+        def prog(done, kk):
+            if time.perf_counter() - last[0] > 10:
+                last[0] = time.perf_counter()
+                log(f"  {done}/{kk} columns")
+        P = g.poisson_kernel(dtype=np.float32, workers=args.setup_workers, progress=prog)
+        ok = srv.add_domain(f"grid{G}", P, (g.adj_ptr, g.adj_idx))
+        log(f"  built in {time.perf_counter() - t0:.0f} s, admitted={ok}")
+        if ok:
+            doms.append((f"grid{G}", g.N, srv.domains[f"grid{G}"].kernel.B))
+        del P
+    # warm every domain once
+    for name, n, _ in doms:
+        srv.submit(name, 0, n - 1)
+    srv.drain()
+    srv.completed.clear()
+    srv.batch_sizes.clear()
+    arr = poisson_arrivals(c["config_id"], [(nm, n) for nm, n, _ in doms], args.qps, args.duration)
+    log(f"serving: {len(arr)} arrivals over {args.duration:.0f} s at {args.qps:.0f} QPS")
+    t0 = time.perf_counter()
+    qs = srv.run_open_loop(arr, timeout=args.duration * 10 + 60)
+    wall = time.perf_counter() - t0
+    summ = latency_summary(qs)
+    entries = sum(next(n * b for nm, n, b in doms if nm == q.domain) for q in qs)
+    per_dom = {}
+    for nm, n, b in doms:
+        sel = [q for q in qs if q.domain == nm]
+        if sel:
+            per_dom[nm] = {"N": n, "B": b, **latency_summary(sel),
+                           "reached": sum(q.status == "reached" for q in sel)}
+    out = {"metric": METRIC, "value": entries / wall, "unit": "entries/s", "n_gpus": 1,
+           "steps": len(qs), "warmup": len(doms), "ms_per_step": 1000.0 * wall / len(qs),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16x3",
+           "data": "synthetic",
+           "config": {"workload": "serving: resident grid domains, open-loop Poisson arrivals, "
+                                  "KL field (f16x3 contraction) + path per query, continuous "
+                                  "batching",
+                      "domains": [nm for nm, _, _ in doms], "refused": [r[0] for r in srv.refused],
+                      "qps_offered": args.qps, "qps_achieved": len(qs) / wall,
+                      "max_batch": c["max_batch"], "slots_per_domain": 2},
+           "latency": summ, "per_domain": per_dom,
+           "batch_size_hist": dict(sorted(srv.batch_sizes.items())),
+           "hbm_admitted_bytes": srv.hbm_used}
+    srv.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -229,6 +320,9 @@ def main():
         sys.exit(2)
     if args.workload == "grid1025":
         run_grid1025(args)
+        return
+    if args.workload == "serving":
+        run_serving(args)
         return
 
     import torch
@@ -239,7 +333,7 @@ def main():
 
     tau = 1e-6
     g = build_config("c2")
-    P = g.poisson_kernel(dtype=np.float32, workers=args.setup_workers)
+    P = kernel_matrix(g, args)
     t_arr, s_arr = targets_sources(1, g.N, max(1, args.batch))
     t, s = int(t_arr[0]), int(s_arr[0])
     adj = (g.adj_ptr, g.adj_idx)

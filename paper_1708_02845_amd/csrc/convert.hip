@@ -141,7 +141,8 @@ __global__ __launch_bounds__(256) void trunc_fill_kernel(DenseView v, const doub
 }
 
 // l_xb = log P_xb - o_x with o_x = log max_b P_xb (natural log, FP64 then
-// rounded): FP32 rows, or an FP16 hi + lo split of them.
+// rounded): FP32, or an FP16 hi + lo split, written in the tile-major layout
+// of the contraction operand (padding rows are zeroed by the caller).
 __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, int64_t lda,
                                                         float* l32, uint16_t* lhi, uint16_t* llo,
                                                         float* offset, int32_t* zeros) {
@@ -155,7 +156,10 @@ __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, i
   if (lane == 0) offset[row] = (float)o;
   const double of = (double)(float)o;   // the offset the epilogue will use
   int nz = 0;
+  const int64_t nch = lda / kGemmK;
+  const int64_t tile_base = (row / kGemmRows) * nch * kGemmRows * kGemmK + (row % kGemmRows) * kGemmK;
   for (int64_t b = lane; b < lda; b += 64) {
+    const int64_t at = tile_base + (b / kGemmK) * kGemmRows * kGemmK + (b % kGemmK);
     double l = 0.0;
     if (b < v.B) {
       const double p = master_at(v, row, (int)b);
@@ -165,12 +169,12 @@ __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, i
         nz = 1;   // log 0: this row cannot enter the contraction
     }
     if (form == 0) {
-      l32[row * lda + b] = (float)l;
+      l32[at] = (float)l;
     } else {
       const _Float16 hi = (_Float16)l;
       const _Float16 lo = (_Float16)(l - (double)hi);
-      lhi[row * lda + b] = __builtin_bit_cast(uint16_t, hi);
-      llo[row * lda + b] = __builtin_bit_cast(uint16_t, lo);
+      lhi[at] = __builtin_bit_cast(uint16_t, hi);
+      llo[at] = __builtin_bit_cast(uint16_t, lo);
     }
   }
   if (__ballot(nz) != 0ull && lane == 0) atomicAdd(zeros, 1);

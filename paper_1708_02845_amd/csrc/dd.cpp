@@ -192,7 +192,7 @@ size_t dense_bytes(int64_t N, int64_t B, int is_f64, const dd_load_opts& o) {
   size_t b = (size_t)(N * ld * 4) + (size_t)N * 8;
   if (is_f64) b += (size_t)(N * B * 8);
   if (o.gemm_form == DD_FORM_F32 || o.gemm_form == DD_FORM_F16X3)
-    b += (size_t)(N * lda * 4) + (size_t)N * 4;
+    b += (size_t)(dd::gemm_rows_padded(N) * lda * 4) + (size_t)N * 4;
   return b;
 }
 
@@ -510,10 +510,16 @@ dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P,
       e = zeros.alloc(4);
       if (!e) e = hipMemset(zeros.p, 0, 4);
       if (!e) e = k->Off.alloc(4 * (size_t)N);
-      if (!e && o.gemm_form == DD_FORM_F32) e = k->L32.alloc(4 * (size_t)N * (size_t)k->lda);
+      const size_t elems = (size_t)dd::gemm_rows_padded(N) * (size_t)k->lda;
+      if (!e && o.gemm_form == DD_FORM_F32) {
+        e = k->L32.alloc(4 * elems);
+        if (!e) e = hipMemset(k->L32.p, 0, 4 * elems);
+      }
       if (!e && o.gemm_form == DD_FORM_F16X3) {
-        e = k->Lhi.alloc(2 * (size_t)N * (size_t)k->lda);
-        if (!e) e = k->Llo.alloc(2 * (size_t)N * (size_t)k->lda);
+        e = k->Lhi.alloc(2 * elems);
+        if (!e) e = k->Llo.alloc(2 * elems);
+        if (!e) e = hipMemset(k->Lhi.p, 0, 2 * elems);
+        if (!e) e = hipMemset(k->Llo.p, 0, 2 * elems);
       }
       if (!e) e = dd::launch_log_forms(k->dense(), o.gemm_form, k->lda, k->L32.as<float>(),
                                        k->Lhi.as<uint16_t>(), k->Llo.as<uint16_t>(),
@@ -736,7 +742,7 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
   const size_t o_small = 0;
   const size_t n_small = inl ? 0 : ((8 * (size_t)T + 15) & ~size_t(15)) + sizeof(dd::Bound) * T;
   const size_t o_row = (o_small + n_small + 255) & ~size_t(255);
-  const size_t n_row = k->is_csr ? 8 * (size_t)T * (size_t)k->B + 32 * (size_t)T : 0;
+  const size_t n_row = 16 * (size_t)T * (size_t)k->B + 32 * (size_t)T;
   const size_t o_nv = (o_row + n_row + 255) & ~size_t(255);
   const size_t n_nv = 4 * (size_t)T * (size_t)k->N * (size_t)k->adj_w;
   AsyncBuf ws(s);
@@ -765,11 +771,13 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
     a.targets = reinterpret_cast<const int32_t*>(base + 4 * (size_t)T);
     a.bounds = reinterpret_cast<const dd::Bound*>(base + o_bnd);
   }
-  if (k->is_csr) {
+  {
     double* trow = reinterpret_cast<double*>(base + o_row);
-    double* tcon = trow + (size_t)T * (size_t)k->B;
-    HIP_OR(dd::launch_target_rows(k->csr(), a, trow, tcon, s));
+    double* tlog = trow + (size_t)T * (size_t)k->B;
+    double* tcon = tlog + (size_t)T * (size_t)k->B;
+    HIP_OR(dd::launch_target_rows(k->dense(), k->csr(), a, trow, tlog, tcon, s));
     a.trow = trow;
+    a.tlog = tlog;
     a.tconst = tcon;
   }
   float* nv = reinterpret_cast<float*>(base + o_nv);

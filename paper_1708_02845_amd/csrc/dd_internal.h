@@ -55,14 +55,23 @@ hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out,
 hipError_t launch_csr_field(CsrView v, int32_t target, int kind, float* out, hipStream_t s);
 
 // ---- batched KL contraction (gemm.hip) ----
+// The log-kernel operand is stored tile-major: rows in tiles of kGemmRows,
+// columns in chunks of kGemmK, element (x, b) at
+//   ((x / kGemmRows) * (lda / kGemmK) + b / kGemmK) * kGemmRows * kGemmK
+//     + (x % kGemmRows) * kGemmK + b % kGemmK,
+// so one workgroup's chunk is one contiguous block.  Rows are padded to a
+// multiple of kGemmRows and columns to lda; padding holds zeros.
+constexpr int kGemmRows = 128;
+constexpr int kGemmK = 64;
 struct GemmView {
-  const float* l32;      // [N][lda] log P - o_x  (form F32)
-  const uint16_t* lhi;   // [N][lda] FP16 bits    (form F16X3)
+  const float* l32;      // tile-major log P - o_x  (form F32)
+  const uint16_t* lhi;   // tile-major FP16 bits    (form F16X3)
   const uint16_t* llo;
   const float* offset;   // [N] o_x = log max_b P_xb
-  int64_t lda;           // a multiple of 64, zero padded
+  int64_t lda;           // a multiple of kGemmK
   int32_t N, B, form;
 };
+inline int64_t gemm_rows_padded(int64_t N) { return (N + kGemmRows - 1) / kGemmRows * kGemmRows; }
 constexpr int kMaxBatch = 64;   // targets per contraction launch
 struct TargetList {
   int32_t t[kMaxBatch];
@@ -90,16 +99,17 @@ struct PathArgs {
   const int32_t* sources;   // [T] device, or nullptr when inline
   const int32_t* targets;   // [T] device, or nullptr when inline
   PathSmall small;
-  const double* trow;       // [T][B] FP64 truncated target rows (CSR handles only)
-  const double* tconst;     // [T][4]: W_t, H_t (natural log), |S_t|, unused (CSR only)
+  const double* trow;       // [T][B] FP64 target rows (truncated rows for CSR handles)
+  const double* tlog;       // [T][B] log of trow (0 where trow is 0)
+  const double* tconst;     // [T][4]: W_t, H_t (natural log), |S_t|, unused
   int32_t* path;            // [T][max_steps+1]
   int32_t* len;             // [T]
   int32_t* status;          // [T]
   int32_t* rechecks;        // [T] or nullptr
   int32_t T, max_steps, kind, is_csr;
 };
-hipError_t launch_target_rows(CsrView cv, PathArgs a, double* trow, double* tconst,
-                              hipStream_t s);
+hipError_t launch_target_rows(DenseView dv, CsrView cv, PathArgs a, double* trow, double* tlog,
+                              double* tconst, hipStream_t s);
 hipError_t launch_neighbor_values(PathArgs a, int32_t N, float* nv, hipStream_t s);
 hipError_t launch_paths(DenseView dv, CsrView cv, PathArgs a, hipStream_t s);
 

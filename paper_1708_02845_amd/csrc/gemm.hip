@@ -20,10 +20,12 @@
 // so the FP32 accumulation error is that of 64-term partial sums; H_t, W_t and
 // the final combination are FP64.
 //
-// The order of K inside a chunk is a free choice, as long as both operands
-// use the same one: lane half h of a wave reads the contiguous K range
-// [32h, 32h+32) of the chunk, which turns the A loads into 64- or 128-byte
-// contiguous reads per lane.
+// The operand is stored tile-major (128 rows x 64 columns per contiguous
+// block, see dd_internal.h), so a workgroup's K-chunk is one 16 KB (FP16) or
+// 32 KB (FP32) block and a wave's loads cover 4-8 KB contiguously.  The order
+// of K inside a chunk is a free choice, as long as both operands use the same
+// one: lane half h of a wave reads the contiguous K range [32h, 32h+32) of
+// its row in the chunk.
 #include <math.h>
 
 #include "dd_internal.h"
@@ -33,9 +35,10 @@ namespace dd {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int KC = 64;           // K per chunk
+constexpr int KC = kGemmK;       // K per chunk
 constexpr int GW = 4;            // waves per workgroup
 constexpr int GROWS = 32 * GW;   // rows per workgroup
+static_assert(GROWS == kGemmRows, "a workgroup owns one row tile of the operand");
 
 struct BatchOperand {
   float* b32;        // [Tpad][lda] FP32 targets (F32)
@@ -186,20 +189,22 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
   _Float16 (*sbl)[KC + 8] = sbh + NT * 32;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
   const int64_t row0 = (int64_t)blockIdx.x * GROWS + wv * 32;
-  const int64_t row = row0 + r;
-  const bool rv = row < gv.N;
-  const uint16_t* ahp = gv.lhi + (rv ? row : 0) * gv.lda + h * 32;
-  const uint16_t* alp = gv.llo + (rv ? row : 0) * gv.lda + h * 32;
   const int nchunks = (int)(gv.lda / KC);
+  // tile-major operand: this workgroup's chunk c is one contiguous block of
+  // GROWS x KC; rows past N are zero in memory
+  const int64_t tile0 = (int64_t)blockIdx.x * nchunks * (GROWS * KC);
+  const int64_t lane_off = (int64_t)(wv * 32 + r) * KC + h * 32;
+  const uint16_t* ahp = gv.lhi + tile0 + lane_off;
+  const uint16_t* alp = gv.llo + tile0 + lane_off;
+  constexpr int64_t CHUNK = GROWS * KC;
   constexpr int SEGS = NT * 32 * 8;          // 16-byte segments per chunk per array
   constexpr int SPT = (SEGS + 255) / 256;    // per thread
 
   uint4 ah[4], al[4], nh[4], nl[4], bh[SPT], bl[SPT];
-  const uint4 z = make_uint4(0, 0, 0, 0);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    ah[q] = rv ? *reinterpret_cast<const uint4*>(ahp + q * 8) : z;
-    al[q] = rv ? *reinterpret_cast<const uint4*>(alp + q * 8) : z;
+    ah[q] = *reinterpret_cast<const uint4*>(ahp + q * 8);
+    al[q] = *reinterpret_cast<const uint4*>(alp + q * 8);
   }
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
@@ -233,10 +238,11 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
     __syncthreads();
     if (c + 1 < nchunks) {
       const int64_t ko = (int64_t)(c + 1) * KC;
+      const int64_t ao = (int64_t)(c + 1) * CHUNK;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        nh[q] = rv ? *reinterpret_cast<const uint4*>(ahp + ko + q * 8) : z;
-        nl[q] = rv ? *reinterpret_cast<const uint4*>(alp + ko + q * 8) : z;
+        nh[q] = *reinterpret_cast<const uint4*>(ahp + ao + q * 8);
+        nl[q] = *reinterpret_cast<const uint4*>(alp + ao + q * 8);
       }
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
@@ -286,17 +292,16 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
   __shared__ __attribute__((aligned(16))) float sb[(NT == 1 ? 2 : NT) * 32][KC + 4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
   const int64_t row0 = (int64_t)blockIdx.x * GROWS + wv * 32;
-  const int64_t row = row0 + r;
-  const bool rv = row < gv.N;
-  const float* ap = gv.l32 + (rv ? row : 0) * gv.lda + h * 32;
   const int nchunks = (int)(gv.lda / KC);
+  const int64_t tile0 = (int64_t)blockIdx.x * nchunks * (GROWS * KC);
+  const float* ap = gv.l32 + tile0 + (int64_t)(wv * 32 + r) * KC + h * 32;
+  constexpr int64_t CHUNK = GROWS * KC;
   constexpr int SEGS = NT * 32 * 16;          // 16-byte segments per chunk
   constexpr int SPT = (SEGS + 255) / 256;
 
   float4 a[8], na[8], bq[SPT];
-  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) a[q] = rv ? *reinterpret_cast<const float4*>(ap + q * 4) : z;
+  for (int q = 0; q < 8; ++q) a[q] = *reinterpret_cast<const float4*>(ap + q * 4);
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
     const int sg = threadIdx.x + q * 256;
@@ -323,8 +328,9 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
     __syncthreads();
     if (c + 1 < nchunks) {
       const int64_t ko = (int64_t)(c + 1) * KC;
+      const int64_t ao = (int64_t)(c + 1) * CHUNK;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) na[q] = rv ? *reinterpret_cast<const float4*>(ap + ko + q * 4) : z;
+      for (int q = 0; q < 8; ++q) na[q] = *reinterpret_cast<const float4*>(ap + ao + q * 4);
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
         const int sg = threadIdx.x + q * 256;

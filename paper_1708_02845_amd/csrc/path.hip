@@ -36,25 +36,45 @@ __device__ __forceinline__ Bound path_bound(const PathArgs& a, int i) {
   return Bound{a.small.babs[i], a.small.brel[i]};
 }
 
-// Truncated target rows in FP64 (stored entries scattered into a dense row)
-// and constants W = sum p, H = sum p ln p, |S| over the stored entries.
-__global__ __launch_bounds__(256) void target_rows_kernel(CsrView cv, PathArgs a, double* trow,
+// Target rows in FP64 (dense: the master row; truncated: the stored entries
+// scattered into a dense row), their logarithms, and constants W = sum p,
+// H = sum p ln p, |S| over the nonzero entries.
+__global__ __launch_bounds__(256) void target_rows_kernel(DenseView dv, CsrView cv, PathArgs a,
+                                                          double* trow, double* tlog,
                                                           double* tconst) {
   const int t = path_target(a, blockIdx.x);
-  const int B = cv.B;
+  const int B = a.is_csr ? cv.B : dv.B;
   double* out = trow + (int64_t)blockIdx.x * B;
+  double* lout = tlog + (int64_t)blockIdx.x * B;
   __shared__ double red[3][8];
-  for (int b = threadIdx.x; b < B; b += blockDim.x) out[b] = 0.0;
-  __syncthreads();
-  const int64_t s = cv.start[t];
-  const int n = cv.len[t];
   double w = 0.0, h = 0.0, c = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double p = cv.val64 ? cv.val64[s + i] : (double)cv.val[s + i];
-    out[cv.col[s + i]] = p;
-    w += p;
-    h += p * log(p);
-    c += 1.0;
+  if (!a.is_csr) {
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+      const double p = dv.P64 ? dv.P64[(int64_t)t * dv.B + b] : (double)dv.P[(int64_t)t * dv.ld + b];
+      const double lp = p > 0.0 ? log(p) : 0.0;
+      out[b] = p;
+      lout[b] = lp;
+      w += p;
+      h += p * lp;
+      c += p > 0.0 ? 1.0 : 0.0;
+    }
+  } else {
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+      out[b] = 0.0;
+      lout[b] = 0.0;
+    }
+    __syncthreads();
+    const int64_t s = cv.start[t];
+    const int n = cv.len[t];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double p = cv.val64 ? cv.val64[s + i] : (double)cv.val[s + i];
+      const double lp = log(p);
+      out[cv.col[s + i]] = p;
+      lout[cv.col[s + i]] = lp;
+      w += p;
+      h += p * lp;
+      c += 1.0;
+    }
   }
   w = wsum(w);
   h = wsum(h);
@@ -103,27 +123,23 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-// FP64 distance of row x to the target, the whole block cooperating.  Dense
-// handles read the target row from the master; truncated handles use the
-// staged FP64 target row and its constants.
+// FP64 distance of row x to the target, the whole block cooperating, from
+// the staged FP64 target row p, its logarithms lp and constants tc.  The KL
+// terms are p (log p - log q).
 __device__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_csr, int kind,
-                                 int t, const double* p, const double* tc, int x, double* red) {
+                                 const double* p, const double* lp, const double* tc, int x,
+                                 double* red) {
   const int tid = threadIdx.x, nt = blockDim.x;
   if (!is_csr) {
     double acc = 0.0;
     for (int b = tid; b < dv.B; b += nt) {
-      double q, pb;
-      if (dv.P64) {
-        q = dv.P64[(int64_t)x * dv.B + b];
-        pb = dv.P64[(int64_t)t * dv.B + b];
-      } else {
-        q = (double)dv.P[(int64_t)x * dv.ld + b];
-        pb = (double)dv.P[(int64_t)t * dv.ld + b];
-      }
+      const double q =
+          dv.P64 ? dv.P64[(int64_t)x * dv.B + b] : (double)dv.P[(int64_t)x * dv.ld + b];
+      const double pb = p[b];
       if (kind == 0) {
         acc += fabs(pb - q);
       } else if (pb > 0.0) {
-        acc += pb * log(pb / q);
+        acc += pb * (lp[b] - log(q));
       }
     }
     return block_sum(acc, red);
@@ -133,13 +149,14 @@ __device__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_
   double acc = 0.0, A = 0.0, E = 0.0, c = 0.0;
   for (int i = tid; i < n; i += nt) {
     const double q = cv.val64 ? cv.val64[s + i] : (double)cv.val[s + i];
-    const double pb = p[cv.col[s + i]];
+    const int b = cv.col[s + i];
+    const double pb = p[b];
     A += pb;
     if (kind == 0) {
       acc += fabs(q - pb);
     } else if (pb > 0.0) {
-      acc += pb * log(pb / q);
-      E += pb * log(pb);
+      acc += pb * (lp[b] - log(q));
+      E += pb * lp[b];
     }
     c += pb > 0.0 ? 1.0 : 0.0;
   }
@@ -177,8 +194,10 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
   const float* nvi = a.nv + (int64_t)i * N * W;
   const Bound bnd = path_bound(a, i);
   const double ea = bnd.abs, er = bnd.rel;
-  const double* p = a.is_csr ? a.trow + (int64_t)i * cv.B : nullptr;
-  const double* tc = a.is_csr ? a.tconst + (int64_t)i * 4 : nullptr;
+  const int Bt = a.is_csr ? cv.B : dv.B;
+  const double* p = a.trow + (int64_t)i * Bt;
+  const double* lpt = a.tlog + (int64_t)i * Bt;
+  const double* tc = a.tconst + (int64_t)i * 4;
   int32_t* path = a.path + (int64_t)i * (a.max_steps + 1);
   const int t = path_target(a, i);
   int v = path_source(a, i);
@@ -244,14 +263,14 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
       stuck = true;
     } else {
       ++rechecks;
-      const double dxv = exact_distance(dv, cv, a.is_csr, a.kind, t, p, tc, v, red);
+      const double dxv = exact_distance(dv, cv, a.is_csr, a.kind, p, lpt, tc, v, red);
       double best = __builtin_inf();
       int best_u = 0x7fffffff;
       for (int j = 0; j < deg; ++j) {
         const int uj = __builtin_amdgcn_readlane(ul, j);
         const double vj = (double)unkey((uint32_t)__builtin_amdgcn_readlane((int)kl, j));
         if (vj - (ea + er * fabs(vj)) > v1 + e1) continue;   // certainly above the best
-        const double dx = exact_distance(dv, cv, a.is_csr, a.kind, t, p, tc, uj, red);
+        const double dx = exact_distance(dv, cv, a.is_csr, a.kind, p, lpt, tc, uj, red);
         if (dx < best || (dx == best && uj < best_u)) {
           best = dx;
           best_u = uj;
@@ -282,9 +301,10 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
   }
 }
 
-hipError_t launch_target_rows(CsrView cv, PathArgs a, double* trow, double* tconst,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(target_rows_kernel, dim3(a.T), dim3(256), 0, s, cv, a, trow, tconst);
+hipError_t launch_target_rows(DenseView dv, CsrView cv, PathArgs a, double* trow, double* tlog,
+                              double* tconst, hipStream_t s) {
+  hipLaunchKernelGGL(target_rows_kernel, dim3(a.T), dim3(256), 0, s, dv, cv, a, trow, tlog,
+                     tconst);
   return hipGetLastError();
 }
 

@@ -59,8 +59,9 @@ def test_footprint_is_host_arithmetic(lib):
     ld = 260
     assert Kernel.dense_footprint(N, B) == N * ld * 4 + N * 8
     assert Kernel.dense_footprint(N, B, f64=True) == N * ld * 4 + N * 8 + N * B * 8
-    lda = 320   # the contraction operand's rows are padded to a multiple of 64
-    assert Kernel.dense_footprint(N, B, gemm_form="f32") == N * ld * 4 + N * lda * 4 + N * 8 + N * 4
+    lda = 320    # operand columns padded to a multiple of 64
+    npad = 1024  # operand rows padded to a multiple of 128 (tile-major layout)
+    assert Kernel.dense_footprint(N, B, gemm_form="f32") == N * ld * 4 + npad * lda * 4 + N * 8 + N * 4
     assert Kernel.dense_footprint(N, B, gemm_form="f16x3") == Kernel.dense_footprint(N, B, gemm_form="f32")
     from paper_1708_02845_amd import _lib as L
     out = C.c_size_t()
