@@ -192,6 +192,21 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
                          int32_t max_steps, int32_t* path_dev, int32_t* len_dev,
                          int32_t* status_dev, int32_t* rechecks_dev, void* stream);
 
+/* Spurious local minima of T fields (Section V, "Low resolution
+ * discretizations"): a vertex v other than the target is a local minimum when
+ * no neighbour u has d(u) < d(v).  Each vertex is classified against the
+ * field's stated bound:
+ *   0  not a minimum: some neighbour is certainly lower,
+ *   1  certainly a minimum: every neighbour is certainly not lower,
+ *   2  undecided within the bound (exact ties included).
+ *   fields_dev  device [T][N] FP32; bounds host [T]; targets host [T]
+ *   class_dev   device [T][N] uint8 classes (nullable)
+ *   counts_dev  device [T][2] int32: certain minima, undecided (nullable)
+ * Needs the adjacency.  Asynchronous on `stream`. */
+dd_status dd_local_minima(dd_kernel* k, int32_t T, const int32_t* targets, const float* fields_dev,
+                          const dd_error_bound* bounds, uint8_t* class_dev, int32_t* counts_dev,
+                          void* stream);
+
 /* Plan one path: the field of `target` (dd_distance_field) followed by the
  * path from `source` (dd_trace_paths).  path_host must hold max_steps+1
  * entries.  rechecks nullable.  Synchronous with respect to `stream`. */

@@ -63,6 +63,8 @@ EXPORTS = {
     "dd_plan_path": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                C.c_void_p]),
+    "dd_local_minima": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                  C.POINTER(dd_error_bound), C.c_void_p, C.c_void_p, C.c_void_p]),
     "dd_free_kernel": (C.c_int, [C.c_void_p]),
     "dd_last_error": (C.c_char_p, []),
 }

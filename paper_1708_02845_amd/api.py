@@ -206,6 +206,24 @@ class Kernel:
                                          C.c_void_p(info[2].data_ptr()), _stream_handle(stream)))
         return paths, info[0], info[1], info[2]
 
+    def local_minima(self, targets, fields, bounds, stream=None):
+        """Device tensors (classes uint8 [T, N], counts int32 [T, 2]) of the
+        local-minimum census: 0 not a minimum, 1 certain minimum, 2 undecided."""
+        torch = _torch()
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        T = len(t)
+        dev = f"cuda:{self.ctx.device}"
+        if not fields.is_contiguous() or fields.dtype != torch.float32:
+            raise ValueError("fields must be contiguous float32")
+        cls = torch.empty((T, self.N), dtype=torch.uint8, device=dev)
+        counts = torch.empty((T, 2), dtype=torch.int32, device=dev)
+        b = (L.dd_error_bound * T)(*[L.dd_error_bound(a, r) for a, r in bounds])
+        L.check(self._lib.dd_local_minima(self._h, int(T), C.c_void_p(t.ctypes.data),
+                                          C.c_void_p(fields.data_ptr()), b,
+                                          C.c_void_p(cls.data_ptr()), C.c_void_p(counts.data_ptr()),
+                                          _stream_handle(stream)))
+        return cls, counts
+
     def plan_path(self, source, target, kind, max_steps=4000, stream=None):
         """(vertex list, status name, FP64 re-decisions) for one query; synchronous."""
         buf = (C.c_int32 * (max_steps + 1))()

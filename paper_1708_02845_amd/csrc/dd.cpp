@@ -787,6 +787,52 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
   return DD_OK;
 }
 
+dd_status dd_local_minima(dd_kernel* k, int32_t T, const int32_t* targets, const float* fields_dev,
+                          const dd_error_bound* bounds, uint8_t* class_dev, int32_t* counts_dev,
+                          void* stream) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (!k->has_adj) return fail(DD_EINVAL, "kernel was loaded without adjacency");
+  if (T <= 0 || !targets || !fields_dev || !bounds)
+    return fail(DD_EINVAL, "T=%d or a required pointer is null", T);
+  for (int32_t i = 0; i < T; ++i) {
+    if (targets[i] < 0 || targets[i] >= k->N)
+      return fail(DD_EINVAL, "targets[%d]=%d not in [0, %d)", i, targets[i], k->N);
+    if (!(bounds[i].abs >= 0.0) || !(bounds[i].rel >= 0.0))
+      return fail(DD_EINVAL, "bound %d is negative or NaN", i);
+  }
+  HIP_OR(hipSetDevice(k->ctx->device));
+  hipStream_t s = as_stream(stream);
+  dd::PathArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.adj = k->adj.as<const int32_t>();
+  a.adj_w = k->adj_w;
+  a.fields = fields_dev;
+  a.T = T;
+  AsyncBuf ws(s);
+  std::vector<unsigned char> host;
+  if (T <= dd::kInlinePaths) {
+    for (int32_t i = 0; i < T; ++i) {
+      a.small.tgt[i] = targets[i];
+      a.small.babs[i] = bounds[i].abs;
+      a.small.brel[i] = bounds[i].rel;
+    }
+  } else {
+    const size_t o_bnd = (4 * (size_t)T + 15) & ~size_t(15);
+    host.resize(o_bnd + sizeof(dd::Bound) * T);
+    std::memcpy(host.data(), targets, 4 * (size_t)T);
+    for (int32_t i = 0; i < T; ++i) {
+      dd::Bound b{bounds[i].abs, bounds[i].rel};
+      std::memcpy(host.data() + o_bnd + sizeof(dd::Bound) * i, &b, sizeof b);
+    }
+    HIP_OR(ws.alloc(host.size()));
+    HIP_OR(hipMemcpyAsync(ws.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
+    a.targets = ws.as<const int32_t>();
+    a.bounds = reinterpret_cast<const dd::Bound*>(ws.as<unsigned char>() + o_bnd);
+  }
+  HIP_OR(dd::launch_local_minima(a, k->N, class_dev, counts_dev, s));
+  return DD_OK;
+}
+
 dd_status dd_plan_path(dd_kernel* k, int32_t source, int32_t target, int32_t kind,
                        int32_t max_steps, int32_t* path_host, int32_t* len, int32_t* status,
                        int32_t* rechecks, void* stream) {

@@ -112,6 +112,10 @@ hipError_t launch_target_rows(DenseView dv, CsrView cv, PathArgs a, double* trow
                               double* tconst, hipStream_t s);
 hipError_t launch_neighbor_values(PathArgs a, int32_t N, float* nv, hipStream_t s);
 hipError_t launch_paths(DenseView dv, CsrView cv, PathArgs a, hipStream_t s);
+// local-minimum census (path.hip): uses adj, adj_w, fields, T, targets/bounds
+// (inline or device) of PathArgs
+hipError_t launch_local_minima(PathArgs a, int32_t N, uint8_t* cls, int32_t* counts,
+                               hipStream_t s);
 
 int num_cus();
 

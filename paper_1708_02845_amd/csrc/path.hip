@@ -301,6 +301,65 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
   }
 }
 
+// One thread per (field, vertex).  Interval test against the field's bound:
+// a neighbour is certainly lower when its upper end is below v's lower end,
+// certainly not lower when its lower end is at or above v's upper end.
+__global__ __launch_bounds__(256) void local_minima_kernel(PathArgs a, int32_t N, uint8_t* cls,
+                                                           int32_t* counts) {
+  const int64_t total = (int64_t)N * a.T;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / N);
+    const int v = (int)(idx - (int64_t)i * N);
+    const float* d = a.fields + (int64_t)i * N;
+    const Bound bnd = path_bound(a, i);
+    int c = 0;
+    if (v != path_target(a, i)) {
+      const double dv = (double)d[v];
+      const double lo_v = dv - (bnd.abs + bnd.rel * fabs(dv));
+      const double hi_v = dv + (bnd.abs + bnd.rel * fabs(dv));
+      bool lower = false, unsure = false;
+      for (int j = 0; j < a.adj_w; ++j) {
+        const int u = a.adj[(int64_t)v * a.adj_w + j];
+        if (u < 0) break;
+        const double du = (double)d[u];
+        const double e = bnd.abs + bnd.rel * fabs(du);
+        if (du + e < lo_v) {
+          lower = true;
+          break;
+        }
+        if (du - e < hi_v) unsure = true;
+      }
+      c = lower ? 0 : (unsure ? 2 : 1);
+    }
+    if (cls) cls[idx] = (uint8_t)c;
+    if (counts && c) atomicAdd(counts + 2 * i + (c - 1), 1);
+  }
+}
+
+// Clears the census counters with a kernel (not a memset node), so a caller
+// may capture the call in a graph.
+__global__ void zero_counts_kernel(int32_t* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+hipError_t launch_local_minima(PathArgs a, int32_t N, uint8_t* cls, int32_t* counts,
+                               hipStream_t s) {
+  if (counts) {
+    hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(256), 0, s, counts, 2 * a.T);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int64_t total = (int64_t)N * a.T;
+  int64_t grid = (total + 255) / 256;
+  const int64_t cap = (int64_t)num_cus() * 16;
+  if (grid > cap) grid = cap;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(local_minima_kernel, dim3((unsigned)grid), dim3(256), 0, s, a, N, cls,
+                     counts);
+  return hipGetLastError();
+}
+
 hipError_t launch_target_rows(DenseView dv, CsrView cv, PathArgs a, double* trow, double* tlog,
                               double* tconst, hipStream_t s) {
   hipLaunchKernelGGL(target_rows_kernel, dim3(a.T), dim3(256), 0, s, dv, cv, a, trow, tlog,
