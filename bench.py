@@ -54,6 +54,9 @@ def parse():
                          "save it there (lets a profiled run skip the build)")
     ap.add_argument("--qps", type=float, default=200.0, help="serving: arrival rate")
     ap.add_argument("--duration", type=float, default=30.0, help="serving: seconds of arrivals")
+    ap.add_argument("--slots", type=int, default=1,
+                    help="serving: batch slots (streams) per domain; keep domains x slots within "
+                         "the process's hardware queues, or short batches queue behind long ones")
     ap.add_argument("--serving-grids", default="129,257,513,1025",
                     help="serving: grid sizes of the resident domains")
     ap.add_argument("--workload", default="grid257", choices=["grid257", "grid1025", "serving"],
@@ -255,7 +258,8 @@ def run_serving(args):
     c = CONFIGS["c4"]
     sizes = [int(x) for x in args.serving_grids.split(",")]
     ctx = Context(0)
-    srv = Server(ctx, max_batch=c["max_batch"], slots_per_domain=2, max_steps=c["max_steps"])
+    srv = Server(ctx, max_batch=c["max_batch"], slots_per_domain=args.slots,
+                 max_steps=c["max_steps"])
     doms = []
     for (G, k, sides) in c["domains"]:
         if G not in sizes:
@@ -303,7 +307,7 @@ def run_serving(args):
                                   "batching",
                       "domains": [nm for nm, _, _ in doms], "refused": [r[0] for r in srv.refused],
                       "qps_offered": args.qps, "qps_achieved": len(qs) / wall,
-                      "max_batch": c["max_batch"], "slots_per_domain": 2},
+                      "max_batch": c["max_batch"], "slots_per_domain": args.slots},
            "latency": summ, "per_domain": per_dom,
            "batch_size_hist": dict(sorted(srv.batch_sizes.items())),
            "hbm_admitted_bytes": srv.hbm_used}

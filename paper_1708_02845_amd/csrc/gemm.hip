@@ -34,6 +34,10 @@ namespace dd {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+// Register arrays use native vector types: arrays of HIP's struct vector
+// types are not promoted to registers and end up in scratch memory.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int KC = kGemmK;       // K per chunk
 constexpr int GW = 4;            // waves per workgroup
@@ -198,22 +202,23 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
   const uint16_t* alp = gv.llo + tile0 + lane_off;
   constexpr int64_t CHUNK = GROWS * KC;
   constexpr int SEGS = NT * 32 * 8;          // 16-byte segments per chunk per array
-  constexpr int SPT = (SEGS + 255) / 256;    // per thread
+  constexpr int SPT = SEGS / 256;            // per thread
+  // every thread stages whole segments unconditionally: a guarded, partly
+  // assigned staging array is placed in scratch memory by the compiler
+  static_assert(SEGS % 256 == 0, "B segments must divide evenly over the workgroup");
 
-  uint4 ah[4], al[4], nh[4], nl[4], bh[SPT], bl[SPT];
+  u32x4 ah[4], al[4], nh[4], nl[4], bh[SPT], bl[SPT];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    ah[q] = *reinterpret_cast<const uint4*>(ahp + q * 8);
-    al[q] = *reinterpret_cast<const uint4*>(alp + q * 8);
+    ah[q] = *reinterpret_cast<const u32x4*>(ahp + q * 8);
+    al[q] = *reinterpret_cast<const u32x4*>(alp + q * 8);
   }
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
     const int sg = threadIdx.x + q * 256;
-    if (sg < SEGS) {
-      const int64_t g = (int64_t)(sg >> 3) * gv.lda + (sg & 7) * 8;
-      bh[q] = *reinterpret_cast<const uint4*>(o.bhi + g);
-      bl[q] = *reinterpret_cast<const uint4*>(o.blo + g);
-    }
+    const int64_t g = (int64_t)(sg >> 3) * gv.lda + (sg & 7) * 8;
+    bh[q] = *reinterpret_cast<const u32x4*>(o.bhi + g);
+    bl[q] = *reinterpret_cast<const u32x4*>(o.blo + g);
   }
   floatx16 acc[NT];
   double accd[NT][16];
@@ -230,10 +235,8 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int sg = threadIdx.x + q * 256;
-      if (sg < SEGS) {
-        *reinterpret_cast<uint4*>(&sbh[sg >> 3][(sg & 7) * 8]) = bh[q];
-        *reinterpret_cast<uint4*>(&sbl[sg >> 3][(sg & 7) * 8]) = bl[q];
-      }
+      *reinterpret_cast<u32x4*>(&sbh[sg >> 3][(sg & 7) * 8]) = bh[q];
+      *reinterpret_cast<u32x4*>(&sbl[sg >> 3][(sg & 7) * 8]) = bl[q];
     }
     __syncthreads();
     if (c + 1 < nchunks) {
@@ -241,17 +244,15 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
       const int64_t ao = (int64_t)(c + 1) * CHUNK;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        nh[q] = *reinterpret_cast<const uint4*>(ahp + ao + q * 8);
-        nl[q] = *reinterpret_cast<const uint4*>(alp + ao + q * 8);
+        nh[q] = *reinterpret_cast<const u32x4*>(ahp + ao + q * 8);
+        nl[q] = *reinterpret_cast<const u32x4*>(alp + ao + q * 8);
       }
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
         const int sg = threadIdx.x + q * 256;
-        if (sg < SEGS) {
-          const int64_t g = (int64_t)(sg >> 3) * gv.lda + ko + (sg & 7) * 8;
-          bh[q] = *reinterpret_cast<const uint4*>(o.bhi + g);
-          bl[q] = *reinterpret_cast<const uint4*>(o.blo + g);
-        }
+        const int64_t g = (int64_t)(sg >> 3) * gv.lda + ko + (sg & 7) * 8;
+        bh[q] = *reinterpret_cast<const u32x4*>(o.bhi + g);
+        bl[q] = *reinterpret_cast<const u32x4*>(o.blo + g);
       }
     }
 #pragma unroll
@@ -297,16 +298,16 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
   const float* ap = gv.l32 + tile0 + (int64_t)(wv * 32 + r) * KC + h * 32;
   constexpr int64_t CHUNK = GROWS * KC;
   constexpr int SEGS = NT * 32 * 16;          // 16-byte segments per chunk
-  constexpr int SPT = (SEGS + 255) / 256;
+  constexpr int SPT = SEGS / 256;
+  static_assert(SEGS % 256 == 0, "B segments must divide evenly over the workgroup");
 
-  float4 a[8], na[8], bq[SPT];
+  f32x4 a[8], na[8], bq[SPT];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) a[q] = *reinterpret_cast<const float4*>(ap + q * 4);
+  for (int q = 0; q < 8; ++q) a[q] = *reinterpret_cast<const f32x4*>(ap + q * 4);
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
     const int sg = threadIdx.x + q * 256;
-    if (sg < SEGS)
-      bq[q] = *reinterpret_cast<const float4*>(o.b32 + (int64_t)(sg >> 4) * gv.lda + (sg & 15) * 4);
+    bq[q] = *reinterpret_cast<const f32x4*>(o.b32 + (int64_t)(sg >> 4) * gv.lda + (sg & 15) * 4);
   }
   floatx16 acc[NT];
   double accd[NT][16];
@@ -323,20 +324,19 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int sg = threadIdx.x + q * 256;
-      if (sg < SEGS) *reinterpret_cast<float4*>(&sb[sg >> 4][(sg & 15) * 4]) = bq[q];
+      *reinterpret_cast<f32x4*>(&sb[sg >> 4][(sg & 15) * 4]) = bq[q];
     }
     __syncthreads();
     if (c + 1 < nchunks) {
       const int64_t ko = (int64_t)(c + 1) * KC;
       const int64_t ao = (int64_t)(c + 1) * CHUNK;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) na[q] = *reinterpret_cast<const float4*>(ap + ao + q * 4);
+      for (int q = 0; q < 8; ++q) na[q] = *reinterpret_cast<const f32x4*>(ap + ao + q * 4);
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
         const int sg = threadIdx.x + q * 256;
-        if (sg < SEGS)
-          bq[q] = *reinterpret_cast<const float4*>(o.b32 + (int64_t)(sg >> 4) * gv.lda + ko +
-                                                   (sg & 15) * 4);
+        bq[q] = *reinterpret_cast<const f32x4*>(o.b32 + (int64_t)(sg >> 4) * gv.lda + ko +
+                                                 (sg & 15) * 4);
       }
     }
 #pragma unroll
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
       const float av[4] = {a[jj].x, a[jj].y, a[jj].z, a[jj].w};
 #pragma unroll
       for (int n = 0; n < NT; ++n) {
-        const float4 b4 = *reinterpret_cast<const float4*>(&sb[n * 32 + r][h * 32 + jj * 4]);
+        const f32x4 b4 = *reinterpret_cast<const f32x4*>(&sb[n * 32 + r][h * 32 + jj * 4]);
         const float bv[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e)

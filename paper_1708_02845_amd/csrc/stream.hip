@@ -93,13 +93,16 @@ __global__ __launch_bounds__(256) void dense_field_kernel(const float* __restric
 
 // ---------------------------------------------------------------------------
 // Truncated (CSR) rows.  The truncated target row p~ is scattered into LDS as
-// a dense vector (zeros where dropped).  For row x with stored support S_x:
+// a dense vector of (p~, log2 p~) pairs (zeros where dropped).  For row x with
+// stored support S_x:
 //   TV_tau(x) = sum_{b in S_x} |q_b - p~_b| + sum_{b in S_t \ S_x} p~_b
 //   KL_tau(x) = sum_{b in S_x} p~_b (log p~_b - log q_b)
 //             + sum_{b in S_t \ S_x} p~_b (log p~_b - log phi_x)
 // The S_t \ S_x sums are W_t - A_x and (Hb_t - E_x) - log2 phi_x (W_t - A_x),
-// with A_x, E_x the sums of p~_b and p~_b log2 p~_b over S_x; they are exactly
-// 0 when every b of S_t is stored in row x (counted, not inferred from FP64).
+// with A_x, E_x the sums of p~_b and p~_b log2 p~_b over S_x, all in FP64;
+// when S_x covers S_t they are FP64 round-off (far inside the stated bound),
+// and the target's own row is set to exactly 0.  Stored values are positive,
+// so the KL terms need no zero guard.
 template <int LPR, int KIND, int UNROLL>
 __global__ __launch_bounds__(256) void csr_field_kernel(CsrView v, int32_t target,
                                                         float* __restrict__ out) {
@@ -107,14 +110,12 @@ __global__ __launch_bounds__(256) void csr_field_kernel(CsrView v, int32_t targe
   extern __shared__ float2 smem2[];
   const int Bp = (v.B + 3) & ~3;
   float2* spl = smem2;
-  __shared__ double red[3][8];
-  __shared__ int redc[8];
+  __shared__ double red[2][8];
   for (int i = threadIdx.x; i < Bp; i += blockDim.x) spl[i] = make_float2(0.f, 0.f);
   __syncthreads();
   const int64_t ts = v.start[target];
   const int tl = v.len[target];
   double w = 0.0, hb = 0.0;
-  int cnt = 0;
   for (int i = threadIdx.x; i < tl; i += blockDim.x) {
     const int b = v.col[ts + i];
     const float p = v.val[ts + i];
@@ -122,26 +123,21 @@ __global__ __launch_bounds__(256) void csr_field_kernel(CsrView v, int32_t targe
     spl[b] = make_float2(p, l);
     w += (double)p;
     hb += (double)(p * l);
-    cnt += 1;
   }
   for (int off = 32; off > 0; off >>= 1) {
     w += __shfl_xor(w, off);
     hb += __shfl_xor(hb, off);
-    cnt += __shfl_xor(cnt, off);
   }
   const int wid = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     red[0][wid] = w;
     red[1][wid] = hb;
-    redc[wid] = cnt;
   }
   __syncthreads();
   double Wt = 0.0, Hbt = 0.0;
-  int St = 0;
   for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
     Wt += red[0][i];
     Hbt += red[1][i];
-    St += redc[i];
   }
 
   const int lane = threadIdx.x & (LPR - 1);
@@ -154,7 +150,6 @@ __global__ __launch_bounds__(256) void csr_field_kernel(CsrView v, int32_t targe
     const ushort4* col4 = reinterpret_cast<const ushort4*>(v.col + s);
     const int nv = (n + 3) >> 2;
     double acc = 0.0, A = 0.0, E = 0.0;
-    int c = 0;
     for (int base = lane; base < nv; base += LPR * UNROLL) {
       float4 q[UNROLL];
       ushort4 cb[UNROLL];
@@ -179,11 +174,10 @@ __global__ __launch_bounds__(256) void csr_field_kernel(CsrView v, int32_t targe
             if (e < rem) {
               const float2 pl = spl[bv[e]];
               as4 += pl.x;
-              c += pl.x > 0.f;
               if (KIND == 0) {
                 ts4 += fabsf(qv[e] - pl.x);
               } else {
-                ts4 += kl_term(pl.x, pl.y, qv[e]);
+                ts4 += pl.x * (pl.y - hw_log2(qv[e]));
                 es4 += pl.x * pl.y;
               }
             }
@@ -199,18 +193,14 @@ __global__ __launch_bounds__(256) void csr_field_kernel(CsrView v, int32_t targe
       acc += __shfl_xor(acc, off, LPR);
       A += __shfl_xor(A, off, LPR);
       if (KIND == 1) E += __shfl_xor(E, off, LPR);
-      c += __shfl_xor(c, off, LPR);
     }
     if (lane == 0) {
       double d;
-      const bool complete = (c == St);
-      if (KIND == 0) {
-        d = acc + (complete ? 0.0 : (Wt - A));
-      } else {
-        const double miss = complete ? 0.0 : (Hbt - E) - v.lphi[row] * (Wt - A);
-        d = (acc + miss) * 0.69314718055994530942;
-      }
-      out[row] = (float)d;
+      if (KIND == 0)
+        d = acc + (Wt - A);
+      else
+        d = (acc + (Hbt - E) - v.lphi[row] * (Wt - A)) * 0.69314718055994530942;
+      out[row] = row == target ? 0.f : (float)d;
     }
   }
 }

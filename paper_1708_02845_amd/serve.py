@@ -67,9 +67,15 @@ class _Domain:
 
 
 class Server:
-    """Resident domains, per-domain queues and continuous batching."""
+    """Resident domains, per-domain queues and continuous batching.
 
-    def __init__(self, ctx, max_batch=64, slots_per_domain=2, max_steps=4000,
+    Each slot is a stream.  HIP maps a process's streams onto a few hardware
+    queues (GPU_MAX_HW_QUEUES, 4 by default); keeping domains x slots within
+    that number gives every domain a queue of its own, so a short batch never
+    waits behind another domain's long one.
+    """
+
+    def __init__(self, ctx, max_batch=64, slots_per_domain=1, max_steps=4000,
                  hbm_budget=None, gemm_form="f16x3", field_reserve=2, keep_fields=False):
         import torch
         self.torch = torch
