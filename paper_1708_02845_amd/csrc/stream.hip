@@ -32,7 +32,7 @@ __device__ __forceinline__ float kl_term(float p, float lp, float q) {
 }
 
 template <int LPR, int KIND, int UNROLL>
-__global__ __launch_bounds__(256) void dense_field_kernel(const float* __restrict__ P, int64_t ld,
+__global__ __launch_bounds__(512) void dense_field_kernel(const float* __restrict__ P, int64_t ld,
                                                           int32_t N, int32_t target,
                                                           float* __restrict__ out) {
   extern __shared__ float4 smem4[];
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void dense_field_kernel(const float* __restric
 // and the target's own row is set to exactly 0.  Stored values are positive,
 // so the KL terms need no zero guard.
 template <int LPR, int KIND, int UNROLL>
-__global__ __launch_bounds__(256) void csr_field_kernel(CsrView v, int32_t target,
+__global__ __launch_bounds__(512) void csr_field_kernel(CsrView v, int32_t target,
                                                         float* __restrict__ out) {
   // LDS: the truncated target row as (p, log2 p) pairs, zeros where dropped
   extern __shared__ float2 smem2[];
@@ -223,6 +223,10 @@ static hipError_t allow_lds(K kern, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Large staged target rows limit the workgroups per CU (160 KB of LDS), so
+// those launches use 512-thread workgroups: twice the waves share one copy.
+static int block_threads(size_t lds) { return lds > 32 * 1024 ? 512 : 256; }
+
 static int grid_for(int64_t groups_needed, int gpb, size_t lds) {
   const int64_t need = (groups_needed + gpb - 1) / gpb;
   int per_cu = lds > 0 ? (int)((160 * 1024) / (lds + 1024)) : 8;
@@ -239,7 +243,7 @@ static hipError_t dense_launch(DenseView v, int32_t target, float* out, hipStrea
   const size_t lds = (size_t)v.ld * sizeof(float) * (KIND == 1 ? 2 : 1);
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
-  const int threads = 256;
+  const int threads = block_threads(lds);
   const int grid = grid_for(v.N, threads / LPR, lds);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v.P, v.ld, v.N, target, out);
   return hipGetLastError();
@@ -263,7 +267,7 @@ static hipError_t csr_launch(CsrView v, int32_t target, float* out, hipStream_t 
   const size_t lds = (size_t)((v.B + 3) & ~3) * sizeof(float) * 2;
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
-  const int threads = 256;
+  const int threads = block_threads(lds);
   const int grid = grid_for(v.N, threads / LPR, lds);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v, target, out);
   return hipGetLastError();
