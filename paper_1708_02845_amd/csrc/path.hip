@@ -111,28 +111,15 @@ __global__ __launch_bounds__(256) void neighbor_values_kernel(PathArgs a, int32_
   }
 }
 
-// Block-wide FP64 sum (all threads of the 256-thread block call it).
-__device__ double block_sum(double v, double* red) {
-  v = wsum(v);
-  const int wid = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
-  return s;
-}
-
-// FP64 distance of row x to the target, the whole block cooperating, from
-// the staged FP64 target row p, its logarithms lp and constants tc.  The KL
+// FP64 distance of row x to the target, computed by one wave, from the
+// staged FP64 target row p, its logarithms lp and constants tc.  The KL
 // terms are p (log p - log q).
 __device__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_csr, int kind,
-                                 const double* p, const double* lp, const double* tc, int x,
-                                 double* red) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+                                 const double* p, const double* lp, const double* tc, int x) {
+  const int lane = threadIdx.x & 63;
   if (!is_csr) {
     double acc = 0.0;
-    for (int b = tid; b < dv.B; b += nt) {
+    for (int b = lane; b < dv.B; b += 64) {
       const double q =
           dv.P64 ? dv.P64[(int64_t)x * dv.B + b] : (double)dv.P[(int64_t)x * dv.ld + b];
       const double pb = p[b];
@@ -142,12 +129,12 @@ __device__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_
         acc += pb * (lp[b] - log(q));
       }
     }
-    return block_sum(acc, red);
+    return wsum(acc);
   }
   const int64_t s = cv.start[x];
   const int n = cv.len[x];
   double acc = 0.0, A = 0.0, E = 0.0, c = 0.0;
-  for (int i = tid; i < n; i += nt) {
+  for (int i = lane; i < n; i += 64) {
     const double q = cv.val64 ? cv.val64[s + i] : (double)cv.val[s + i];
     const int b = cv.col[s + i];
     const double pb = p[b];
@@ -160,10 +147,10 @@ __device__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_
     }
     c += pb > 0.0 ? 1.0 : 0.0;
   }
-  acc = block_sum(acc, red);
-  A = block_sum(A, red);
-  E = block_sum(E, red);
-  c = block_sum(c, red);
+  acc = wsum(acc);
+  A = wsum(A);
+  E = wsum(E);
+  c = wsum(c);
   if (c == tc[2]) return acc;
   if (kind == 0) return acc + (tc[0] - A);
   return acc + (tc[1] - E) - log(cv.phi[x]) * (tc[0] - A);
@@ -178,16 +165,20 @@ __device__ __forceinline__ float unkey(uint32_t k) {
 }
 
 // One 256-thread block per path.  The walk itself is uniform: every wave
-// takes the same decisions from the same loads; the four waves only split
-// the FP64 re-decisions.  A step loads the padded neighbour row (ids and
+// takes the same decisions from the same loads; the four waves split the rows
+// of an FP64 re-decision between them (one row per wave).  A step loads the padded neighbour row (ids and
 // pre-gathered values) lane-parallel, moves it into scalar registers, and
 // takes the best and second-best neighbour on order-preserving integer keys
 // (ties: lowest id) with scalar instructions, so no cross-lane reduction
 // chain sits on the critical path.  Padding slots (-1) are trailing.
 __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, PathArgs a) {
-  __shared__ double red[4];
+  // rows of the current and the previous FP64 re-decision (at most W + 1 <= 65)
+  __shared__ int cur_x[65], prev_x[65];
+  __shared__ double cur_d[65], prev_d[65];
+  int prev_n = 0;
   const int i = blockIdx.x;
   const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   const int N = a.is_csr ? cv.N : dv.N;
   const int W = a.adj_w;
   const float* d = a.fields + (int64_t)i * N;
@@ -262,22 +253,58 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
     } else if (certain && v1 - e1 >= dvv + ev) {
       stuck = true;
     } else {
+      // FP64 re-decision.  Rows: the current vertex, then every neighbour that
+      // could be the minimum; wave (position % waves) computes each row, rows
+      // known from the previous re-decision are reused.
       ++rechecks;
-      const double dxv = exact_distance(dv, cv, a.is_csr, a.kind, p, lpt, tc, v, red);
+      const int nw = (int)(blockDim.x >> 6);
+      int pos = 0;
+      for (int j = -1; j < deg; ++j) {
+        int x;
+        if (j < 0) {
+          x = v;
+        } else {
+          x = __builtin_amdgcn_readlane(ul, j);
+          const double vj = (double)unkey((uint32_t)__builtin_amdgcn_readlane((int)kl, j));
+          if (vj - (ea + er * fabs(vj)) > v1 + e1) continue;   // certainly above the best
+        }
+        if (pos % nw == wave) {
+          double dx = 0.0;
+          bool have = false;
+          for (int q = 0; q < prev_n && !have; ++q)
+            if (prev_x[q] == x) {
+              dx = prev_d[q];
+              have = true;
+            }
+          if (!have) dx = exact_distance(dv, cv, a.is_csr, a.kind, p, lpt, tc, x);
+          if (lane == 0) {
+            cur_x[pos] = x;
+            cur_d[pos] = dx;
+          }
+        }
+        ++pos;
+      }
+      __syncthreads();
+      const double dxv = cur_d[0];
       double best = __builtin_inf();
       int best_u = 0x7fffffff;
-      for (int j = 0; j < deg; ++j) {
-        const int uj = __builtin_amdgcn_readlane(ul, j);
-        const double vj = (double)unkey((uint32_t)__builtin_amdgcn_readlane((int)kl, j));
-        if (vj - (ea + er * fabs(vj)) > v1 + e1) continue;   // certainly above the best
-        const double dx = exact_distance(dv, cv, a.is_csr, a.kind, p, lpt, tc, uj, red);
-        if (dx < best || (dx == best && uj < best_u)) {
+      for (int q = 1; q < pos; ++q) {
+        const double dx = cur_d[q];
+        const int cu = cur_x[q];
+        if (dx < best || (dx == best && cu < best_u)) {
           best = dx;
-          best_u = uj;
+          best_u = cu;
         }
       }
       next = best_u;
       stuck = !(best < dxv);
+      __syncthreads();   // everyone has read cur_* before it becomes prev_*
+      if (threadIdx.x < pos) {
+        prev_x[threadIdx.x] = cur_x[threadIdx.x];
+        prev_d[threadIdx.x] = cur_d[threadIdx.x];
+      }
+      prev_n = pos;   // uniform
+      __syncthreads();
     }
     if (stuck) {
       status = 1;
