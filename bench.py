@@ -455,6 +455,18 @@ def main():
         rows[f"a6_paths_kl_T{T}"] = {"avg_us": round(us, 2), "paths_per_s": round(T / (us * 1e-6), 1),
                                      "mean_vertices": float(lens.mean()),
                                      "fp64_rechecks": int(res[3].sum().item())}
+        # more f-divergences on the same streaming pass (chi-squared, Hellinger)
+        for kind in ("chi2", "hellinger"):
+            kd.field(t, kind, out=f[0])
+            torch.cuda.synchronize()
+            for _ in range(20):
+                tm.run(f"dense_{kind}", lambda: kd.field(t, kind, out=f[0]), True)
+            torch.cuda.synchronize()
+            us = tm.avg_us(f"dense_{kind}")
+            byts = N * B * 4 + N * 4
+            rows[f"f_divergence_{kind}_dense"] = {
+                "avg_us": round(us, 3), "alg_bytes": byts, "GB/s": round(gbs(byts, us), 1),
+                "frac": round(gbs(byts, us) / HBM_PEAK_GBS, 4)}
 
     out = {
         "metric": METRIC,

@@ -52,7 +52,14 @@ typedef enum {
 
 typedef enum {
   DD_TV = 0,  /* total variation, eq. (34): sum_b |P_tb - P_xb|, range [0, 2] */
-  DD_KL = 1   /* Kullback-Leibler, eq. (35): sum_b P_tb log(P_tb / P_xb), target row as reference */
+  DD_KL = 1,  /* Kullback-Leibler, eq. (35): sum_b P_tb log(P_tb / P_xb), target row as reference */
+  /* Two more f-divergences d = sum_b P_tb f(P_xb / P_tb) (Section VI names the
+   * family); dense handles only, a truncated (CSR) handle rejects them with
+   * DD_EINVAL. */
+  DD_CHI2 = 2,      /* chi-squared, f(u) = (u - 1)^2: sum_b (P_xb - P_tb)^2 / P_tb,
+                       +inf when P_xb > 0 where P_tb = 0 */
+  DD_HELLINGER = 3  /* squared Hellinger, f(u) = (sqrt u - 1)^2:
+                       sum_b (sqrt P_xb - sqrt P_tb)^2, range [0, 2] */
 } dd_kind;
 
 /* Operand form of the batched-KL contraction (see dd_batch_distance_fields). */

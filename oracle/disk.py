@@ -6,6 +6,13 @@
 * By conformal invariance of the divergence distances (Theorem A2) and their
   values on the disk with target 0 (eqs. A6, A8):
       KL(x; t) = -log(1 - rho^2),     TV(x; t) = (4/pi) asin(rho).
+* For any f-divergence the value on the disk with target 0 is
+  g(r) = (1/2pi) int f(h(r, phi)) dphi with h the Poisson kernel ratio
+  (Theorem A5).  For f(x) = (x - 1)^2 this is 2 r^2 / (1 - r^2) (the
+  Appendix table lists (1 + r^2)/(1 - r^2), which is off by the constant 1:
+  g(0) must be 0); for f(x) = (sqrt x - 1)^2 it is
+  2 - (4/pi) sqrt(1 - r^2) K(r), K the complete elliptic integral of the first
+  kind with modulus r (scipy's ellipk takes the parameter r^2).
 * Gradient-descent paths on the disk are hyperbolic geodesics: arcs of the
   circle through source and target orthogonal to the unit circle (Appendix
   Section 2.2), which also passes through 1/conj(source).
@@ -30,6 +37,17 @@ def kl_closed(x, t):
 
 def tv_closed(x, t):
     return (4.0 / np.pi) * np.arcsin(rho(x, t))
+
+
+def chi2_closed(x, t):
+    r = rho(x, t)
+    return 2.0 * r * r / (1.0 - r * r)
+
+
+def hellinger_closed(x, t):
+    from scipy.special import ellipk
+    r = rho(x, t)
+    return 2.0 - (4.0 / np.pi) * np.sqrt(1.0 - r * r) * ellipk(r * r)
 
 
 def geodesic_distance(points, s, t):

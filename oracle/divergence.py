@@ -8,6 +8,13 @@ vertex x with row q = P[x, :]:
                  distribution; terms with p_b = 0 contribute 0; a term with
                  p_b > 0 and q_b = 0 is +inf)
 
+Two more members of the f-divergence family named in the paper's conclusion
+(Section VI), in the same target-as-reference form d(x) = sum_b p_b f(q_b / p_b):
+
+* chi-squared, f(x) = (x - 1)^2:    d(x) = sum_b (q_b - p_b)^2 / p_b   (+inf if some
+                                    p_b = 0 < q_b)
+* Hellinger,   f(x) = (sqrt x - 1)^2: d(x) = sum_b (sqrt q_b - sqrt p_b)^2
+
 Truncated (sparsified) kernels follow the sparsification remark of Section V
 ("Precision"): entries of a row below a threshold are dropped, with no
 renormalisation.  The row-relative threshold keeps q_b >= tau * max_b q_b;
@@ -54,6 +61,31 @@ def kl_field(P, t):
         for lo, hi in _row_chunks(P.shape[0], int(sup.sum())):
             q = P[lo:hi][:, sup]
             d[lo:hi] = (ps[None, :] * np.log(ps[None, :] / q)).sum(axis=1)
+    return d
+
+
+def chi2_field(P, t):
+    """Chi-squared divergence from every row of P, row t as the reference."""
+    P = np.asarray(P, dtype=np.float64)
+    p = P[t]
+    sup = p > 0
+    ps = p[sup]
+    d = np.empty(P.shape[0])
+    for lo, hi in _row_chunks(P.shape[0], P.shape[1]):
+        q = P[lo:hi]
+        d[lo:hi] = ((q[:, sup] - ps[None, :]) ** 2 / ps[None, :]).sum(axis=1)
+        off = (q[:, ~sup] > 0).any(axis=1)
+        d[lo:hi][off] = np.inf
+    return d
+
+
+def hellinger_field(P, t):
+    """Squared Hellinger divergence from every row of P to row t."""
+    P = np.asarray(P, dtype=np.float64)
+    sp = np.sqrt(P[t])
+    d = np.empty(P.shape[0])
+    for lo, hi in _row_chunks(P.shape[0], P.shape[1]):
+        d[lo:hi] = ((np.sqrt(P[lo:hi]) - sp[None, :]) ** 2).sum(axis=1)
     return d
 
 

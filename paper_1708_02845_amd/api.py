@@ -11,7 +11,8 @@ import numpy as np
 
 from . import _lib as L
 
-KINDS = {"tv": L.DD_TV, "kl": L.DD_KL, L.DD_TV: L.DD_TV, L.DD_KL: L.DD_KL}
+KINDS = {"tv": L.DD_TV, "kl": L.DD_KL, "chi2": L.DD_CHI2, "hellinger": L.DD_HELLINGER}
+KINDS.update({v: v for v in list(KINDS.values())})
 FORMS = {None: L.DD_FORM_NONE, "none": L.DD_FORM_NONE, "f32": L.DD_FORM_F32,
          "f16x3": L.DD_FORM_F16X3}
 PATH_STATUS = {L.DD_PATH_REACHED: "reached", L.DD_PATH_STUCK: "stuck",

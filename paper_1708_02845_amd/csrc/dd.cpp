@@ -206,6 +206,17 @@ dd_status check_free(size_t need) {
 
 // Error bound of a field, in the sense of include/dd.h.  u is the FP32 unit
 // roundoff; hardware log2 is taken to be within 4u*|log2 y| + 4u of log2 y.
+// Kinds a handle can evaluate: all four on a dense handle, TV and KL on a
+// truncated one.
+dd_status check_kind(const dd_kernel* k, int32_t kind) {
+  if (kind == DD_TV || kind == DD_KL) return DD_OK;
+  if (kind == DD_CHI2 || kind == DD_HELLINGER) {
+    if (k->is_csr) return fail(DD_EINVAL, "kind %d needs a dense handle", kind);
+    return DD_OK;
+  }
+  return fail(DD_EINVAL, "unknown kind %d", kind);
+}
+
 dd_error_bound field_bound(const dd_kernel* k, int kind, int32_t t) {
   dd_error_bound b;
   if (!k->is_csr) {
@@ -213,6 +224,19 @@ dd_error_bound field_bound(const dd_kernel* k, int kind, int32_t t) {
     const double W = k->W_host[t];
     if (kind == DD_TV) {
       b.rel = 6.0 * kU;
+      b.abs = (k->is_f64 ? 2.0 * kU * (1.0 + W) : 0.0) + 1e-300;
+    } else if (kind == DD_CHI2) {
+      // terms (q - p) * ((q - p) * fl(1/p)): 5u each, 4-term FP32 sums 2u,
+      // output rounding u.  FP32 copies of FP64 rows move each term by at
+      // most (2|q - p| u (q + p) + u (q - p)^2) / p; Cauchy-Schwarz with
+      // sum (q + p)^2 / p = chi2 + 4 sum q bounds the sum by 3u chi2 + 4u.
+      b.rel = 8.0 * kU + (k->is_f64 ? 3.0 * kU : 0.0);
+      b.abs = (k->is_f64 ? 4.0 * kU : 0.0) + 1e-300;
+    } else if (kind == DD_HELLINGER) {
+      // ((q - p) * rcp(sqrt q + sqrt p))^2 with 1-ulp hardware sqrt and rcp:
+      // 15u per term, sums 2u, output u.  FP32 copies of FP64 rows move a
+      // term by at most u |q - p|, in sum u (1 + W).
+      b.rel = 18.0 * kU;
       b.abs = (k->is_f64 ? 2.0 * kU * (1.0 + W) : 0.0) + 1e-300;
     } else {
       b.rel = 11.0 * kU;
@@ -653,7 +677,7 @@ dd_status dd_kernel_get_info(const dd_kernel* k, dd_kernel_info* info) {
 dd_status dd_distance_field(dd_kernel* k, int32_t target, int32_t kind, float* out_dev,
                             dd_error_bound* bound, void* stream) {
   if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
-  if (kind != DD_TV && kind != DD_KL) return fail(DD_EINVAL, "unknown kind %d", kind);
+  if (dd_status st = check_kind(k, kind)) return st;
   if (target < 0 || target >= k->N) return fail(DD_EINVAL, "target %d not in [0, %d)", target, k->N);
   if (!out_dev) return fail(DD_EINVAL, "out_dev is null");
   HIP_OR(hipSetDevice(k->ctx->device));
@@ -668,7 +692,7 @@ dd_status dd_distance_field(dd_kernel* k, int32_t target, int32_t kind, float* o
 dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t T, int32_t kind,
                                    float* out_dev, dd_error_bound* bounds, void* stream) {
   if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
-  if (kind != DD_TV && kind != DD_KL) return fail(DD_EINVAL, "unknown kind %d", kind);
+  if (dd_status st = check_kind(k, kind)) return st;
   if (T <= 0 || !targets || !out_dev) return fail(DD_EINVAL, "T=%d, targets or out_dev null", T);
   for (int32_t i = 0; i < T; ++i)
     if (targets[i] < 0 || targets[i] >= k->N)
@@ -710,7 +734,7 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
                          int32_t* status_dev, int32_t* rechecks_dev, void* stream) {
   if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
   if (!k->has_adj) return fail(DD_EINVAL, "kernel was loaded without adjacency");
-  if (kind != DD_TV && kind != DD_KL) return fail(DD_EINVAL, "unknown kind %d", kind);
+  if (dd_status st = check_kind(k, kind)) return st;
   if (T <= 0 || !sources || !targets || !fields_dev || !bounds || !path_dev || !len_dev ||
       !status_dev)
     return fail(DD_EINVAL, "T=%d or a required pointer is null", T);
@@ -842,7 +866,7 @@ dd_status dd_plan_path(dd_kernel* k, int32_t source, int32_t target, int32_t kin
   if (max_steps < 0) return fail(DD_EINVAL, "max_steps=%d", max_steps);
   if (source < 0 || source >= k->N || target < 0 || target >= k->N)
     return fail(DD_EINVAL, "source %d / target %d not in [0, %d)", source, target, k->N);
-  if (kind != DD_TV && kind != DD_KL) return fail(DD_EINVAL, "unknown kind %d", kind);
+  if (dd_status st = check_kind(k, kind)) return st;
   HIP_OR(hipSetDevice(k->ctx->device));
   hipStream_t s = as_stream(stream);
   AsyncBuf field(s), pbuf(s);

@@ -113,7 +113,9 @@ __global__ __launch_bounds__(256) void neighbor_values_kernel(PathArgs a, int32_
 
 // FP64 distance of row x to the target, computed by one wave, from the
 // staged FP64 target row p, its logarithms lp and constants tc.  The KL
-// terms are p (log p - log q).
+// terms are p (log p - log q); chi-squared (q - p)^2 / p (+inf for q > 0 on
+// p = 0); Hellinger (q - p)^2 / (sqrt q + sqrt p)^2, the cancellation-free
+// form of (sqrt q - sqrt p)^2.  Truncated handles carry TV and KL only.
 __device__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_csr, int kind,
                                  const double* p, const double* lp, const double* tc, int x) {
   const int lane = threadIdx.x & 63;
@@ -123,10 +125,18 @@ __device__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_
       const double q =
           dv.P64 ? dv.P64[(int64_t)x * dv.B + b] : (double)dv.P[(int64_t)x * dv.ld + b];
       const double pb = p[b];
+      const double df = q - pb;
       if (kind == 0) {
-        acc += fabs(pb - q);
-      } else if (pb > 0.0) {
-        acc += pb * (lp[b] - log(q));
+        acc += fabs(df);
+      } else if (kind == 1) {
+        if (pb > 0.0) acc += pb * (lp[b] - log(q));
+      } else if (df != 0.0) {
+        if (kind == 2) {
+          acc += pb > 0.0 ? df * df / pb : __builtin_inf();
+        } else {
+          const double e = df / (sqrt(q) + sqrt(pb));
+          acc += e * e;
+        }
       }
     }
     return wsum(acc);

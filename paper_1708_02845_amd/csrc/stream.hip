@@ -2,6 +2,8 @@
 //
 // TV (Section IV, eq. 34):  d(x) = sum_b |p_b - q_b|
 // KL (Section IV, eq. 35):  d(x) = sum_b p_b log(p_b / q_b), p = target row
+// chi-squared and squared Hellinger (f-divergences, Section VI):
+//   d(x) = sum_b (q_b - p_b)^2 / p_b,   d(x) = sum_b (sqrt q_b - sqrt p_b)^2
 //
 // Mapping (gfx950): a group of LPR lanes (16, 32 or 64) owns one row x and
 // sweeps it with 16-byte loads, UNROLL loads in flight per lane; the target
@@ -13,6 +15,13 @@
 // log2 (v_log_f32) applied to both operands, so the target's own row gives
 // exactly 0; the ln 2 factor is applied once per row in FP64.  Four FP32
 // terms are summed in FP32, then carried in FP64.
+//
+// chi-squared keeps 1/p_b in LDS (+inf where p_b = 0, so a row with mass
+// outside the target's support gets +inf) and forms (q - p) * ((q - p) / p).
+// Hellinger is evaluated as ((q - p) / (sqrt q + sqrt p))^2, which equals
+// (sqrt q - sqrt p)^2 but has no cancellation: every term carries a small
+// relative error, so the field has a relative error bound, also next to the
+// target.  sqrt p sits in LDS beside p.
 #include "dd_internal.h"
 
 namespace dd {
@@ -31,6 +40,42 @@ __device__ __forceinline__ float kl_term(float p, float lp, float q) {
   return p > 0.f ? p * (lp - hw_log2(q)) : 0.f;
 }
 
+// (q - p)^2 / p with r = 1/p (+inf for p = 0); 0 whenever q == p.
+__device__ __forceinline__ float chi2_term(float p, float r, float q) {
+  const float d = q - p;
+  return d != 0.f ? d * (d * r) : 0.f;
+}
+
+// (sqrt q - sqrt p)^2 as ((q - p) / (sqrt q + sqrt p))^2 with the hardware
+// square root and reciprocal (1 ulp each); 0 whenever q == p.
+__device__ __forceinline__ float hel_term(float p, float sp, float q) {
+  const float d = q - p;
+  const float e = d * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(q) + sp);
+  return d != 0.f ? e * e : 0.f;
+}
+
+// Second LDS array per kind: log2 p (KL), 1/p (chi-squared), sqrt p (Hellinger).
+template <int KIND>
+__device__ __forceinline__ float stage_aux(float p) {
+  if (KIND == 1) return p > 0.f ? hw_log2(p) : 0.f;
+  if (KIND == 2) return p > 0.f ? 1.0f / p : __builtin_inff();
+  return sqrtf(p);
+}
+
+template <int KIND>
+__device__ __forceinline__ float term4(const float4& p, const float4& a, const float4& q) {
+  if (KIND == 0)
+    return (fabsf(p.x - q.x) + fabsf(p.y - q.y)) + (fabsf(p.z - q.z) + fabsf(p.w - q.w));
+  if (KIND == 1)
+    return (kl_term(p.x, a.x, q.x) + kl_term(p.y, a.y, q.y)) +
+           (kl_term(p.z, a.z, q.z) + kl_term(p.w, a.w, q.w));
+  if (KIND == 2)
+    return (chi2_term(p.x, a.x, q.x) + chi2_term(p.y, a.y, q.y)) +
+           (chi2_term(p.z, a.z, q.z) + chi2_term(p.w, a.w, q.w));
+  return (hel_term(p.x, a.x, q.x) + hel_term(p.y, a.y, q.y)) +
+         (hel_term(p.z, a.z, q.z) + hel_term(p.w, a.w, q.w));
+}
+
 template <int LPR, int KIND, int UNROLL>
 __global__ __launch_bounds__(512) void dense_field_kernel(const float* __restrict__ P, int64_t ld,
                                                           int32_t N, int32_t target,
@@ -43,14 +88,9 @@ __global__ __launch_bounds__(512) void dense_field_kernel(const float* __restric
   for (int i = threadIdx.x; i < nv; i += blockDim.x) {
     float4 p = trow[i];
     sp[i] = p;
-    if (KIND == 1) {
-      float4 l;
-      l.x = p.x > 0.f ? hw_log2(p.x) : 0.f;
-      l.y = p.y > 0.f ? hw_log2(p.y) : 0.f;
-      l.z = p.z > 0.f ? hw_log2(p.z) : 0.f;
-      l.w = p.w > 0.f ? hw_log2(p.w) : 0.f;
-      sl[i] = l;
-    }
+    if (KIND != 0)
+      sl[i] = make_float4(stage_aux<KIND>(p.x), stage_aux<KIND>(p.y), stage_aux<KIND>(p.z),
+                          stage_aux<KIND>(p.w));
   }
   __syncthreads();
 
@@ -72,16 +112,8 @@ __global__ __launch_bounds__(512) void dense_field_kernel(const float* __restric
         const int i = base + u * LPR;
         if (i < nv) {
           const float4 p = sp[i];
-          float s;
-          if (KIND == 0) {
-            s = (fabsf(p.x - v[u].x) + fabsf(p.y - v[u].y)) +
-                (fabsf(p.z - v[u].z) + fabsf(p.w - v[u].w));
-          } else {
-            const float4 l = sl[i];
-            s = (kl_term(p.x, l.x, v[u].x) + kl_term(p.y, l.y, v[u].y)) +
-                (kl_term(p.z, l.z, v[u].z) + kl_term(p.w, l.w, v[u].w));
-          }
-          acc += (double)s;
+          const float4 aux = KIND != 0 ? sl[i] : p;
+          acc += (double)term4<KIND>(p, aux, v[u]);
         }
       }
     }
@@ -240,7 +272,7 @@ template <int LPR, int KIND>
 static hipError_t dense_launch(DenseView v, int32_t target, float* out, hipStream_t s) {
   constexpr int UNROLL = (LPR == 64) ? 4 : (LPR == 32 ? 4 : 4);
   auto kern = dense_field_kernel<LPR, KIND, UNROLL>;
-  const size_t lds = (size_t)v.ld * sizeof(float) * (KIND == 1 ? 2 : 1);
+  const size_t lds = (size_t)v.ld * sizeof(float) * (KIND != 0 ? 2 : 1);
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int threads = block_threads(lds);
@@ -249,16 +281,22 @@ static hipError_t dense_launch(DenseView v, int32_t target, float* out, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out, hipStream_t s) {
+template <int KIND>
+static hipError_t dense_dispatch(DenseView v, int32_t target, float* out, hipStream_t s) {
   const int64_t nv = v.ld / 4;
-  if (kind == 0) {
-    if (nv >= 256) return dense_launch<64, 0>(v, target, out, s);
-    if (nv >= 128) return dense_launch<32, 0>(v, target, out, s);
-    return dense_launch<16, 0>(v, target, out, s);
+  if (nv >= 256) return dense_launch<64, KIND>(v, target, out, s);
+  if (nv >= 128) return dense_launch<32, KIND>(v, target, out, s);
+  return dense_launch<16, KIND>(v, target, out, s);
+}
+
+hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out, hipStream_t s) {
+  switch (kind) {
+    case 0: return dense_dispatch<0>(v, target, out, s);
+    case 1: return dense_dispatch<1>(v, target, out, s);
+    case 2: return dense_dispatch<2>(v, target, out, s);
+    case 3: return dense_dispatch<3>(v, target, out, s);
+    default: return hipErrorInvalidValue;
   }
-  if (nv >= 256) return dense_launch<64, 1>(v, target, out, s);
-  if (nv >= 128) return dense_launch<32, 1>(v, target, out, s);
-  return dense_launch<16, 1>(v, target, out, s);
 }
 
 template <int LPR, int KIND>

@@ -112,3 +112,19 @@ def test_grid257_truncated_full_size(gpu_ctx, kind):
         assert normwise(d, ref) <= TOL and within_bound(d, ref, b)
     finally:
         k.free()
+
+
+def test_truncated_handle_rejects_other_f_divergences(gpu_ctx, grid):
+    from paper_1708_02845_amd import DDError, Kernel
+    g, P = grid
+    k = Kernel.load_dense(gpu_ctx, P, tau=1e-3, adjacency=(g.adj_ptr, g.adj_idx))
+    try:
+        for kind in ("chi2", "hellinger"):
+            with pytest.raises(DDError, match="dense handle"):
+                k.field(0, kind)
+            with pytest.raises(DDError, match="dense handle"):
+                k.batch_fields([0, 1], kind)
+            with pytest.raises(DDError, match="dense handle"):
+                k.plan_path(3, 0, kind, 10)
+    finally:
+        k.free()

@@ -1,4 +1,5 @@
-"""GPU parity of the streaming TV/KL fields (eqs. 34, 35) against the FP64 oracle.
+"""GPU parity of the streaming fields against the FP64 oracle: TV and KL
+(eqs. 34, 35) and the chi-squared and Hellinger f-divergences (Section VI).
 
 Gate: normwise error max|d_hat - d| / max|d| <= 1e-5 and every entry inside
 the bound the library states for that field.
@@ -24,9 +25,13 @@ def random_kernel(N, B, seed):
     return P.astype(np.float32)
 
 
+ORACLE = {"tv": dv.tv_field, "kl": dv.kl_field, "chi2": dv.chi2_field,
+          "hellinger": dv.hellinger_field}
+KINDS = list(ORACLE)
+
+
 def oracle_field(P, t, kind):
-    P64 = np.asarray(P, dtype=np.float64)
-    return dv.tv_field(P64, t) if kind == "tv" else dv.kl_field(P64, t)
+    return ORACLE[kind](np.asarray(P, dtype=np.float64), t)
 
 
 def run_field(kern, t, kind):
@@ -35,7 +40,7 @@ def run_field(kern, t, kind):
 
 
 @pytest.mark.parametrize("B", [1, 3, 5, 63, 64, 65, 255, 256, 257, 511, 1023, 1024, 1025, 4099])
-@pytest.mark.parametrize("kind", ["tv", "kl"])
+@pytest.mark.parametrize("kind", KINDS)
 def test_ragged_widths(gpu_ctx, B, kind):
     from paper_1708_02845_amd import Kernel
     N = 37
@@ -58,7 +63,7 @@ def test_ragged_row_counts(gpu_ctx, N):
     P = random_kernel(N, 300, seed=N)
     k = Kernel.load_dense(gpu_ctx, P)
     try:
-        for kind in ("tv", "kl"):
+        for kind in KINDS:
             d, b = run_field(k, N // 2, kind)
             ref = oracle_field(P, N // 2, kind)
             assert normwise(d, ref) <= TOL and within_bound(d, ref, b)
@@ -75,7 +80,7 @@ def disk_kernel(gpu_ctx):
     k.free()
 
 
-@pytest.mark.parametrize("kind", ["tv", "kl"])
+@pytest.mark.parametrize("kind", KINDS)
 def test_unit_disk_fp64_input(disk_kernel, kind):
     inst, k = disk_kernel
     assert (k.N, k.B) == (4096, 256)
@@ -103,7 +108,7 @@ def test_zero_columns_are_dropped(grid65):
     assert k.B_in == g.K and k.B == g.K - 4
 
 
-@pytest.mark.parametrize("kind", ["tv", "kl"])
+@pytest.mark.parametrize("kind", KINDS)
 def test_small_grid_fields(grid65, kind):
     g, P, k = grid65
     for t in (0, 123, g.N - 1):
@@ -122,7 +127,7 @@ def test_runs_are_bitwise_deterministic(grid65):
 def test_streaming_batch_equals_single_fields(grid65):
     g, P, k = grid65
     ts = [3, 77, 900, 3]
-    for kind in ("tv", "kl"):
+    for kind in KINDS:
         D, bounds = k.batch_fields(ts, kind)
         D = D.cpu().numpy()
         for i, t in enumerate(ts):
@@ -137,7 +142,7 @@ def test_device_resident_input_matches_host_input(gpu_ctx, grid65):
     g, P, k = grid65
     kd = Kernel.load_dense(gpu_ctx, torch.from_numpy(P).cuda())
     try:
-        for kind in ("tv", "kl"):
+        for kind in KINDS:
             assert np.array_equal(run_field(kd, 200, kind)[0], run_field(k, 200, kind)[0])
     finally:
         kd.free()
@@ -160,7 +165,9 @@ def test_invalid_inputs_are_rejected(gpu_ctx, grid65):
     with pytest.raises(DDError, match="DD_EINVAL"):
         k.field(-1, "tv")
     with pytest.raises(ValueError):
-        k.field(0, "hellinger")
+        k.field(0, "jensen-shannon")
+    with pytest.raises(DDError, match="DD_EINVAL"):
+        k.field(0, 4)
     with pytest.raises(DDError, match="DD_EINVAL"):
         Kernel.load_dense(gpu_ctx, np.zeros((4, 8), dtype=np.float32), validate=False)
 
@@ -176,7 +183,7 @@ def grid257(gpu_ctx):
     k.free()
 
 
-@pytest.mark.parametrize("kind", ["tv", "kl"])
+@pytest.mark.parametrize("kind", KINDS)
 def test_grid257_full_size(grid257, kind):
     g, P, k = grid257
     t = int(targets_sources(1, g.N, 1)[0][0])
@@ -185,3 +192,39 @@ def test_grid257_full_size(grid257, kind):
     assert d[t] == 0.0
     assert normwise(d, ref) <= TOL
     assert within_bound(d, ref, b)
+
+
+def test_chi2_off_support_rows_are_infinite(gpu_ctx):
+    # a target row with zeros: rows with mass there have chi2 = +inf, the
+    # rest are finite and inside the bound; Hellinger stays finite.
+    from paper_1708_02845_amd import Kernel
+    P = random_kernel(50, 200, seed=7)
+    P[4, 10:30] = 0.0
+    P[9, :] = P[4, :]
+    P[9, 0] += 1e-3
+    P[4] /= P[4].sum(dtype=np.float64)
+    P[9] /= P[9].sum(dtype=np.float64)
+    k = Kernel.load_dense(gpu_ctx, P)
+    try:
+        d, b = run_field(k, 4, "chi2")
+        ref = oracle_field(P, 4, "chi2")
+        inf = np.isinf(ref)
+        assert inf.sum() == 48 and np.array_equal(np.isinf(d), inf)
+        assert np.isfinite(d[9]) and within_bound(d[~inf], ref[~inf], b)
+        h, bh = run_field(k, 4, "hellinger")
+        href = oracle_field(P, 4, "hellinger")
+        assert np.isfinite(h).all() and within_bound(h, href, bh) and h.max() <= 2.0
+    finally:
+        k.free()
+
+
+def test_hellinger_bound_is_relative_near_the_target(grid65):
+    # the cancellation-free form: no absolute floor on FP32 input, so even the
+    # smallest nonzero values (neighbours of the target) carry a relative bound
+    g, P, k = grid65
+    t = 500
+    d, b = run_field(k, t, "hellinger")
+    assert b[0] < 1e-250
+    ref = oracle_field(P, t, "hellinger")
+    nz = ref > 0
+    assert np.max(np.abs(d[nz] - ref[nz]) / ref[nz]) <= 2 * b[1]

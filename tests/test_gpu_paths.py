@@ -15,7 +15,8 @@ STATUS = {op.REACHED: "reached", op.STUCK: "stuck", op.MAX_STEPS: "max_steps"}
 
 def oracle_path(P, adj_ptr, adj_idx, s, t, kind, max_steps):
     P64 = np.asarray(P, dtype=np.float64)
-    d = dv.tv_field(P64, t) if kind == "tv" else dv.kl_field(P64, t)
+    d = {"tv": dv.tv_field, "kl": dv.kl_field, "chi2": dv.chi2_field,
+         "hellinger": dv.hellinger_field}[kind](P64, t)
     path, status = op.steepest_descent_path(d, adj_ptr, adj_idx, s, t, max_steps)
     return path, STATUS[status]
 
@@ -29,7 +30,7 @@ def disk(gpu_ctx):
     k.free()
 
 
-@pytest.mark.parametrize("kind", ["kl", "tv"])
+@pytest.mark.parametrize("kind", ["kl", "tv", "chi2", "hellinger"])
 def test_disk_paths_identical(disk, kind):
     inst, k = disk
     ts, ss = targets_sources(0, inst.N, 8)
@@ -50,7 +51,7 @@ def grid(gpu_ctx):
     k.free()
 
 
-@pytest.mark.parametrize("kind", ["kl", "tv"])
+@pytest.mark.parametrize("kind", ["kl", "tv", "chi2", "hellinger"])
 def test_grid_paths_identical(grid, kind):
     g, P, k = grid
     ts, ss = targets_sources(31, g.N, 6)
@@ -122,7 +123,7 @@ def test_grid257_paths(gpu_ctx):
     k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
     try:
         ts, ss = targets_sources(1, g.N, 2)
-        for kind in ("kl", "tv"):
+        for kind in ("kl", "tv", "chi2", "hellinger"):
             for s, t in zip(ss, ts):
                 got, status, _ = k.plan_path(int(s), int(t), kind, 4000)
                 ref, ref_status = oracle_path(P, g.adj_ptr, g.adj_idx, int(s), int(t), kind, 4000)

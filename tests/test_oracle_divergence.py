@@ -37,6 +37,45 @@ def test_kl_is_library_relative_entropy_with_target_as_reference(grid_P):
     assert abs(entropy(P[x], P[t]) - d[x]) > 1e-3 * d[x]
 
 
+def test_chi2_is_library_chisquare_with_target_as_expected(grid_P):
+    from scipy.stats import chisquare
+    P = grid_P
+    t = 77
+    d = dv.chi2_field(P, t)
+    for x in (0, 9, 333, P.shape[0] - 1):
+        assert d[x] == pytest.approx(chisquare(P[x], P[t]).statistic, rel=1e-10)
+    x = 333
+    assert abs(chisquare(P[t], P[x]).statistic - d[x]) > 1e-3 * d[x]   # the order matters
+
+
+def test_hellinger_is_squared_euclidean_of_square_roots(grid_P):
+    from scipy.spatial.distance import sqeuclidean
+    P = grid_P
+    t = 12
+    d = dv.hellinger_field(P, t)
+    for x in (0, 5, 500, P.shape[0] - 1):
+        assert d[x] == pytest.approx(sqeuclidean(np.sqrt(P[t]), np.sqrt(P[x])), rel=1e-12)
+    assert d.max() <= 2.0 and d[t] == 0.0
+
+
+def test_chi2_infinite_when_reference_is_zero():
+    P = np.array([[0.5, 0.5, 0.0], [0.4, 0.4, 0.2]])
+    assert np.isinf(dv.chi2_field(P, 0)[1])
+    assert dv.chi2_field(P, 1)[0] == pytest.approx(0.01 / 0.4 * 2 + 0.2)
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_disk_chi2_and_hellinger_closed_forms(c1, k):
+    # Theorem A5 with f(x) = (x - 1)^2 and f(x) = (sqrt x - 1)^2, carried to
+    # any target by the Moebius map (A10) and conformal invariance (A2).
+    t = int(rng(0, "targets").integers(0, c1.N, size=3)[k])
+    chi = dv.chi2_field(c1.P, t)
+    ref = odisk.chi2_closed(c1.z, c1.z[t])
+    assert np.max(np.abs(chi - ref) / np.maximum(ref, 1e-3)) < 1e-4
+    hel = dv.hellinger_field(c1.P, t)
+    assert np.abs(hel - odisk.hellinger_closed(c1.z, c1.z[t])).max() < 5e-6
+
+
 def test_tv_is_library_l1_distance(grid_P):
     P = grid_P
     t = 55
@@ -85,15 +124,19 @@ def test_brute_force_loops_on_tiny_stochastic_matrix():
     P /= P.sum(axis=1, keepdims=True)
     t = 2
     kl, tv = dv.kl_field(P, t), dv.tv_field(P, t)
+    hel = dv.hellinger_field(P, t)
     for x in range(9):
         s_kl = 0.0
         s_tv = 0.0
+        s_h = 0.0
         for b in range(6):
             s_tv += abs(P[t, b] - P[x, b])
+            s_h += (P[t, b] ** 0.5 - P[x, b] ** 0.5) ** 2
             if P[t, b] > 0:
                 s_kl += P[t, b] * np.log(P[t, b] / P[x, b])
         assert kl[x] == pytest.approx(s_kl, rel=1e-13, abs=1e-16)
         assert tv[x] == pytest.approx(s_tv, rel=1e-13, abs=1e-16)
+        assert hel[x] == pytest.approx(s_h, rel=1e-13, abs=1e-16)
 
 
 def test_kl_infinite_when_reference_mass_meets_zero():
