@@ -204,8 +204,6 @@ dd_status check_free(size_t need) {
   return DD_OK;
 }
 
-// Error bound of a field, in the sense of include/dd.h.  u is the FP32 unit
-// roundoff; hardware log2 is taken to be within 4u*|log2 y| + 4u of log2 y.
 // Kinds a handle can evaluate: all four on a dense handle, TV and KL on a
 // truncated one.
 dd_status check_kind(const dd_kernel* k, int32_t kind) {
@@ -217,6 +215,8 @@ dd_status check_kind(const dd_kernel* k, int32_t kind) {
   return fail(DD_EINVAL, "unknown kind %d", kind);
 }
 
+// Error bound of a field, in the sense of include/dd.h.  u is the FP32 unit
+// roundoff; hardware log2 is taken to be within 4u*|log2 y| + 4u of log2 y.
 dd_error_bound field_bound(const dd_kernel* k, int kind, int32_t t) {
   dd_error_bound b;
   if (!k->is_csr) {

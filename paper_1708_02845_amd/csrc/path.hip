@@ -116,46 +116,70 @@ __global__ __launch_bounds__(256) void neighbor_values_kernel(PathArgs a, int32_
 // terms are p (log p - log q); chi-squared (q - p)^2 / p (+inf for q > 0 on
 // p = 0); Hellinger (q - p)^2 / (sqrt q + sqrt p)^2, the cancellation-free
 // form of (sqrt q - sqrt p)^2.  Truncated handles carry TV and KL only.
-__device__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_csr, int kind,
+__device__ __forceinline__ double term64(int kind, double pb, double lpb, double q) {
+  const double df = q - pb;
+  if (kind == 0) return fabs(df);
+  if (kind == 1) return pb > 0.0 ? pb * (lpb - log(q)) : 0.0;
+  if (df == 0.0) return 0.0;
+  if (kind == 2) return pb > 0.0 ? df * df / pb : __builtin_inf();
+  const double e = df / (sqrt(q) + sqrt(pb));
+  return e * e;
+}
+
+// Loads are issued kU at a time per lane (indices clamped into the row, the
+// clamped slots are not summed), so a row costs a few memory round trips
+// rather than one per 64 entries.
+__device__ __noinline__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_csr, int kind,
                                  const double* p, const double* lp, const double* tc, int x) {
+  constexpr int kU = 8;
   const int lane = threadIdx.x & 63;
   if (!is_csr) {
     double acc = 0.0;
-    for (int b = lane; b < dv.B; b += 64) {
-      const double q =
-          dv.P64 ? dv.P64[(int64_t)x * dv.B + b] : (double)dv.P[(int64_t)x * dv.ld + b];
-      const double pb = p[b];
-      const double df = q - pb;
-      if (kind == 0) {
-        acc += fabs(df);
-      } else if (kind == 1) {
-        if (pb > 0.0) acc += pb * (lp[b] - log(q));
-      } else if (df != 0.0) {
-        if (kind == 2) {
-          acc += pb > 0.0 ? df * df / pb : __builtin_inf();
-        } else {
-          const double e = df / (sqrt(q) + sqrt(pb));
-          acc += e * e;
-        }
+    const bool f64 = dv.P64 != nullptr;
+    const double* q64 = dv.P64 + (int64_t)x * dv.B;
+    const float* q32 = dv.P + (int64_t)x * dv.ld;
+    for (int b0 = lane; b0 < dv.B; b0 += 64 * kU) {
+      double q[kU], pb[kU], lpb[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int b = b0 + 64 * u < dv.B ? b0 + 64 * u : 0;
+        q[u] = f64 ? q64[b] : (double)q32[b];
+        pb[u] = p[b];
+        lpb[u] = lp[b];
       }
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (b0 + 64 * u < dv.B) acc += term64(kind, pb[u], lpb[u], q[u]);
     }
     return wsum(acc);
   }
   const int64_t s = cv.start[x];
   const int n = cv.len[x];
   double acc = 0.0, A = 0.0, E = 0.0, c = 0.0;
-  for (int i = lane; i < n; i += 64) {
-    const double q = cv.val64 ? cv.val64[s + i] : (double)cv.val[s + i];
-    const int b = cv.col[s + i];
-    const double pb = p[b];
-    A += pb;
-    if (kind == 0) {
-      acc += fabs(q - pb);
-    } else if (pb > 0.0) {
-      acc += pb * (lp[b] - log(q));
-      E += pb * lp[b];
+  for (int i0 = lane; i0 < n; i0 += 64 * kU) {
+    double q[kU];
+    int col[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t e = s + (i0 + 64 * u < n ? i0 + 64 * u : 0);
+      q[u] = cv.val64 ? cv.val64[e] : (double)cv.val[e];
+      col[u] = cv.col[e];
     }
-    c += pb > 0.0 ? 1.0 : 0.0;
+    double pb[kU], lpb[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      pb[u] = p[col[u]];
+      lpb[u] = lp[col[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (i0 + 64 * u < n) {
+        A += pb[u];
+        acc += term64(kind, pb[u], lpb[u], q[u]);
+        if (kind == 1 && pb[u] > 0.0) E += pb[u] * lpb[u];
+        c += pb[u] > 0.0 ? 1.0 : 0.0;
+      }
+    }
   }
   acc = wsum(acc);
   A = wsum(A);
@@ -164,6 +188,31 @@ __device__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_
   if (c == tc[2]) return acc;
   if (kind == 0) return acc + (tc[0] - A);
   return acc + (tc[1] - E) - log(cv.phi[x]) * (tc[0] - A);
+}
+
+__device__ __forceinline__ double uniform(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Minimum of a 32-bit key over lanes [0, W) of the wave (W <= 64), uniform.
+// Lanes at or above W must hold 0xffffffff.  Within each row of 16 lanes a
+// butterfly of DPP moves (swap neighbours, swap pairs, mirror halves, mirror
+// the row) leaves the row minimum in every lane; rows are then combined.
+__device__ __forceinline__ uint32_t wave_min(uint32_t x, int W) {
+  x = min(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false));
+  x = min(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false));
+  x = min(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false));
+  x = min(x, (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, false));
+  uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)x, 0);
+  if (W > 16) m = min(m, (uint32_t)__builtin_amdgcn_readlane((int)x, 16));
+  if (W > 32) {
+    m = min(m, (uint32_t)__builtin_amdgcn_readlane((int)x, 32));
+    m = min(m, (uint32_t)__builtin_amdgcn_readlane((int)x, 48));
+  }
+  return m;
 }
 
 // Order-preserving map of a float to an unsigned key (for any non-NaN value).
@@ -176,11 +225,12 @@ __device__ __forceinline__ float unkey(uint32_t k) {
 
 // One 256-thread block per path.  The walk itself is uniform: every wave
 // takes the same decisions from the same loads; the four waves split the rows
-// of an FP64 re-decision between them (one row per wave).  A step loads the padded neighbour row (ids and
-// pre-gathered values) lane-parallel, moves it into scalar registers, and
-// takes the best and second-best neighbour on order-preserving integer keys
-// (ties: lowest id) with scalar instructions, so no cross-lane reduction
-// chain sits on the critical path.  Padding slots (-1) are trailing.
+// of an FP64 re-decision between them (one row per wave).  A step loads the
+// padded neighbour row (ids and pre-gathered values), one slot per lane, then
+// takes the best neighbour as a DPP minimum over order-preserving integer keys
+// (ties: lowest id) and the set of neighbours that could still be the minimum
+// as one ballot: a few dozen instructions between the loads of consecutive
+// steps.
 __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, PathArgs a) {
   // rows of the current and the previous FP64 re-decision (at most W + 1 <= 65)
   __shared__ int cur_x[65], prev_x[65];
@@ -188,19 +238,20 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
   int prev_n = 0;
   const int i = blockIdx.x;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int N = a.is_csr ? cv.N : dv.N;
   const int W = a.adj_w;
   const float* d = a.fields + (int64_t)i * N;
   const float* nvi = a.nv + (int64_t)i * N * W;
   const Bound bnd = path_bound(a, i);
-  const double ea = bnd.abs, er = bnd.rel;
+  const double ea = uniform(bnd.abs), er = uniform(bnd.rel);
   const int Bt = a.is_csr ? cv.B : dv.B;
   const double* p = a.trow + (int64_t)i * Bt;
   const double* lpt = a.tlog + (int64_t)i * Bt;
   const double* tc = a.tconst + (int64_t)i * 4;
   int32_t* path = a.path + (int64_t)i * (a.max_steps + 1);
-  const int t = path_target(a, i);
+  const int t = __builtin_amdgcn_readfirstlane(path_target(a, i));
+  const int32_t* __restrict__ adj = a.adj;
   int v = path_source(a, i);
   float cur = d[v];   // FP32 field value at v
   int len = 1;
@@ -208,6 +259,10 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
   int rechecks = 0;
   if (threadIdx.x == 0) path[0] = v;
   for (;;) {
+    // the walk state is wave-uniform; say so, so that its branches are scalar
+    v = __builtin_amdgcn_readfirstlane(v);
+    len = __builtin_amdgcn_readfirstlane(len);
+    cur = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cur)));
     if (v == t) {
       status = 0;
       break;
@@ -219,64 +274,54 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
     int ul = -1;
     float vl = __builtin_inff();
     if (lane < W) {
-      ul = a.adj[(int64_t)v * W + lane];
+      ul = adj[(int64_t)v * W + lane];
       vl = nvi[(int64_t)v * W + lane];
     }
-    const uint32_t kl = fkey(__float_as_uint(vl));
-    // best (k1, u1) and second best (k2, u2) in scalar registers
-    uint32_t k1 = 0xffffffffu, k2 = 0xffffffffu;
-    int u1 = 0x7fffffff, u2 = 0x7fffffff;
-    int deg = 0;
-    for (int j = 0; j < W; ++j) {
-      const int uj = __builtin_amdgcn_readlane(ul, j);
-      if (uj < 0) break;
-      const uint32_t kj = (uint32_t)__builtin_amdgcn_readlane((int)kl, j);
-      ++deg;
-      if (kj < k1 || (kj == k1 && uj < u1)) {
-        k2 = k1;
-        u2 = u1;
-        k1 = kj;
-        u1 = uj;
-      } else if (kj < k2 || (kj == k2 && uj < u2)) {
-        k2 = kj;
-        u2 = uj;
-      }
-    }
-    if (deg == 0) {
+    const uint64_t live = __ballot(ul >= 0);
+    if (live == 0) {
       status = 1;
       break;
+    }
+    // best neighbour: smallest key, ties to the lowest id
+    const uint32_t kl = ul >= 0 ? fkey(__float_as_uint(vl)) : 0xffffffffu;
+    const uint32_t k1 = wave_min(kl, W);
+    const uint64_t eq = __ballot(kl == k1) & live;
+    int L = (int)__builtin_ctzll(eq);
+    int u1 = __builtin_amdgcn_readlane(ul, L);
+    if (eq & (eq - 1)) {
+      u1 = (int)wave_min(((eq >> lane) & 1) ? (uint32_t)ul : 0xffffffffu, W);
+      L = (int)__builtin_ctzll(__ballot(ul == u1) & eq);
     }
     const double v1 = (double)unkey(k1);
     const double e1 = ea + er * fabs(v1);
     const double dvv = (double)cur;
     const double ev = ea + er * fabs(dvv);
-    // the argmin is certain when the second best lies above the best's interval
-    bool certain = deg == 1;
-    if (!certain) {
-      const double v2 = (double)unkey(k2);
-      certain = v2 - (ea + er * fabs(v2)) > v1 + e1;
-    }
+    // neighbours that could be the minimum: all but those whose lower end
+    // lies above the best's upper end (the test is monotone in the value)
+    const double vj = (double)vl;
+    const uint64_t cand = __ballot(ul >= 0 && !(vj - (ea + er * fabs(vj)) > v1 + e1));
+    const bool certain = (cand & ~(1ull << L)) == 0;
     int next = u1;
+    float nextv = unkey(k1);
     bool stuck;
     if (certain && v1 + e1 < dvv - ev) {
       stuck = false;
     } else if (certain && v1 - e1 >= dvv + ev) {
       stuck = true;
     } else {
-      // FP64 re-decision.  Rows: the current vertex, then every neighbour that
-      // could be the minimum; wave (position % waves) computes each row, rows
-      // known from the previous re-decision are reused.
+      // FP64 re-decision.  Rows: the current vertex, then every candidate
+      // neighbour; wave (position % waves) computes each row, rows known from
+      // the previous re-decision are reused.
       ++rechecks;
       const int nw = (int)(blockDim.x >> 6);
+      uint64_t rest = cand | (1ull << L);
       int pos = 0;
-      for (int j = -1; j < deg; ++j) {
-        int x;
-        if (j < 0) {
-          x = v;
-        } else {
-          x = __builtin_amdgcn_readlane(ul, j);
-          const double vj = (double)unkey((uint32_t)__builtin_amdgcn_readlane((int)kl, j));
-          if (vj - (ea + er * fabs(vj)) > v1 + e1) continue;   // certainly above the best
+      for (;;) {
+        int x = v;
+        if (pos > 0) {
+          if (rest == 0) break;
+          x = __builtin_amdgcn_readlane(ul, (int)__builtin_ctzll(rest));
+          rest &= rest - 1;
         }
         if (pos % nw == wave) {
           double dx = 0.0;
@@ -306,8 +351,8 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
           best_u = cu;
         }
       }
-      next = best_u;
-      stuck = !(best < dxv);
+      next = __builtin_amdgcn_readfirstlane(best_u);
+      stuck = __builtin_amdgcn_readfirstlane(best < dxv ? 0 : 1) != 0;
       __syncthreads();   // everyone has read cur_* before it becomes prev_*
       if (threadIdx.x < pos) {
         prev_x[threadIdx.x] = cur_x[threadIdx.x];
@@ -315,16 +360,15 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
       }
       prev_n = pos;   // uniform
       __syncthreads();
+      if (!stuck) {
+        const int ln = (int)__builtin_ctzll(__ballot(ul == next) & live);
+        nextv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vl), ln));
+      }
     }
     if (stuck) {
       status = 1;
       break;
     }
-    // FP32 value of the chosen neighbour
-    float nextv = 0.f;
-    for (int j = 0; j < deg; ++j)
-      if (__builtin_amdgcn_readlane(ul, j) == next)
-        nextv = unkey((uint32_t)__builtin_amdgcn_readlane((int)kl, j));
     cur = nextv;
     v = next;
     if (threadIdx.x == 0) path[len] = v;

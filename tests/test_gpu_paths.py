@@ -131,3 +131,59 @@ def test_grid257_paths(gpu_ctx):
                 assert got == ref
     finally:
         k.free()
+
+
+ALL_KINDS = ["kl", "tv", "chi2", "hellinger"]
+
+
+def test_exact_tie_goes_to_lowest_id_not_first_slot(gpu_ctx):
+    # vertices 2 and 3 have identical rows, so their distances tie exactly in
+    # FP32 and in FP64; the source lists 3 before 2.
+    from paper_1708_02845_amd import Kernel
+    P = np.array([[0.7, 0.1, 0.1, 0.1],
+                  [0.1, 0.3, 0.3, 0.3],
+                  [0.4, 0.2, 0.2, 0.2],
+                  [0.4, 0.2, 0.2, 0.2]], dtype=np.float32)
+    adj_ptr = np.array([0, 2, 4, 6, 8], dtype=np.int64)
+    adj_idx = np.array([2, 3, 3, 2, 1, 0, 1, 0], dtype=np.int32)
+    k = Kernel.load_dense(gpu_ctx, P, adjacency=(adj_ptr, adj_idx))
+    try:
+        for kind in ALL_KINDS:
+            got, status, rechecks = k.plan_path(1, 0, kind, 10)
+            ref, ref_status = oracle_path(P, adj_ptr, adj_idx, 1, 0, kind, 10)
+            assert ref == [1, 2, 0] and got == ref and status == ref_status == "reached"
+            assert rechecks >= 1
+    finally:
+        k.free()
+
+
+def test_high_degree_vertices(gpu_ctx):
+    # a hub adjacent to 63 vertices (padded width 64: every lane of the wave
+    # holds a neighbour) and a ring through the rest
+    from paper_1708_02845_amd import Kernel
+    g = np.random.default_rng(11)
+    N, B = 90, 40
+    P = (g.random((N, B)) ** 3 + 1e-4).astype(np.float64)
+    P /= P.sum(axis=1, keepdims=True)
+    P = P.astype(np.float32)
+    nbrs = [set() for _ in range(N)]
+    for u in range(1, 64):
+        nbrs[0].add(u)
+        nbrs[u].add(0)
+    for u in range(1, N):
+        w = u + 1 if u + 1 < N else 1
+        nbrs[u].add(w)
+        nbrs[w].add(u)
+    order = [sorted(s, key=lambda x: -x) for s in nbrs]   # descending ids
+    adj_ptr = np.cumsum([0] + [len(o) for o in order]).astype(np.int64)
+    adj_idx = np.concatenate([np.array(o, dtype=np.int32) for o in order])
+    k = Kernel.load_dense(gpu_ctx, P, adjacency=(adj_ptr, adj_idx))
+    try:
+        pairs = [(70, 5), (0, 40), (85, 63), (12, 77), (33, 0)]
+        for kind in ALL_KINDS:
+            for s, t in pairs:
+                got, status, _ = k.plan_path(s, t, kind, 200)
+                ref, ref_status = oracle_path(P, adj_ptr, adj_idx, s, t, kind, 200)
+                assert got == ref and status == ref_status
+    finally:
+        k.free()
