@@ -207,11 +207,16 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
   // assigned staging array is placed in scratch memory by the compiler
   static_assert(SEGS % 256 == 0, "B segments must divide evenly over the workgroup");
 
+  // Chunk c's A fragment is loaded into nh/nl during chunk c-1 and copied
+  // into ah/al at the top of chunk c, so the registers the MFMAs read are
+  // never the destination of a load in flight; otherwise the compiler's wait
+  // counting merges the loop edges and makes the MFMAs of chunk c wait for
+  // the loads of chunk c+1.
   u32x4 ah[4], al[4], nh[4], nl[4], bh[SPT], bl[SPT];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    ah[q] = *reinterpret_cast<const u32x4*>(ahp + q * 8);
-    al[q] = *reinterpret_cast<const u32x4*>(alp + q * 8);
+    nh[q] = *reinterpret_cast<const u32x4*>(ahp + q * 8);
+    nl[q] = *reinterpret_cast<const u32x4*>(alp + q * 8);
   }
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
@@ -237,6 +242,11 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
       const int sg = threadIdx.x + q * 256;
       *reinterpret_cast<u32x4*>(&sbh[sg >> 3][(sg & 7) * 8]) = bh[q];
       *reinterpret_cast<u32x4*>(&sbl[sg >> 3][(sg & 7) * 8]) = bl[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ah[q] = nh[q];
+      al[q] = nl[q];
     }
     __syncthreads();
     if (c + 1 < nchunks) {
@@ -275,11 +285,6 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
         accd[n][i] += (double)acc[n][i];
         acc[n][i] = 0.f;
       }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ah[q] = nh[q];
-      al[q] = nl[q];
-    }
   }
   __syncthreads();   // every wave is done with the staged target tiles
   write_fields<NT>(gv, o, T, row0, lane, accd, reinterpret_cast<float*>(lds), out);
@@ -301,9 +306,10 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
   constexpr int SPT = SEGS / 256;
   static_assert(SEGS % 256 == 0, "B segments must divide evenly over the workgroup");
 
+  // A fragments are staged as in kl_gemm_f16x3: loaded into na, copied into a.
   f32x4 a[8], na[8], bq[SPT];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) a[q] = *reinterpret_cast<const f32x4*>(ap + q * 4);
+  for (int q = 0; q < 8; ++q) na[q] = *reinterpret_cast<const f32x4*>(ap + q * 4);
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
     const int sg = threadIdx.x + q * 256;
@@ -326,6 +332,8 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
       const int sg = threadIdx.x + q * 256;
       *reinterpret_cast<f32x4*>(&sb[sg >> 4][(sg & 15) * 4]) = bq[q];
     }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = na[q];
     __syncthreads();
     if (c + 1 < nchunks) {
       const int64_t ko = (int64_t)(c + 1) * KC;
@@ -358,8 +366,6 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
         accd[n][i] += (double)acc[n][i];
         acc[n][i] = 0.f;
       }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) a[q] = na[q];
   }
   __syncthreads();
   write_fields<NT>(gv, o, T, row0, lane, accd, &sb[0][0], out);
