@@ -87,7 +87,7 @@ def kernel_matrix(g, args, progress=None):
 def run_grid1025(args):
     """Full-size measurements on the 1025x1025 domain (N = 992,998, B = 8,150).
 
-    The 64-target contraction in both forms, the single-target TV/KL streams,
+    The 64- and 256-target contraction in both forms, the single-target TV/KL streams,
     and the truncated (tau = 1e-5) TV/KL streams with their local-minimum
     census.  Parity at this size is checked by tests/test_gpu_full_size.py.
     """
@@ -109,7 +109,8 @@ def run_grid1025(args):
     P = kernel_matrix(g, args, progress=prog)
     build_s = time.perf_counter() - t0
     T = 64
-    ts = targets_sources(2, g.N, T)[0]
+    ts_all = targets_sources(2, g.N, 256)[0]
+    ts = ts_all[:T]
     ctx = Context(0)
     res = {}
     for form in ("f16x3", "f32"):
@@ -119,27 +120,31 @@ def run_grid1025(args):
         load_s = time.perf_counter() - t1
         N, B = k.N, k.B
         lda = (B + 63) // 64 * 64
-        D = torch.empty((T, N), dtype=torch.float32, device="cuda:0")
-        k.batch_fields(ts, "kl", out=D)
-        torch.cuda.synchronize()
         reps = 5
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
-            _, bounds = k.batch_fields(ts, "kl", out=D)
-        b.record()
-        torch.cuda.synchronize()
-        us = 1000.0 * a.elapsed_time(b) / reps
-        flops = 2.0 * N * B * T * (3 if form == "f16x3" else 1)
-        byts = N * lda * 4 + T * lda * 4 + T * N * 4 + N * 4
-        tf = flops / (us * 1e-6) / 1e12
-        res[f"a5_batched_kl_{form}_T{T}"] = {
-            "avg_us": round(us, 1), "entries_per_s": N * B * T / (us * 1e-6),
-            "alg_bytes": byts, "GB/s": round(gbs(byts, us), 1),
-            "hbm_frac": round(gbs(byts, us) / HBM_PEAK_GBS, 4), "mfma_TFLOP/s": round(tf, 1),
-            "mfma_frac": round(tf / MFMA_PEAK_TFLOPS[form], 4), "load_s": round(load_s, 1)}
-        log(f"{form}: {us:.0f} us per 64-target launch")
+        for TT in (64, 256):
+            tsT = ts_all[:TT]
+            D = torch.empty((TT, N), dtype=torch.float32, device="cuda:0")
+            k.batch_fields(tsT, "kl", out=D)
+            torch.cuda.synchronize()
+            a.record()
+            for _ in range(reps):
+                _, bounds = k.batch_fields(tsT, "kl", out=D)
+            b.record()
+            torch.cuda.synchronize()
+            us = 1000.0 * a.elapsed_time(b) / reps
+            flops = 2.0 * N * B * TT * (3 if form == "f16x3" else 1)
+            byts = N * lda * 4 + TT * lda * 4 + TT * N * 4 + N * 4
+            tf = flops / (us * 1e-6) / 1e12
+            res[f"a5_batched_kl_{form}_T{TT}"] = {
+                "avg_us": round(us, 1), "entries_per_s": N * B * TT / (us * 1e-6),
+                "alg_bytes": byts, "GB/s": round(gbs(byts, us), 1),
+                "hbm_frac": round(gbs(byts, us) / HBM_PEAK_GBS, 4), "mfma_TFLOP/s": round(tf, 1),
+                "mfma_frac": round(tf / MFMA_PEAK_TFLOPS[form], 4), "load_s": round(load_s, 1)}
+            log(f"{form}: {us:.0f} us per {TT}-target launch")
+            del D
+            torch.cuda.empty_cache()
         if form == "f16x3":
             f = torch.empty((k.N,), dtype=torch.float32, device="cuda:0")
             for kind in ("tv", "kl"):
@@ -156,7 +161,6 @@ def run_grid1025(args):
                     "avg_us": round(us, 1), "alg_bytes": byts, "GB/s": round(gbs(byts, us), 1),
                     "hbm_frac": round(gbs(byts, us) / HBM_PEAK_GBS, 4)}
                 log(f"stream {kind}: {us:.0f} us")
-        del D
         k.free()
         torch.cuda.empty_cache()
     # the truncated kernel (tau = 1e-5 row-relative): streams and local-minimum census

@@ -703,7 +703,7 @@ dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t
     dd::GemmView gv{k->L32.as<const float>(), k->Lhi.as<const uint16_t>(),
                     k->Llo.as<const uint16_t>(), k->Off.as<const float>(),
                     k->lda, k->N, k->B, k->gemm_form};
-    // groups of up to 64 targets; each group reads the log-kernel once
+    // up to 256 targets per launch; each launch reads the log-kernel about once
     AsyncBuf ws(s);
     HIP_OR(ws.alloc(dd::batch_kl_workspace(gv, std::min<int32_t>(T, dd::kMaxBatch))));
     for (int32_t g0 = 0; g0 < T; g0 += dd::kMaxBatch) {

@@ -72,7 +72,7 @@ struct GemmView {
   int32_t N, B, form;
 };
 inline int64_t gemm_rows_padded(int64_t N) { return (N + kGemmRows - 1) / kGemmRows * kGemmRows; }
-constexpr int kMaxBatch = 64;   // targets per contraction launch
+constexpr int kMaxBatch = 256;  // targets per contraction launch (groups of 64 per workgroup)
 struct TargetList {
   int32_t t[kMaxBatch];
 };

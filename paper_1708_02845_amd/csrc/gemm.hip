@@ -5,10 +5,18 @@
 //   H_t     = sum_b p_tb log p_tb,   W_t = sum_b p_tb,
 //
 // with S = l * P_T^T an (N x B) by (B x T) product on MFMA.  The log-kernel l
-// (built once at load) is the A operand and is streamed from HBM exactly once
-// per launch; the target rows are the B operand, staged per K-chunk in LDS
-// and shared by the four waves of a workgroup.  Each wave owns 32 rows and all
-// target columns (32 per column tile).
+// (built once at load) is the A operand; the target rows are the B operand,
+// staged per K-chunk in LDS and shared by the four waves of a workgroup.  A
+// workgroup owns 128 rows and one group of up to 64 targets; each wave owns
+// 32 rows and all columns of the group (32 per column tile).
+//
+// Up to 256 targets run in one launch as groups of 64.  The workgroups of
+// one row block (one per group) are given consecutive positions in the
+// dispatch order of one XCD: work-groups are handed to the eight XCDs round
+// robin, so block b runs on XCD b mod 8, and the decode below places row block
+// rb's groups at consecutive b with the same b mod 8.  They start together and
+// read the same A chunks at about the same time, so the A operand comes from
+// HBM about once and from that XCD's L2 for the other groups.
 //
 // Forms:
 //   F32    l and p in FP32, v_mfma_f32_32x32x2_f32.
@@ -74,8 +82,20 @@ static BatchOperand carve(GemmView gv, int Tpad, void* ws) {
   return o;
 }
 
+constexpr int kXcds = 8;   // MI355X: 8 XCDs, work-groups dispatched round robin
+
+static int padded_targets(int32_t T) { return T <= 32 ? 32 : (T + 63) / 64 * 64; }
+
+// Row block and target group of this workgroup (see the header comment).
+__device__ __forceinline__ void block_tile(int groups, int& rb, int& g) {
+  const int b = (int)blockIdx.x;
+  const int j = b / kXcds;
+  rb = (j / groups) * kXcds + b % kXcds;
+  g = j % groups;
+}
+
 size_t batch_kl_workspace(GemmView gv, int32_t T) {
-  const int Tpad = T <= 32 ? 32 : 64;
+  const int Tpad = padded_targets(T);
   size_t off = gv.form == 0 ? align256(4 * (size_t)Tpad * gv.lda)
                             : 2 * align256(2 * (size_t)Tpad * gv.lda);
   return off + 3 * 8 * (size_t)Tpad;
@@ -151,13 +171,14 @@ __global__ __launch_bounds__(256) void batch_target_prep(DenseView dv, GemmView 
 // 128-byte row segments of two target fields.  `stage` is 4 x 32 x 33 floats.
 template <int NT>
 __device__ __forceinline__ void write_fields(const GemmView& gv, const BatchOperand& o, int32_t T,
-                                             int64_t row0, int lane, const double (&accd)[NT][16],
-                                             float* stage, float* out) {
+                                             int tbase, int64_t row0, int lane,
+                                             const double (&accd)[NT][16], float* stage,
+                                             float* out) {
   const int r = lane & 31, h = lane >> 5;
   float* tile = stage + (threadIdx.x >> 6) * (32 * 33);
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
-    const int t = n * 32 + r;
+    const int t = tbase + n * 32 + r;
     const bool tv = t < T;
     const double H = tv ? o.H[t] : 0.0, W = tv ? o.W[t] : 0.0, is = tv ? o.inv_s[t] : 0.0;
 #pragma unroll
@@ -172,7 +193,7 @@ __device__ __forceinline__ void write_fields(const GemmView& gv, const BatchOper
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int tl = 2 * q + h;
-      const int tt = n * 32 + tl;
+      const int tt = tbase + n * 32 + tl;
       const int64_t x = row0 + r;
       if (tt < T && x < gv.N) out[(int64_t)tt * gv.N + x] = tile[tl * 33 + r];
     }
@@ -182,7 +203,11 @@ __device__ __forceinline__ void write_fields(const GemmView& gv, const BatchOper
 
 template <int NT>
 __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o, int32_t T,
-                                                     float* __restrict__ out) {
+                                                     int32_t groups, float* __restrict__ out) {
+  int rb, grp;
+  block_tile(groups, rb, grp);
+  if ((int64_t)rb * GROWS >= gv.N) return;   // padding of the grid to whole XCD rounds
+  const int tbase = grp * 64;
   // target tiles (hi, lo) in one LDS buffer, reused by the epilogue as a
   // 4 x 32 x 33-float stage
   constexpr int TILE_BYTES = 2 * NT * 32 * (KC + 8) * 2;
@@ -192,11 +217,13 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
   _Float16 (*sbh)[KC + 8] = reinterpret_cast<_Float16 (*)[KC + 8]>(lds);
   _Float16 (*sbl)[KC + 8] = sbh + NT * 32;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
-  const int64_t row0 = (int64_t)blockIdx.x * GROWS + wv * 32;
+  const int64_t row0 = (int64_t)rb * GROWS + wv * 32;
   const int nchunks = (int)(gv.lda / KC);
   // tile-major operand: this workgroup's chunk c is one contiguous block of
   // GROWS x KC; rows past N are zero in memory
-  const int64_t tile0 = (int64_t)blockIdx.x * nchunks * (GROWS * KC);
+  const int64_t tile0 = (int64_t)rb * nchunks * (GROWS * KC);
+  const uint16_t* bhp = o.bhi + (int64_t)tbase * gv.lda;
+  const uint16_t* blp = o.blo + (int64_t)tbase * gv.lda;
   const int64_t lane_off = (int64_t)(wv * 32 + r) * KC + h * 32;
   const uint16_t* ahp = gv.lhi + tile0 + lane_off;
   const uint16_t* alp = gv.llo + tile0 + lane_off;
@@ -222,8 +249,8 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
   for (int q = 0; q < SPT; ++q) {
     const int sg = threadIdx.x + q * 256;
     const int64_t g = (int64_t)(sg >> 3) * gv.lda + (sg & 7) * 8;
-    bh[q] = *reinterpret_cast<const u32x4*>(o.bhi + g);
-    bl[q] = *reinterpret_cast<const u32x4*>(o.blo + g);
+    bh[q] = *reinterpret_cast<const u32x4*>(bhp + g);
+    bl[q] = *reinterpret_cast<const u32x4*>(blp + g);
   }
   floatx16 acc[NT];
   double accd[NT][16];
@@ -261,8 +288,8 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
       for (int q = 0; q < SPT; ++q) {
         const int sg = threadIdx.x + q * 256;
         const int64_t g = (int64_t)(sg >> 3) * gv.lda + ko + (sg & 7) * 8;
-        bh[q] = *reinterpret_cast<const u32x4*>(o.bhi + g);
-        bl[q] = *reinterpret_cast<const u32x4*>(o.blo + g);
+        bh[q] = *reinterpret_cast<const u32x4*>(bhp + g);
+        bl[q] = *reinterpret_cast<const u32x4*>(blp + g);
       }
     }
 #pragma unroll
@@ -287,20 +314,25 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
       }
   }
   __syncthreads();   // every wave is done with the staged target tiles
-  write_fields<NT>(gv, o, T, row0, lane, accd, reinterpret_cast<float*>(lds), out);
+  write_fields<NT>(gv, o, T, tbase, row0, lane, accd, reinterpret_cast<float*>(lds), out);
 }
 
 template <int NT>
 __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, int32_t T,
-                                                   float* __restrict__ out) {
+                                                   int32_t groups, float* __restrict__ out) {
+  int rb, grp;
+  block_tile(groups, rb, grp);
+  if ((int64_t)rb * GROWS >= gv.N) return;   // padding of the grid to whole XCD rounds
+  const int tbase = grp * 64;
   // target tile, reused by the epilogue as a 4 x 32 x 33-float stage
   // (at least 64 rows of 68 floats = 17,408 bytes >= 16,896)
   __shared__ __attribute__((aligned(16))) float sb[(NT == 1 ? 2 : NT) * 32][KC + 4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
-  const int64_t row0 = (int64_t)blockIdx.x * GROWS + wv * 32;
+  const int64_t row0 = (int64_t)rb * GROWS + wv * 32;
   const int nchunks = (int)(gv.lda / KC);
-  const int64_t tile0 = (int64_t)blockIdx.x * nchunks * (GROWS * KC);
+  const int64_t tile0 = (int64_t)rb * nchunks * (GROWS * KC);
   const float* ap = gv.l32 + tile0 + (int64_t)(wv * 32 + r) * KC + h * 32;
+  const float* bp = o.b32 + (int64_t)tbase * gv.lda;
   constexpr int64_t CHUNK = GROWS * KC;
   constexpr int SEGS = NT * 32 * 16;          // 16-byte segments per chunk
   constexpr int SPT = SEGS / 256;
@@ -313,7 +345,7 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
     const int sg = threadIdx.x + q * 256;
-    bq[q] = *reinterpret_cast<const f32x4*>(o.b32 + (int64_t)(sg >> 4) * gv.lda + (sg & 15) * 4);
+    bq[q] = *reinterpret_cast<const f32x4*>(bp + (int64_t)(sg >> 4) * gv.lda + (sg & 15) * 4);
   }
   floatx16 acc[NT];
   double accd[NT][16];
@@ -343,7 +375,7 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
         const int sg = threadIdx.x + q * 256;
-        bq[q] = *reinterpret_cast<const f32x4*>(o.b32 + (int64_t)(sg >> 4) * gv.lda + ko +
+        bq[q] = *reinterpret_cast<const f32x4*>(bp + (int64_t)(sg >> 4) * gv.lda + ko +
                                                  (sg & 15) * 4);
       }
     }
@@ -368,28 +400,31 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
       }
   }
   __syncthreads();
-  write_fields<NT>(gv, o, T, row0, lane, accd, &sb[0][0], out);
+  write_fields<NT>(gv, o, T, tbase, row0, lane, accd, &sb[0][0], out);
 }
 
 hipError_t launch_batch_kl(DenseView dv, GemmView gv, TargetList tl, int32_t T, void* ws,
                            float* out, hipStream_t s) {
-  if (T <= 0 || T > 64 || gv.lda % KC != 0) return hipErrorInvalidValue;
-  const int Tpad = T <= 32 ? 32 : 64;
+  if (T <= 0 || T > kMaxBatch || gv.lda % KC != 0) return hipErrorInvalidValue;
+  const int Tpad = padded_targets(T);
   const BatchOperand o = carve(gv, Tpad, ws);
   hipLaunchKernelGGL(batch_target_prep, dim3(Tpad), dim3(256), 0, s, dv, gv, tl, T, o);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)((gv.N + GROWS - 1) / GROWS));
+  const int groups = Tpad <= 32 ? 1 : Tpad / 64;
+  const int64_t rblocks = (gv.N + GROWS - 1) / GROWS;
+  const int64_t rpad = (rblocks + kXcds - 1) / kXcds * kXcds;
+  const dim3 grid((unsigned)(rpad * groups));
   if (gv.form == 0) {
     if (Tpad == 32)
-      hipLaunchKernelGGL(kl_gemm_f32<1>, grid, dim3(256), 0, s, gv, o, T, out);
+      hipLaunchKernelGGL(kl_gemm_f32<1>, grid, dim3(256), 0, s, gv, o, T, groups, out);
     else
-      hipLaunchKernelGGL(kl_gemm_f32<2>, grid, dim3(256), 0, s, gv, o, T, out);
+      hipLaunchKernelGGL(kl_gemm_f32<2>, grid, dim3(256), 0, s, gv, o, T, groups, out);
   } else {
     if (Tpad == 32)
-      hipLaunchKernelGGL(kl_gemm_f16x3<1>, grid, dim3(256), 0, s, gv, o, T, out);
+      hipLaunchKernelGGL(kl_gemm_f16x3<1>, grid, dim3(256), 0, s, gv, o, T, groups, out);
     else
-      hipLaunchKernelGGL(kl_gemm_f16x3<2>, grid, dim3(256), 0, s, gv, o, T, out);
+      hipLaunchKernelGGL(kl_gemm_f16x3<2>, grid, dim3(256), 0, s, gv, o, T, groups, out);
   }
   return hipGetLastError();
 }

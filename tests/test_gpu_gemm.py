@@ -30,7 +30,7 @@ def gemm_kernel(request, gpu_ctx, grid):
     k.free()
 
 
-@pytest.mark.parametrize("T", [1, 5, 32, 33, 64, 70])
+@pytest.mark.parametrize("T", [1, 5, 32, 33, 64, 70, 128, 200, 256, 300])
 def test_batched_kl_matches_oracle(grid, gemm_kernel, T):
     g, P = grid
     form, k = gemm_kernel
@@ -39,7 +39,9 @@ def test_batched_kl_matches_oracle(grid, gemm_kernel, T):
     D, bounds = k.batch_fields(ts, "kl")
     D = D.cpu().numpy()
     P64 = P.astype(np.float64)
-    for i in sorted({0, T // 2, T - 1}):
+    # first, middle and last target, and the first and last of each group of 64
+    picks = {0, T // 2, T - 1} | {i for g0 in range(64, T, 64) for i in (g0 - 1, g0)}
+    for i in sorted(picks):
         ref = dv.kl_field(P64, int(ts[i]))
         assert normwise(D[i], ref) <= TOL, (form, T, i)
         assert within_bound(D[i], ref, bounds[i]), (form, T, i)
@@ -53,8 +55,12 @@ def test_batch_invariance(grid, gemm_kernel):
     alone = k.batch_fields([t], "kl")[0].cpu().numpy()[0]
     in_64 = k.batch_fields(ts, "kl")[0].cpu().numpy()[37]
     first = k.batch_fields([t] + ts[1:], "kl")[0].cpu().numpy()[0]
+    wide = list(targets_sources(78, g.N, 256)[0])
+    wide[200] = t
+    in_256 = k.batch_fields(wide, "kl")[0].cpu().numpy()[200]
     assert np.array_equal(alone, in_64)
     assert np.array_equal(alone, first)
+    assert np.array_equal(alone, in_256)
 
 
 def test_paths_on_contraction_fields(grid, gemm_kernel):
@@ -104,17 +110,17 @@ def test_zero_entry_cannot_build_operand(gpu_ctx):
 
 
 @pytest.mark.parametrize("form", FORMS)
-def test_grid257_batch_of_64(gpu_ctx, form):
+def test_grid257_batch_of_256(gpu_ctx, form):
     from paper_1708_02845_amd import Kernel
     g = build_config("c2")
     P = g.poisson_kernel(dtype=np.float32)
     k = Kernel.load_dense(gpu_ctx, P, gemm_form=form)
     try:
-        ts = targets_sources(1, g.N, 64)[0]
+        ts = targets_sources(1, g.N, 256)[0]
         D, bounds = k.batch_fields(ts, "kl")
         D = D.cpu().numpy()
         P64 = P.astype(np.float64)
-        for i in (0, 63):
+        for i in (0, 63, 64, 191, 255):
             ref = dv.kl_field(P64, int(ts[i]))
             assert normwise(D[i], ref) <= TOL
             assert within_bound(D[i], ref, bounds[i])
