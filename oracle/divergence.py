@@ -26,6 +26,14 @@ dropped entry of row x stands at the threshold of row x (the floor phi_x):
 * KL_tau:  d(x) = sum_{b: p~_b > 0} p~_b (log p~_b - log q^_b),
            q^_b = q~_b if q~_b > 0 else phi_x.
 
+The paper's own sparse KL keeps log P of every row exact and sums only over
+the support of the truncated *target* row (the remedy of Section V,
+"Precision": log P combined in the sparse sum after small values of P are
+eliminated).  This oracle evaluates it as
+
+* KL_S:    d(x) = sum_{b in S_t} p_b log(p_b / q_b),   S_t = {b : p_b >= thr_t, p_b > 0},
+           thr_t = tau * max_b p_b (row-relative) or tau (absolute).
+
 All arithmetic is FP64, rows processed in chunks to bound memory.
 """
 
@@ -87,6 +95,40 @@ def hellinger_field(P, t):
     for lo, hi in _row_chunks(P.shape[0], P.shape[1]):
         d[lo:hi] = ((np.sqrt(P[lo:hi]) - sp[None, :]) ** 2).sum(axis=1)
     return d
+
+
+def support(p, tau, relative=True):
+    """Mask of the truncated support of row p: p_b > 0 and p_b >= the threshold."""
+    p = np.asarray(p, dtype=np.float64)
+    thr = tau * p.max() if relative else float(tau)
+    return (p > 0) & (p >= thr)
+
+
+def kl_support_field(P, t, tau, relative=True):
+    """KL_S: eq. (35) summed over the truncated support of the target row only."""
+    P = np.asarray(P, dtype=np.float64)
+    sup = support(P[t], tau, relative)
+    ps = P[t][sup]
+    d = np.empty(P.shape[0])
+    with np.errstate(divide="ignore"):
+        for lo, hi in _row_chunks(P.shape[0], int(sup.sum())):
+            q = P[lo:hi][:, sup]
+            d[lo:hi] = (ps[None, :] * np.log(ps[None, :] / q)).sum(axis=1)
+    return d
+
+
+FIELDS = {"tv": tv_field, "kl": kl_field, "chi2": chi2_field, "hellinger": hellinger_field}
+
+
+def distances(P, t, xs, kind, tau=0.0, relative=True):
+    """Distances of the rows xs to the target row t: the field functions
+    applied to the stacked rows [P[t]; P[xs]] (equal to the field entries up
+    to summation order).  kind "kl_s" is KL_S with threshold tau."""
+    P = np.asarray(P, dtype=np.float64)
+    sub = np.vstack([P[t][None, :], P[np.asarray(xs, dtype=np.int64)]])
+    if kind == "kl_s":
+        return kl_support_field(sub, 0, tau, relative)[1:]
+    return FIELDS[kind](sub, 0)[1:]
 
 
 def truncate(P, tau, relative=True):

@@ -184,3 +184,53 @@ def test_csr_round_trip(grid_P):
     for x in range(Pt.shape[0]):
         back[x, col[ptr[x]:ptr[x + 1]]] = val[ptr[x]:ptr[x + 1]]
     assert np.array_equal(back, Pt)
+
+
+def test_support_kl_threshold_zero_is_dense_kl(grid_P):
+    t = 210
+    assert np.array_equal(dv.kl_support_field(grid_P, t, 0.0), dv.kl_field(grid_P, t))
+
+
+def test_support_kl_brute_force():
+    g = np.random.default_rng(9)
+    P = g.random((12, 30)) ** 4
+    P /= P.sum(axis=1, keepdims=True)
+    t, tau = 3, 0.05
+    d = dv.kl_support_field(P, t, tau)
+    da = dv.kl_support_field(P, t, 0.01, relative=False)
+    for x in range(12):
+        s_rel = 0.0
+        s_abs = 0.0
+        for b in range(30):
+            p, q = P[t, b], P[x, b]
+            if p >= tau * max(P[t]):
+                s_rel += p * np.log(p / q)
+            if p >= 0.01:
+                s_abs += p * np.log(p / q)
+        assert d[x] == pytest.approx(s_rel, rel=1e-13, abs=1e-16)
+        assert da[x] == pytest.approx(s_abs, rel=1e-13, abs=1e-16)
+
+
+def test_support_kl_log_sum_lower_bound(grid_P):
+    # log-sum inequality on S_t: d(x) >= W_S log(W_S / Q_S(x)), equality at x = t
+    t, tau = 400, 1e-2
+    d = dv.kl_support_field(grid_P, t, tau)
+    sup = dv.support(grid_P[t], tau)
+    assert 0 < sup.sum() < sup.size
+    W = grid_P[t, sup].sum()
+    Q = grid_P[:, sup].sum(axis=1)
+    lb = W * np.log(W / Q)
+    assert np.all(d >= lb - 1e-12 * np.abs(d)) and d[t] == 0.0
+    # it is not the dense KL: the dropped mass changes the value
+    assert np.abs(d - dv.kl_field(grid_P, t)).max() > 1e-4
+
+
+def test_row_distances_equal_field_entries(grid_P):
+    t = 50
+    xs = [0, 7, 50, 900, 901]
+    # equal up to the order numpy sums a row in (the stacked matrix is small)
+    for kind, f in dv.FIELDS.items():
+        assert np.allclose(dv.distances(grid_P, t, xs, kind), f(grid_P, t)[xs],
+                           rtol=1e-14, atol=0)
+    assert np.allclose(dv.distances(grid_P, t, xs, "kl_s", 1e-3),
+                       dv.kl_support_field(grid_P, t, 1e-3)[xs], rtol=1e-14, atol=0)

@@ -102,3 +102,20 @@ def test_no_spurious_minima_in_disk_fields(c1):
     t = int(targets_sources(0, c1.N, 1)[0][0])
     for field in (dv.kl_field(c1.P, t), dv.tv_field(c1.P, t)):
         assert op.spurious_minima(field, c1.adj_ptr, c1.adj_idx, t) == []
+
+
+@pytest.mark.parametrize("kind", ["kl", "tv"])
+def test_on_demand_walk_equals_full_field_walk(c1, kind):
+    # Section V: the CPU evaluates distances only where the path needs them;
+    # the walk must be the one the full field gives, at a small fraction of
+    # the evaluations
+    ts, ss = targets_sources(0, c1.N, 4)
+    for s, t in zip(ss, ts):
+        s, t = int(s), int(t)
+        full = dv.FIELDS[kind](c1.P, t)
+        ref, ref_st = op.steepest_descent_path(full, c1.adj_ptr, c1.adj_idx, s, t, 4000)
+        got, st, n_eval = op.steepest_descent_path_lazy(
+            lambda xs: dv.distances(c1.P, t, xs, kind), c1.adj_ptr, c1.adj_idx, s, t, 4000)
+        assert got == ref and st == ref_st
+        deg = int(np.diff(c1.adj_ptr).max())
+        assert n_eval <= 1 + (len(got) - 1) * deg and n_eval < c1.N // 10
