@@ -199,6 +199,39 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
                          int32_t max_steps, int32_t* path_dev, int32_t* len_dev,
                          int32_t* status_dev, int32_t* rechecks_dev, void* stream);
 
+/* Paths with distances evaluated on demand (Section V: the CPU evaluates
+ * the distances only at the vertices the path needs): no field is given; at
+ * each step the FP64 distances of the current vertex's neighbours are
+ * computed from the resident rows and the walk of dd_trace_paths is taken on
+ * them, so the path is the one the exact FP64 field gives.
+ *   kind          as for the field entry points (dense: all kinds; CSR: TV, KL
+ *                 of the truncated rows)
+ *   target_tau    0, or with DD_KL on a dense handle the truncation of the
+ *                 target row before the sums (the target-support KL of
+ *                 dd_support_kl_field); row-relative if target_tau_relative
+ *   sources, targets  host [T]
+ *   path_dev, len_dev, status_dev  as for dd_trace_paths
+ *   evals_dev     device [T] int32 distances evaluated per path, nullable
+ * Needs the adjacency.  Asynchronous on `stream`. */
+dd_status dd_trace_paths_on_demand(dd_kernel* k, int32_t T, const int32_t* sources,
+                                   const int32_t* targets, int32_t kind, double target_tau,
+                                   int32_t target_tau_relative, int32_t max_steps,
+                                   int32_t* path_dev, int32_t* len_dev, int32_t* status_dev,
+                                   int32_t* evals_dev, void* stream);
+
+/* KL summed over the truncated support of the target row, with the rows of
+ * x kept exact (the sparse KL of Section V, "Precision"):
+ *     d(x) = sum_{b in S_t} P_tb log(P_tb / P_xb),
+ *     S_t  = {b : P_tb > 0, P_tb >= thr}, thr = tau * max_b P_tb (tau_relative)
+ *            or tau,
+ * into out_dev[N] (device FP32).  The support is decided on the FP64 master
+ * row when the handle has one.  One streaming pass that reads only the
+ * 16-byte row pieces meeting S_t.  tau = 0 gives the DD_KL field bit for bit.
+ * Dense handles only.  bound: nullable host pointer (the DD_KL bound, which
+ * covers this subset of its terms).  Asynchronous on `stream`. */
+dd_status dd_support_kl_field(dd_kernel* k, int32_t target, double tau, int32_t tau_relative,
+                              float* out_dev, dd_error_bound* bound, void* stream);
+
 /* Spurious local minima of T fields (Section V, "Low resolution
  * discretizations"): a vertex v other than the target is a local minimum when
  * no neighbour u has d(u) < d(v).  Each vertex is classified against the

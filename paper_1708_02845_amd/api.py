@@ -207,6 +207,34 @@ class Kernel:
                                          C.c_void_p(info[2].data_ptr()), _stream_handle(stream)))
         return paths, info[0], info[1], info[2]
 
+    def trace_paths_on_demand(self, sources, targets, kind, max_steps, target_tau=0.0,
+                              target_tau_relative=True, stream=None):
+        """Device tensors (paths [T, max_steps+1], len [T], status [T], evaluations [T])
+        of walks that evaluate FP64 distances only where the path needs them."""
+        torch = _torch()
+        s = np.ascontiguousarray(sources, dtype=np.int32)
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        T = len(s)
+        dev = f"cuda:{self.ctx.device}"
+        paths = torch.empty((T, max_steps + 1), dtype=torch.int32, device=dev)
+        info = torch.empty((3, T), dtype=torch.int32, device=dev)
+        L.check(self._lib.dd_trace_paths_on_demand(
+            self._h, int(T), C.c_void_p(s.ctypes.data), C.c_void_p(t.ctypes.data), _kind(kind),
+            float(target_tau), int(bool(target_tau_relative)), int(max_steps),
+            C.c_void_p(paths.data_ptr()), C.c_void_p(info[0].data_ptr()),
+            C.c_void_p(info[1].data_ptr()), C.c_void_p(info[2].data_ptr()),
+            _stream_handle(stream)))
+        return paths, info[0], info[1], info[2]
+
+    def support_kl_field(self, target, tau, relative=True, out=None, stream=None):
+        """(field [N], bound) of KL summed over the truncated target support."""
+        out = self._out((self.N,), out)
+        b = L.dd_error_bound()
+        L.check(self._lib.dd_support_kl_field(self._h, int(target), float(tau), int(bool(relative)),
+                                              C.c_void_p(out.data_ptr()), C.byref(b),
+                                              _stream_handle(stream)))
+        return out, bound_tuple(b)
+
     def local_minima(self, targets, fields, bounds, stream=None):
         """Device tensors (classes uint8 [T, N], counts int32 [T, 2]) of the
         local-minimum census: 0 not a minimum, 1 certain minimum, 2 undecided."""

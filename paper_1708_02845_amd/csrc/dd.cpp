@@ -811,6 +811,91 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
   return DD_OK;
 }
 
+dd_status dd_trace_paths_on_demand(dd_kernel* k, int32_t T, const int32_t* sources,
+                                   const int32_t* targets, int32_t kind, double target_tau,
+                                   int32_t target_tau_relative, int32_t max_steps,
+                                   int32_t* path_dev, int32_t* len_dev, int32_t* status_dev,
+                                   int32_t* evals_dev, void* stream) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (!k->has_adj) return fail(DD_EINVAL, "kernel was loaded without adjacency");
+  if (dd_status st = check_kind(k, kind)) return st;
+  if (T <= 0 || !sources || !targets || !path_dev || !len_dev || !status_dev)
+    return fail(DD_EINVAL, "T=%d or a required pointer is null", T);
+  if (max_steps < 0) return fail(DD_EINVAL, "max_steps=%d", max_steps);
+  if (!(target_tau >= 0.0) || !std::isfinite(target_tau))
+    return fail(DD_EINVAL, "target_tau=%g", target_tau);
+  if (target_tau > 0.0 && (kind != DD_KL || k->is_csr))
+    return fail(DD_EINVAL, "a target-row truncation needs DD_KL on a dense handle");
+  for (int32_t i = 0; i < T; ++i)
+    if (sources[i] < 0 || sources[i] >= k->N || targets[i] < 0 || targets[i] >= k->N)
+      return fail(DD_EINVAL, "path %d: source %d / target %d not in [0, %d)", i, sources[i],
+                  targets[i], k->N);
+  HIP_OR(hipSetDevice(k->ctx->device));
+  hipStream_t s = as_stream(stream);
+  dd::PathArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.adj = k->adj.as<const int32_t>();
+  a.adj_w = k->adj_w;
+  a.path = path_dev;
+  a.len = len_dev;
+  a.status = status_dev;
+  a.rechecks = evals_dev;
+  a.T = T;
+  a.max_steps = max_steps;
+  a.kind = kind;
+  a.is_csr = k->is_csr;
+  a.tgt_tau = target_tau;
+  a.tgt_tau_relative = target_tau_relative ? 1 : 0;
+  // scratch: [sources, targets when T is large] [FP64 target rows, logs, constants]
+  const bool inl = T <= dd::kInlinePaths;
+  const size_t n_small = inl ? 0 : 8 * (size_t)T;
+  const size_t o_row = (n_small + 255) & ~size_t(255);
+  const size_t n_row = 16 * (size_t)T * (size_t)k->B + 32 * (size_t)T;
+  AsyncBuf ws(s);
+  HIP_OR(ws.alloc(o_row + n_row));
+  unsigned char* base = ws.as<unsigned char>();
+  std::vector<int32_t> host;
+  if (inl) {
+    for (int32_t i = 0; i < T; ++i) {
+      a.small.src[i] = sources[i];
+      a.small.tgt[i] = targets[i];
+    }
+  } else {
+    host.resize(2 * (size_t)T);
+    std::memcpy(host.data(), sources, 4 * (size_t)T);
+    std::memcpy(host.data() + T, targets, 4 * (size_t)T);
+    // pageable source: the copy is staged before hipMemcpyAsync returns
+    HIP_OR(hipMemcpyAsync(base, host.data(), n_small, hipMemcpyHostToDevice, s));
+    a.sources = reinterpret_cast<const int32_t*>(base);
+    a.targets = reinterpret_cast<const int32_t*>(base + 4 * (size_t)T);
+  }
+  double* trow = reinterpret_cast<double*>(base + o_row);
+  double* tlog = trow + (size_t)T * (size_t)k->B;
+  double* tcon = tlog + (size_t)T * (size_t)k->B;
+  HIP_OR(dd::launch_target_rows(k->dense(), k->csr(), a, trow, tlog, tcon, s));
+  a.trow = trow;
+  a.tlog = tlog;
+  a.tconst = tcon;
+  HIP_OR(dd::launch_paths_on_demand(k->dense(), k->csr(), a, s));
+  return DD_OK;
+}
+
+dd_status dd_support_kl_field(dd_kernel* k, int32_t target, double tau, int32_t tau_relative,
+                              float* out_dev, dd_error_bound* bound, void* stream) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (k->is_csr) return fail(DD_EINVAL, "the target-support KL needs a dense handle");
+  if (target < 0 || target >= k->N || !out_dev)
+    return fail(DD_EINVAL, "target %d not in [0, %d) or out_dev null", target, k->N);
+  if (!(tau >= 0.0) || !std::isfinite(tau) || (tau_relative && tau > 1.0))
+    return fail(DD_EINVAL, "tau=%g", tau);
+  HIP_OR(hipSetDevice(k->ctx->device));
+  HIP_OR(dd::launch_support_kl_field(k->dense(), target, tau, tau_relative ? 1 : 0, out_dev,
+                                     as_stream(stream)));
+  // the terms are a subset of eq. (35)'s, so the dense KL bound holds
+  if (bound) *bound = field_bound(k, DD_KL, target);
+  return DD_OK;
+}
+
 dd_status dd_local_minima(dd_kernel* k, int32_t T, const int32_t* targets, const float* fields_dev,
                           const dd_error_bound* bounds, uint8_t* class_dev, int32_t* counts_dev,
                           void* stream) {

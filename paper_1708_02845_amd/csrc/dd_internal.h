@@ -105,13 +105,23 @@ struct PathArgs {
   int32_t* path;            // [T][max_steps+1]
   int32_t* len;             // [T]
   int32_t* status;          // [T]
-  int32_t* rechecks;        // [T] or nullptr
+  int32_t* rechecks;        // [T] or nullptr (on-demand walk: rows evaluated)
   int32_t T, max_steps, kind, is_csr;
+  // truncation of the target row before the sums (0: none); thr = tau * max
+  // of the row when tau_relative, else tau
+  double tgt_tau;
+  int32_t tgt_tau_relative;
 };
 hipError_t launch_target_rows(DenseView dv, CsrView cv, PathArgs a, double* trow, double* tlog,
                               double* tconst, hipStream_t s);
 hipError_t launch_neighbor_values(PathArgs a, int32_t N, float* nv, hipStream_t s);
 hipError_t launch_paths(DenseView dv, CsrView cv, PathArgs a, hipStream_t s);
+// walk that evaluates FP64 distances on demand (no field): uses adj, sources,
+// targets, trow/tlog/tconst, path/len/status, rechecks (= rows evaluated)
+hipError_t launch_paths_on_demand(DenseView dv, CsrView cv, PathArgs a, hipStream_t s);
+// KL over the truncated support of the target row, one streaming pass
+hipError_t launch_support_kl_field(DenseView v, int32_t target, double tau, int tau_relative,
+                                   float* out, hipStream_t s);
 // local-minimum census (path.hip): uses adj, adj_w, fields, T, targets/bounds
 // (inline or device) of PathArgs
 hipError_t launch_local_minima(PathArgs a, int32_t N, uint8_t* cls, int32_t* counts,

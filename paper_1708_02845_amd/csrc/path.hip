@@ -47,10 +47,33 @@ __global__ __launch_bounds__(256) void target_rows_kernel(DenseView dv, CsrView 
   double* out = trow + (int64_t)blockIdx.x * B;
   double* lout = tlog + (int64_t)blockIdx.x * B;
   __shared__ double red[3][8];
+  __shared__ double thr_s;
   double w = 0.0, h = 0.0, c = 0.0;
   if (!a.is_csr) {
+    // threshold of the target-row truncation (none when tgt_tau == 0)
+    double thr = 0.0;
+    if (a.tgt_tau > 0.0) {
+      if (a.tgt_tau_relative) {
+        double m = 0.0;
+        for (int b = threadIdx.x; b < B; b += blockDim.x)
+          m = fmax(m, dv.P64 ? dv.P64[(int64_t)t * dv.B + b] : (double)dv.P[(int64_t)t * dv.ld + b]);
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+        if ((threadIdx.x & 63) == 0) red[0][threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          double M = 0.0;
+          for (int i = 0; i < (int)(blockDim.x >> 6); ++i) M = fmax(M, red[0][i]);
+          thr_s = a.tgt_tau * M;
+        }
+        __syncthreads();
+        thr = thr_s;
+      } else {
+        thr = a.tgt_tau;
+      }
+    }
     for (int b = threadIdx.x; b < B; b += blockDim.x) {
-      const double p = dv.P64 ? dv.P64[(int64_t)t * dv.B + b] : (double)dv.P[(int64_t)t * dv.ld + b];
+      double p = dv.P64 ? dv.P64[(int64_t)t * dv.B + b] : (double)dv.P[(int64_t)t * dv.ld + b];
+      if (p < thr) p = 0.0;
       const double lp = p > 0.0 ? log(p) : 0.0;
       out[b] = p;
       lout[b] = lp;
@@ -79,6 +102,7 @@ __global__ __launch_bounds__(256) void target_rows_kernel(DenseView dv, CsrView 
   w = wsum(w);
   h = wsum(h);
   c = wsum(c);
+  __syncthreads();   // red[] may still be read by the threshold step
   const int wid = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     red[0][wid] = w;
@@ -382,6 +406,120 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
   }
 }
 
+// On-demand walk (Section V: the CPU evaluates the distances only at the
+// vertices the path needs).  No field is given: at each step the FP64
+// distances of the current vertex's neighbours are computed from the resident
+// rows, one row per wave, and the decision is taken on them directly, so the
+// walk is the one the exact FP64 field gives.  Rows evaluated at the previous
+// step (its neighbours and the vertex itself) are reused.  `rechecks`
+// receives the number of rows evaluated.
+__global__ __launch_bounds__(256) void paths_on_demand_kernel(DenseView dv, CsrView cv,
+                                                              PathArgs a) {
+  __shared__ int cur_x[65], prev_x[65];
+  __shared__ double cur_d[65], prev_d[65];
+  __shared__ double first_d;
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nw = (int)(blockDim.x >> 6);
+  const int W = a.adj_w;
+  const int Bt = a.is_csr ? cv.B : dv.B;
+  const double* p = a.trow + (int64_t)i * Bt;
+  const double* lpt = a.tlog + (int64_t)i * Bt;
+  const double* tc = a.tconst + (int64_t)i * 4;
+  int32_t* path = a.path + (int64_t)i * (a.max_steps + 1);
+  const int32_t* __restrict__ adj = a.adj;
+  const int t = __builtin_amdgcn_readfirstlane(path_target(a, i));
+  int v = __builtin_amdgcn_readfirstlane(path_source(a, i));
+  if (wave == 0) {
+    const double dx = exact_distance(dv, cv, a.is_csr, a.kind, p, lpt, tc, v);
+    if (lane == 0) first_d = dx;
+  }
+  __syncthreads();
+  double dcur = uniform(first_d);
+  int evals = 1;
+  int prev_n = 0;
+  int len = 1;
+  int status = 0;
+  if (threadIdx.x == 0) path[0] = v;
+  for (;;) {
+    v = __builtin_amdgcn_readfirstlane(v);
+    len = __builtin_amdgcn_readfirstlane(len);
+    if (v == t) {
+      status = 0;
+      break;
+    }
+    if (len - 1 >= a.max_steps) {
+      status = 2;
+      break;
+    }
+    const int ul = lane < W ? adj[(int64_t)v * W + lane] : -1;
+    const uint64_t live = __ballot(ul >= 0);
+    if (live == 0) {
+      status = 1;
+      break;
+    }
+    uint64_t rest = live;
+    int pos = 0;
+    while (rest) {
+      const int x = __builtin_amdgcn_readlane(ul, (int)__builtin_ctzll(rest));
+      rest &= rest - 1;
+      int hit = -1;
+      for (int q = 0; q < prev_n; ++q)
+        if (prev_x[q] == x) hit = q;
+      hit = __builtin_amdgcn_readfirstlane(hit);
+      if (hit < 0) ++evals;
+      if (pos % nw == wave) {
+        const double dx = hit >= 0 ? prev_d[hit]
+                                   : exact_distance(dv, cv, a.is_csr, a.kind, p, lpt, tc, x);
+        if (lane == 0) {
+          cur_x[pos] = x;
+          cur_d[pos] = dx;
+        }
+      }
+      ++pos;
+    }
+    __syncthreads();
+    double best = __builtin_inf();
+    int best_u = 0x7fffffff;
+    for (int q = 0; q < pos; ++q) {
+      const double dx = cur_d[q];
+      const int cu = cur_x[q];
+      if (dx < best || (dx == best && cu < best_u)) {
+        best = dx;
+        best_u = cu;
+      }
+    }
+    best = uniform(best);
+    best_u = __builtin_amdgcn_readfirstlane(best_u);
+    __syncthreads();   // everyone has read cur_* before it becomes prev_*
+    if (threadIdx.x < pos) {
+      prev_x[threadIdx.x] = cur_x[threadIdx.x];
+      prev_d[threadIdx.x] = cur_d[threadIdx.x];
+    }
+    if (threadIdx.x == 0) {
+      prev_x[pos] = v;
+      prev_d[pos] = dcur;
+    }
+    prev_n = pos + 1;
+    __syncthreads();
+    if (!(best < dcur)) {
+      status = 1;
+      break;
+    }
+    v = best_u;
+    dcur = best;
+    if (threadIdx.x == 0) path[len] = v;
+    ++len;
+  }
+  for (int k = len + threadIdx.x; k <= a.max_steps; k += blockDim.x) path[k] = -1;
+  if (threadIdx.x == 0) {
+    a.len[i] = len;
+    a.status[i] = status;
+    if (a.rechecks) a.rechecks[i] = evals;
+  }
+}
+
 // One thread per (field, vertex).  Interval test against the field's bound:
 // a neighbour is certainly lower when its upper end is below v's lower end,
 // certainly not lower when its lower end is at or above v's upper end.
@@ -460,6 +598,11 @@ hipError_t launch_neighbor_values(PathArgs a, int32_t N, float* nv, hipStream_t 
 
 hipError_t launch_paths(DenseView dv, CsrView cv, PathArgs a, hipStream_t s) {
   hipLaunchKernelGGL(paths_kernel, dim3(a.T), dim3(256), 0, s, dv, cv, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_paths_on_demand(DenseView dv, CsrView cv, PathArgs a, hipStream_t s) {
+  hipLaunchKernelGGL(paths_on_demand_kernel, dim3(a.T), dim3(256), 0, s, dv, cv, a);
   return hipGetLastError();
 }
 

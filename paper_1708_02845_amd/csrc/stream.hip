@@ -124,6 +124,84 @@ __global__ __launch_bounds__(512) void dense_field_kernel(const float* __restric
 }
 
 // ---------------------------------------------------------------------------
+// KL over the truncated support of the target row (the sparse KL of Section V,
+// "Precision", with the rows of x kept exact):
+//   d(x) = sum_{b in S_t} p_b log(p_b / q_b),  S_t = {b : p_b > 0, p_b >= thr},
+// thr = tau * max_b p_b (row-relative) or tau.  The truncated target row and
+// its log2 sit in LDS; a lane skips the 16-byte load of a row piece whose four
+// target entries are all outside S_t, so the pass reads only the pieces of
+// each row that meet the support (clustered along the boundary for the
+// harmonic measure).  The support is decided on the FP64 master row when the
+// handle has one, so it is the set the FP64 definition gives.
+template <int LPR, int UNROLL>
+__global__ __launch_bounds__(512) void support_kl_kernel(const float* __restrict__ P,
+                                                         const double* __restrict__ P64,
+                                                         int64_t ld, int32_t B, int32_t N,
+                                                         int32_t target, double tau,
+                                                         int tau_relative,
+                                                         float* __restrict__ out) {
+  extern __shared__ float4 smem4[];
+  __shared__ double redm[8];
+  const int nv = (int)(ld >> 2);
+  float4* sp = smem4;
+  float4* sl = smem4 + nv;
+  const float* trow = P + (int64_t)target * ld;
+  const double* trow64 = P64 ? P64 + (int64_t)target * B : nullptr;
+  double thr = tau;
+  if (tau_relative) {
+    double m = 0.0;
+    for (int b = threadIdx.x; b < B; b += blockDim.x)
+      m = fmax(m, trow64 ? trow64[b] : (double)trow[b]);
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) redm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, redm[i]);
+    thr = tau * m;
+  }
+  float* spf = reinterpret_cast<float*>(sp);
+  float* slf = reinterpret_cast<float*>(sl);
+  for (int b = threadIdx.x; b < 4 * nv; b += blockDim.x) {
+    float pv = b < B ? trow[b] : 0.f;
+    const double pd = b < B ? (trow64 ? trow64[b] : (double)pv) : 0.0;
+    if (!(pd > 0.0 && pd >= thr)) pv = 0.f;
+    spf[b] = pv;
+    slf[b] = pv > 0.f ? hw_log2(pv) : 0.f;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & (LPR - 1);
+  const int grp = threadIdx.x / LPR;
+  const int gpb = blockDim.x / LPR;
+  for (int64_t row = (int64_t)blockIdx.x * gpb + grp; row < N; row += (int64_t)gridDim.x * gpb) {
+    const float4* q = reinterpret_cast<const float4*>(P + row * ld);
+    double acc = 0.0;
+    for (int base = lane; base < nv; base += LPR * UNROLL) {
+      vf4 v[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const int i = base + u * LPR;
+        const float4 pp = i < nv ? sp[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const bool need = (pp.x + pp.y) + (pp.z + pp.w) > 0.f;
+        v[u] = need ? __builtin_nontemporal_load(reinterpret_cast<const vf4*>(q + i))
+                    : vf4{1.f, 1.f, 1.f, 1.f};
+      }
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const int i = base + u * LPR;
+        if (i < nv) {
+          const float4 qv = make_float4(v[u].x, v[u].y, v[u].z, v[u].w);
+          acc += (double)term4<1>(sp[i], sl[i], qv);
+        }
+      }
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
+    if (lane == 0) out[row] = (float)(acc * 0.69314718055994530942);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Truncated (CSR) rows.  The truncated target row p~ is scattered into LDS as
 // a dense vector of (p~, log2 p~) pairs (zeros where dropped).  For row x with
 // stored support S_x:
@@ -297,6 +375,28 @@ hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out,
     case 3: return dense_dispatch<3>(v, target, out, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int LPR>
+static hipError_t support_launch(DenseView v, int32_t target, double tau, int tau_relative,
+                                 float* out, hipStream_t s) {
+  auto kern = support_kl_kernel<LPR, 4>;
+  const size_t lds = (size_t)v.ld * sizeof(float) * 2;
+  hipError_t e = allow_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  const int threads = block_threads(lds);
+  const int grid = grid_for(v.N, threads / LPR, lds);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v.P, v.P64, v.ld, v.B, v.N, target,
+                     tau, tau_relative, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_support_kl_field(DenseView v, int32_t target, double tau, int tau_relative,
+                                   float* out, hipStream_t s) {
+  const int64_t nv = v.ld / 4;
+  if (nv >= 256) return support_launch<64>(v, target, tau, tau_relative, out, s);
+  if (nv >= 128) return support_launch<32>(v, target, tau, tau_relative, out, s);
+  return support_launch<16>(v, target, tau, tau_relative, out, s);
 }
 
 template <int LPR, int KIND>

@@ -1,0 +1,198 @@
+"""GPU on-demand walks (distances evaluated only where the path needs them,
+Section V) and the KL over the truncated target support (Section V,
+"Precision"), against the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+from conftest import normwise, within_bound
+from oracle import divergence as dv
+from oracle import path as op
+from workloads import build_config, grid_domain
+from workloads.seeds import targets_sources
+
+pytestmark = pytest.mark.gpu
+
+STATUS = {op.REACHED: "reached", op.STUCK: "stuck", op.MAX_STEPS: "max_steps"}
+KINDS = ["kl", "tv", "chi2", "hellinger"]
+
+
+def run_on_demand(k, ss, ts, kind, max_steps, **kw):
+    import torch
+    paths, lens, status, evals = k.trace_paths_on_demand(ss, ts, kind, max_steps, **kw)
+    torch.cuda.synchronize()
+    paths, lens = paths.cpu().numpy(), lens.cpu().numpy()
+    out = []
+    for i in range(len(ss)):
+        assert np.all(paths[i, lens[i]:] == -1)
+        out.append((list(paths[i, :lens[i]]), {0: "reached", 1: "stuck", 2: "max_steps"}[
+            int(status[i])], int(evals[i])))
+    return out
+
+
+@pytest.fixture(scope="module")
+def disk(gpu_ctx):
+    from paper_1708_02845_amd import Kernel
+    inst = build_config("c1")
+    k = Kernel.load_dense(gpu_ctx, inst.P, adjacency=(inst.adj_ptr, inst.adj_idx))
+    yield inst, k
+    k.free()
+
+
+@pytest.fixture(scope="module")
+def grid(gpu_ctx):
+    from paper_1708_02845_amd import Kernel
+    g = grid_domain(97, 3, (0.1, 0.25), config_id=31)
+    P = g.poisson_kernel().astype(np.float32)
+    k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
+    yield g, P, k
+    k.free()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_disk_on_demand_paths(disk, kind):
+    inst, k = disk
+    ts, ss = targets_sources(0, inst.N, 8)
+    res = run_on_demand(k, ss, ts, kind, 4000)
+    deg = int(np.diff(inst.adj_ptr).max())
+    for (got, st, n_eval), s, t in zip(res, ss, ts):
+        ref, ref_st = op.steepest_descent_path(dv.FIELDS[kind](inst.P, int(t)), inst.adj_ptr,
+                                               inst.adj_idx, int(s), int(t), 4000)
+        assert got == ref and st == STATUS[ref_st] == "reached"
+        assert n_eval <= 1 + (len(got) - 1) * deg and n_eval < inst.N // 10
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_grid_on_demand_paths_equal_field_paths(grid, kind):
+    g, P, k = grid
+    ts, ss = targets_sources(33, g.N, 20)    # more than the inline argument limit
+    res = run_on_demand(k, ss, ts, kind, 4000)
+    P64 = P.astype(np.float64)
+    for i, ((got, st, _), s, t) in enumerate(zip(res, ss, ts)):
+        if i < 6:
+            ref, ref_st = op.steepest_descent_path(dv.FIELDS[kind](P64, int(t)), g.adj_ptr,
+                                                   g.adj_idx, int(s), int(t), 4000)
+            assert got == ref and st == STATUS[ref_st]
+        field_path, field_st, _ = k.plan_path(int(s), int(t), kind, 4000)
+        assert got == field_path and st == field_st
+
+
+def test_step_cap_and_source_equals_target(grid):
+    g, P, k = grid
+    (got, st, n), = run_on_demand(k, [g.N - 10], [10], "kl", 3)
+    ref, ref_st = op.steepest_descent_path(dv.kl_field(P.astype(np.float64), 10), g.adj_ptr,
+                                           g.adj_idx, g.N - 10, 10, 3)
+    assert got == ref and len(got) == 4 and st == STATUS[ref_st] == "max_steps"
+    (got, st, n), = run_on_demand(k, [10], [10], "tv", 5)
+    assert got == [10] and st == "reached" and n == 1
+
+
+@pytest.mark.parametrize("tau,relative", [(1e-3, True), (1e-2, True), (1e-4, False)])
+def test_on_demand_target_support_kl(grid, tau, relative):
+    g, P, k = grid
+    ts, ss = targets_sources(34, g.N, 5)
+    res = run_on_demand(k, ss, ts, "kl", 4000, target_tau=tau, target_tau_relative=relative)
+    P64 = P.astype(np.float64)
+    for (got, st, _), s, t in zip(res, ss, ts):
+        f = dv.kl_support_field(P64, int(t), tau, relative)
+        ref, ref_st = op.steepest_descent_path(f, g.adj_ptr, g.adj_idx, int(s), int(t), 4000)
+        assert got == ref and st == STATUS[ref_st]
+
+
+def test_on_demand_on_truncated_handle(gpu_ctx, grid):
+    from paper_1708_02845_amd import Kernel
+    g, P, _ = grid
+    tau = 1e-3
+    kc = Kernel.load_dense(gpu_ctx, P, tau=tau, adjacency=(g.adj_ptr, g.adj_idx))
+    try:
+        ts, ss = targets_sources(35, g.N, 4)
+        P64 = P.astype(np.float64)
+        Pt, thr = dv.truncate(P64, tau, True)
+        for kind in ("kl", "tv"):
+            res = run_on_demand(kc, ss, ts, kind, 4000)
+            for (got, st, _), s, t in zip(res, ss, ts):
+                f = (dv.kl_trunc_field(Pt, int(t), thr) if kind == "kl"
+                     else dv.tv_trunc_field(Pt, int(t)))
+                ref, ref_st = op.steepest_descent_path(f, g.adj_ptr, g.adj_idx, int(s), int(t),
+                                                       4000)
+                assert got == ref and st == STATUS[ref_st]
+    finally:
+        kc.free()
+
+
+def test_on_demand_rejects_bad_arguments(gpu_ctx, grid):
+    from paper_1708_02845_amd import DDError, Kernel
+    g, P, k = grid
+    with pytest.raises(DDError, match="DD_EINVAL"):
+        k.trace_paths_on_demand([0], [5], "tv", 10, target_tau=1e-3)
+    with pytest.raises(DDError, match="DD_EINVAL"):
+        k.trace_paths_on_demand([0], [g.N], "kl", 10)
+    with pytest.raises(DDError, match="DD_EINVAL"):
+        k.trace_paths_on_demand([0], [5], "kl", 10, target_tau=-1.0)
+    kn = Kernel.load_dense(gpu_ctx, P)
+    try:
+        with pytest.raises(DDError, match="without adjacency"):
+            kn.trace_paths_on_demand([0], [5], "kl", 10)
+    finally:
+        kn.free()
+
+
+# ----------------------------------------------------------------- support KL
+
+def test_support_kl_tau_zero_is_the_kl_field(grid):
+    g, P, k = grid
+    for t in (0, 777, g.N - 1):
+        a, ba = k.support_kl_field(t, 0.0)
+        b, bb = k.field(t, "kl")
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()) and ba == bb
+
+
+@pytest.mark.parametrize("tau,relative", [(1e-4, True), (1e-2, True), (0.3, True), (1e-4, False)])
+def test_support_kl_matches_oracle(grid, tau, relative):
+    g, P, k = grid
+    P64 = P.astype(np.float64)
+    for t in (5, 1500, g.N - 3):
+        d, b = k.support_kl_field(t, tau, relative)
+        d = d.cpu().numpy()
+        ref = dv.kl_support_field(P64, t, tau, relative)
+        assert d[t] == 0.0
+        assert normwise(d, ref) <= 1e-5 and within_bound(d, ref, b)
+
+
+def test_support_kl_fp64_input(disk):
+    inst, k = disk
+    t = int(targets_sources(0, inst.N, 1)[0][0])
+    d, b = k.support_kl_field(t, 1e-2)
+    ref = dv.kl_support_field(inst.P, t, 1e-2)
+    d = d.cpu().numpy()
+    assert normwise(d, ref) <= 1e-5 and within_bound(d, ref, b)
+
+
+def test_support_kl_full_size_257(gpu_ctx):
+    from paper_1708_02845_amd import Kernel
+    g = build_config("c2")
+    P = g.poisson_kernel(dtype=np.float32)
+    k = Kernel.load_dense(gpu_ctx, P)
+    try:
+        t = int(targets_sources(1, g.N, 1)[0][0])
+        for tau in (1e-6, 1e-3):
+            d, b = k.support_kl_field(t, tau)
+            ref = dv.kl_support_field(P.astype(np.float64), t, tau)
+            d = d.cpu().numpy()
+            assert normwise(d, ref) <= 1e-5 and within_bound(d, ref, b)
+    finally:
+        k.free()
+
+
+def test_support_kl_rejects_bad_arguments(gpu_ctx, grid):
+    from paper_1708_02845_amd import DDError, Kernel
+    g, P, k = grid
+    for bad in (-1.0, float("nan"), 2.0):
+        with pytest.raises(DDError, match="DD_EINVAL"):
+            k.support_kl_field(0, bad)
+    kc = Kernel.load_dense(gpu_ctx, P, tau=1e-3)
+    try:
+        with pytest.raises(DDError, match="dense handle"):
+            kc.support_kl_field(0, 1e-3)
+    finally:
+        kc.free()
