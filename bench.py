@@ -229,10 +229,17 @@ def cpu_baseline(P32, tau, t, s, adj, max_steps, entries_per_step):
         el = time.perf_counter() - t0
         if el >= 10.0 or reps >= 4:
             break
+    # the paper's CPU mode: KL distances only at the vertices the path needs
+    t1 = time.perf_counter()
+    path, _, n_eval = op.steepest_descent_path_lazy(
+        lambda xs: dv.distances(P64, t, xs, "kl"), adj[0], adj[1], s, t, max_steps)
+    lazy_ms = 1000.0 * (time.perf_counter() - t1)
     return {"value": entries_per_step * reps / el, "unit": "entries/s", "cores": 1,
             "kind": "oracle",
             "sample": f"{reps} full step(s) of this workload (5 fields + 2 paths), FP64 NumPy "
-                      f"on one core, {el:.1f} s"}
+                      f"on one core, {el:.1f} s",
+            "path_only_kl": {"ms_per_query": round(lazy_ms, 2), "rows_evaluated": n_eval,
+                             "path_vertices": len(path)}}
 
 
 class Timer:
@@ -459,6 +466,39 @@ def main():
         rows[f"a6_paths_kl_T{T}"] = {"avg_us": round(us, 2), "paths_per_s": round(T / (us * 1e-6), 1),
                                      "mean_vertices": float(lens.mean()),
                                      "fp64_rechecks": int(res[3].sum().item())}
+        # on-demand walks: FP64 distances only where the path needs them
+        for TT in (1, T):
+            for _ in range(2):
+                kd.trace_paths_on_demand(ss[:TT], ts[:TT], "kl", args.max_steps)
+            torch.cuda.synchronize()
+            for _ in range(5):
+                res = tm.run(f"ondemand_T{TT}",
+                             lambda: kd.trace_paths_on_demand(ss[:TT], ts[:TT], "kl",
+                                                              args.max_steps), True)
+            torch.cuda.synchronize()
+            us = tm.avg_us(f"ondemand_T{TT}")
+            rows[f"on_demand_paths_kl_T{TT}"] = {
+                "avg_us": round(us, 2), "paths_per_s": round(TT / (us * 1e-6), 1),
+                "mean_vertices": float(res[1].float().mean().item()),
+                "rows_evaluated": int(res[3].sum().item())}
+        # KL over the truncated target support (rows of x exact)
+        prow = np.asarray(P[t], dtype=np.float64)[np.asarray(P.max(axis=0) > 0)]
+        for tau_s in (1e-3, 1e-6):
+            kd.support_kl_field(t, tau_s, out=f[0])
+            torch.cuda.synchronize()
+            for _ in range(20):
+                tm.run(f"support_{tau_s}", lambda: kd.support_kl_field(t, tau_s, out=f[0]), True)
+            torch.cuda.synchronize()
+            us = tm.avg_us(f"support_{tau_s}")
+            keep = (prow > 0) & (prow >= tau_s * prow.max())
+            pieces = np.zeros((B + 3) // 4 * 4, dtype=bool)
+            pieces[:B] = keep
+            npieces = int(pieces.reshape(-1, 4).any(axis=1).sum())
+            byts = N * npieces * 16 + N * 4
+            rows[f"support_kl_tau{tau_s:g}"] = {
+                "avg_us": round(us, 3), "support_frac": round(float(keep.mean()), 4),
+                "alg_bytes": byts, "GB/s": round(gbs(byts, us), 1),
+                "frac": round(gbs(byts, us) / HBM_PEAK_GBS, 4)}
         # more f-divergences on the same streaming pass (chi-squared, Hellinger)
         for kind in ("chi2", "hellinger"):
             kd.field(t, kind, out=f[0])
