@@ -232,6 +232,38 @@ dd_status dd_trace_paths_on_demand(dd_kernel* k, int32_t T, const int32_t* sourc
 dd_status dd_support_kl_field(dd_kernel* k, int32_t target, double tau, int32_t tau_relative,
                               float* out_dev, dd_error_bound* bound, void* stream);
 
+/* Attaches the triangle mesh of the interior for triangle-based paths.
+ *   faces  host [n_faces][3] int32 vertex ids in [0, N) (interior-local, as
+ *          the rows of the kernel), any orientation (stored counter-clockwise);
+ *          only triangles whose three vertices are interior belong here
+ *   xy     host [N][2] FP64 vertex coordinates
+ * Zero-area faces, repeated vertices, an edge shared by more than two faces
+ * or a vertex in more than 64 faces give DD_EINVAL.  Replaces an earlier mesh.
+ * Synchronous. */
+dd_status dd_attach_mesh(dd_kernel* k, int32_t n_faces, const int32_t* faces, const double* xy);
+
+/* Triangle-based steepest-descent paths on precomputed fields (Section IV,
+ * "Gradient-descent path generation", the method of the paper's figures):
+ * the field is linear on each triangle; from the source the descent
+ * direction of an incident triangle that points into it is followed across
+ * triangles; at a vertex with no such triangle the path takes the steepest
+ * decreasing incident edge; where the next triangle is missing or its descent
+ * direction points back, it slides along the edge to the lower endpoint; an
+ * edge incident on the target ends the path at the target.  Geometry in FP64
+ * on the given FP32 field values.
+ *   fields_dev  device [T][N] FP32
+ *   points_dev  device [T][max_steps+1][2] FP64 path points (0 past the end)
+ *   where_dev   device [T][max_steps+1][2] int32: (v, -1) for vertex v, (a, b)
+ *               with a < b for a point inside edge ab, (-1, -1) past the end
+ *   len_dev     device [T] points per path (source included)
+ *   status_dev  device [T] dd_path_status
+ * Needs the mesh (dd_attach_mesh) and the adjacency.  Asynchronous on
+ * `stream`. */
+dd_status dd_trace_paths_triangles(dd_kernel* k, int32_t T, const int32_t* sources,
+                                   const int32_t* targets, const float* fields_dev,
+                                   int32_t max_steps, double* points_dev, int32_t* where_dev,
+                                   int32_t* len_dev, int32_t* status_dev, void* stream);
+
 /* Spurious local minima of T fields (Section V, "Low resolution
  * discretizations"): a vertex v other than the target is a local minimum when
  * no neighbour u has d(u) < d(v).  Each vertex is classified against the

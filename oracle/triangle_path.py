@@ -13,9 +13,10 @@ where the paper is silent (listed with the others in the design notes):
 
 * at a vertex, among the incident triangles whose descent direction points
   strictly into the triangle, the one with the largest |g| is followed (ties:
-  lowest triangle index).  With none, the path moves along the incident edge
-  with the largest decrease per unit length to its other end (ties: lowest
-  vertex id), and stops (STUCK) when no incident edge decreases;
+  lowest triangle index; |g| is compared through |g|^2).  With none, the path
+  moves along the incident edge with the largest decrease per unit length
+  (compared through its square) to its other end (ties: lowest vertex id), and
+  stops (STUCK) when no incident edge decreases;
 * on an edge, when the triangle on the far side does not exist or its descent
   direction does not point into it, the path slides along the edge to the
   endpoint with the lower value (ties: lowest id);
@@ -128,7 +129,7 @@ def triangle_path(mesh, d, adj_ptr, adj_idx, source, target, max_steps):
                 a, b = fa[(r + 1) % 3], fa[(r + 2) % 3]
                 w = -mesh.gradient(f, d)
                 if cross(xy[a] - xy[v], w) > 0 and cross(w, xy[b] - xy[v]) > 0:
-                    n = float(np.hypot(w[0], w[1]))
+                    n = w[0] * w[0] + w[1] * w[1]      # |g|^2 orders as |g|
                     if n > best_norm:
                         best, best_norm = f, n
             if best >= 0:
@@ -146,7 +147,9 @@ def triangle_path(mesh, d, adj_ptr, adj_idx, source, target, max_steps):
                 u = int(u)
                 if not d[u] < d[v]:
                     continue
-                slope = (d[v] - d[u]) / float(np.hypot(*(xy[u] - xy[v])))
+                e = xy[u] - xy[v]
+                dd = d[v] - d[u]
+                slope = dd * dd / (e[0] * e[0] + e[1] * e[1])   # squared: same order
                 if slope > bslope or (slope == bslope and bu >= 0 and u < bu):
                     bu, bslope = u, slope
             if bu < 0:

@@ -71,6 +71,10 @@ EXPORTS = {
                                            C.c_void_p]),
     "dd_support_kl_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_void_p,
                                       C.POINTER(dd_error_bound), C.c_void_p]),
+    "dd_attach_mesh": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "dd_trace_paths_triangles": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p, C.c_void_p]),
     "dd_free_kernel": (C.c_int, [C.c_void_p]),
     "dd_last_error": (C.c_char_p, []),
 }

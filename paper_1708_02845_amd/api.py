@@ -235,6 +235,35 @@ class Kernel:
                                               _stream_handle(stream)))
         return out, bound_tuple(b)
 
+    def attach_mesh(self, faces, xy):
+        """Triangle mesh of the interior: faces [F, 3] interior-local ids, xy [N, 2]."""
+        f = np.ascontiguousarray(faces, dtype=np.int32)
+        c = np.ascontiguousarray(xy, dtype=np.float64)
+        if f.ndim != 2 or f.shape[1] != 3 or c.shape != (self.N, 2):
+            raise ValueError("faces must be [F, 3] and xy [N, 2]")
+        L.check(self._lib.dd_attach_mesh(self._h, int(f.shape[0]), C.c_void_p(f.ctypes.data),
+                                         C.c_void_p(c.ctypes.data)))
+
+    def trace_paths_triangles(self, sources, targets, fields, max_steps, stream=None):
+        """Device tensors (points [T, max_steps+1, 2] f64, where [T, max_steps+1, 2] i32,
+        len [T], status [T]) of triangle-based paths on the given fields."""
+        torch = _torch()
+        s = np.ascontiguousarray(sources, dtype=np.int32)
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        T = len(s)
+        dev = f"cuda:{self.ctx.device}"
+        if not fields.is_contiguous() or fields.dtype != torch.float32:
+            raise ValueError("fields must be contiguous float32")
+        pts = torch.empty((T, max_steps + 1, 2), dtype=torch.float64, device=dev)
+        wh = torch.empty((T, max_steps + 1, 2), dtype=torch.int32, device=dev)
+        info = torch.empty((2, T), dtype=torch.int32, device=dev)
+        L.check(self._lib.dd_trace_paths_triangles(
+            self._h, int(T), C.c_void_p(s.ctypes.data), C.c_void_p(t.ctypes.data),
+            C.c_void_p(fields.data_ptr()), int(max_steps), C.c_void_p(pts.data_ptr()),
+            C.c_void_p(wh.data_ptr()), C.c_void_p(info[0].data_ptr()),
+            C.c_void_p(info[1].data_ptr()), _stream_handle(stream)))
+        return pts, wh, info[0], info[1]
+
     def local_minima(self, targets, fields, bounds, stream=None):
         """Device tensors (classes uint8 [T, N], counts int32 [T, 2]) of the
         local-minimum census: 0 not a minimum, 1 certain minimum, 2 undecided."""

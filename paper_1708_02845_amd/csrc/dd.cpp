@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "dd_internal.h"
@@ -114,11 +115,15 @@ struct dd_kernel {
   DevBuf adj;          // [N][adj_w] int32, -1 padded
   int32_t adj_w = 0;
   int has_adj = 0;
+  // triangle mesh of the interior (triangle-based paths)
+  DevBuf mesh_faces, mesh_xy, mesh_vf;
+  int32_t mesh_F = 0, mesh_vf_w = 0;
+  int has_mesh = 0;
 
   size_t footprint() const {
     return P32.bytes + P64.bytes + H.bytes + L32.bytes + Lhi.bytes + Llo.bytes + Off.bytes +
            start.bytes + len.bytes + col.bytes + val.bytes + val64.bytes + phi.bytes + lphi.bytes +
-           adj.bytes;
+           adj.bytes + mesh_faces.bytes + mesh_xy.bytes + mesh_vf.bytes;
   }
   dd::DenseView dense() const {
     return dd::DenseView{P32.as<const float>(), P64.as<const double>(), ld, N, B};
@@ -893,6 +898,116 @@ dd_status dd_support_kl_field(dd_kernel* k, int32_t target, double tau, int32_t 
                                      as_stream(stream)));
   // the terms are a subset of eq. (35)'s, so the dense KL bound holds
   if (bound) *bound = field_bound(k, DD_KL, target);
+  return DD_OK;
+}
+
+dd_status dd_attach_mesh(dd_kernel* k, int32_t n_faces, const int32_t* faces, const double* xy) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (n_faces <= 0 || !faces || !xy) return fail(DD_EINVAL, "n_faces=%d or a null pointer", n_faces);
+  const int32_t N = k->N;
+  for (int64_t i = 0; i < 2 * (int64_t)N; ++i)
+    if (!std::isfinite(xy[i])) return fail(DD_EINVAL, "xy[%lld] is not finite", (long long)i);
+  std::vector<int32_t> rec((size_t)n_faces * 8, -1);
+  std::unordered_map<uint64_t, std::pair<int32_t, int32_t>> edges;   // edge -> (face, k)
+  edges.reserve((size_t)n_faces * 2);
+  std::vector<int32_t> deg(N, 0);
+  for (int32_t f = 0; f < n_faces; ++f) {
+    int32_t v[3] = {faces[3 * (int64_t)f], faces[3 * (int64_t)f + 1], faces[3 * (int64_t)f + 2]};
+    for (int j = 0; j < 3; ++j)
+      if (v[j] < 0 || v[j] >= N) return fail(DD_EINVAL, "face %d: vertex %d not in [0, %d)", f, v[j], N);
+    if (v[0] == v[1] || v[1] == v[2] || v[2] == v[0])
+      return fail(DD_EINVAL, "face %d repeats a vertex", f);
+    const double ax = xy[2 * v[1]] - xy[2 * v[0]], ay = xy[2 * v[1] + 1] - xy[2 * v[0] + 1];
+    const double bx = xy[2 * v[2]] - xy[2 * v[0]], by = xy[2 * v[2] + 1] - xy[2 * v[0] + 1];
+    const double area = ax * by - ay * bx;
+    if (!(area != 0.0)) return fail(DD_EINVAL, "face %d has zero area", f);
+    if (area < 0) std::swap(v[1], v[2]);
+    for (int j = 0; j < 3; ++j) {
+      rec[8 * (size_t)f + j] = v[j];
+      ++deg[v[j]];
+    }
+  }
+  for (int32_t f = 0; f < n_faces; ++f)
+    for (int j = 0; j < 3; ++j) {
+      const uint32_t a = (uint32_t)rec[8 * (size_t)f + j];
+      const uint32_t b = (uint32_t)rec[8 * (size_t)f + (j + 1) % 3];
+      const uint64_t key = ((uint64_t)std::min(a, b) << 32) | std::max(a, b);
+      auto it = edges.find(key);
+      if (it == edges.end()) {
+        edges.emplace(key, std::make_pair(f, j));
+      } else {
+        const int32_t g = it->second.first, kg = it->second.second;
+        if (g < 0 || rec[8 * (size_t)g + 3 + kg] >= 0)
+          return fail(DD_EINVAL, "edge %u-%u is shared by more than two faces", a, b);
+        rec[8 * (size_t)g + 3 + kg] = f;
+        rec[8 * (size_t)f + 3 + j] = g;
+      }
+    }
+  int32_t w = 1;
+  for (int32_t v = 0; v < N; ++v) w = std::max(w, deg[v]);
+  if (w > kMaxDegree) return fail(DD_EINVAL, "a vertex is in %d faces (limit %d)", w, kMaxDegree);
+  std::vector<int32_t> vf((size_t)N * w, -1), fill(N, 0);
+  for (int32_t f = 0; f < n_faces; ++f)   // ascending face index per vertex
+    for (int j = 0; j < 3; ++j) {
+      const int32_t v = rec[8 * (size_t)f + j];
+      vf[(size_t)v * w + fill[v]++] = f;
+    }
+  HIP_OR(hipSetDevice(k->ctx->device));
+  HIP_OR(k->mesh_faces.alloc(4 * rec.size()));
+  HIP_OR(hipMemcpy(k->mesh_faces.p, rec.data(), 4 * rec.size(), hipMemcpyHostToDevice));
+  HIP_OR(k->mesh_xy.alloc(16 * (size_t)N));
+  HIP_OR(hipMemcpy(k->mesh_xy.p, xy, 16 * (size_t)N, hipMemcpyHostToDevice));
+  HIP_OR(k->mesh_vf.alloc(4 * vf.size()));
+  HIP_OR(hipMemcpy(k->mesh_vf.p, vf.data(), 4 * vf.size(), hipMemcpyHostToDevice));
+  k->mesh_F = n_faces;
+  k->mesh_vf_w = w;
+  k->has_mesh = 1;
+  return DD_OK;
+}
+
+dd_status dd_trace_paths_triangles(dd_kernel* k, int32_t T, const int32_t* sources,
+                                   const int32_t* targets, const float* fields_dev,
+                                   int32_t max_steps, double* points_dev, int32_t* where_dev,
+                                   int32_t* len_dev, int32_t* status_dev, void* stream) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (!k->has_mesh) return fail(DD_EINVAL, "no mesh attached (dd_attach_mesh)");
+  if (!k->has_adj) return fail(DD_EINVAL, "kernel was loaded without adjacency");
+  if (T <= 0 || !sources || !targets || !fields_dev || !points_dev || !where_dev || !len_dev ||
+      !status_dev)
+    return fail(DD_EINVAL, "T=%d or a required pointer is null", T);
+  if (max_steps < 0) return fail(DD_EINVAL, "max_steps=%d", max_steps);
+  for (int32_t i = 0; i < T; ++i)
+    if (sources[i] < 0 || sources[i] >= k->N || targets[i] < 0 || targets[i] >= k->N)
+      return fail(DD_EINVAL, "path %d: source %d / target %d not in [0, %d)", i, sources[i],
+                  targets[i], k->N);
+  HIP_OR(hipSetDevice(k->ctx->device));
+  hipStream_t s = as_stream(stream);
+  AsyncBuf ws(s);
+  HIP_OR(ws.alloc(8 * (size_t)T));
+  std::vector<int32_t> host(2 * (size_t)T);
+  std::memcpy(host.data(), sources, 4 * (size_t)T);
+  std::memcpy(host.data() + T, targets, 4 * (size_t)T);
+  // pageable source: the copy is staged before hipMemcpyAsync returns
+  HIP_OR(hipMemcpyAsync(ws.p, host.data(), 8 * (size_t)T, hipMemcpyHostToDevice, s));
+  dd::TriArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.faces = k->mesh_faces.as<const int32_t>();
+  a.xy = k->mesh_xy.as<const double>();
+  a.vfaces = k->mesh_vf.as<const int32_t>();
+  a.vf_w = k->mesh_vf_w;
+  a.adj = k->adj.as<const int32_t>();
+  a.adj_w = k->adj_w;
+  a.fields = fields_dev;
+  a.sources = ws.as<const int32_t>();
+  a.targets = ws.as<const int32_t>() + T;
+  a.points = points_dev;
+  a.where = where_dev;
+  a.len = len_dev;
+  a.status = status_dev;
+  a.T = T;
+  a.N = k->N;
+  a.max_steps = max_steps;
+  HIP_OR(dd::launch_triangle_paths(a, s));
   return DD_OK;
 }
 

@@ -127,6 +127,26 @@ hipError_t launch_support_kl_field(DenseView v, int32_t target, double tau, int 
 hipError_t launch_local_minima(PathArgs a, int32_t N, uint8_t* cls, int32_t* counts,
                                hipStream_t s);
 
+// Triangle-based paths (tri.hip).
+struct TriArgs {
+  const int32_t* faces;     // [F][8]: v0 v1 v2 counter-clockwise, then the face across
+                            // edge (v_k, v_k+1) for k = 0..2 (-1: none), 2 unused
+  const double* xy;         // [N][2]
+  const int32_t* vfaces;    // [N][vf_w] incident faces ascending, -1 padded
+  int32_t vf_w;
+  const int32_t* adj;       // [N][adj_w] neighbour ids, -1 padded
+  int32_t adj_w;
+  const float* fields;      // [T][N]
+  const int32_t* sources;   // device [T]
+  const int32_t* targets;   // device [T]
+  double* points;           // [T][max_steps+1][2]
+  int32_t* where;           // [T][max_steps+1][2]
+  int32_t* len;             // [T]
+  int32_t* status;          // [T]
+  int32_t T, N, max_steps;
+};
+hipError_t launch_triangle_paths(TriArgs a, hipStream_t s);
+
 int num_cus();
 
 }  // namespace dd

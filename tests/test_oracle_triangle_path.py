@@ -14,12 +14,7 @@ from workloads.seeds import targets_sources
 
 
 def grid_mesh(g):
-    """Walkable triangles of a grid domain in interior-local ids, and coordinates."""
-    loc = -np.ones(g.G * g.G, dtype=np.int64)
-    loc[g.interior] = np.arange(g.N)
-    f = loc[g.triangles]
-    f = f[(f >= 0).all(axis=1)]
-    return tp.Mesh(f, g.xy()[g.interior])
+    return tp.Mesh(*g.interior_mesh())
 
 
 def test_hand_traced_square():
@@ -95,7 +90,7 @@ def test_disk_triangle_paths_follow_geodesics_better_than_edge_paths(kind):
     # Appendix 2.2: descent paths on the disk are hyperbolic geodesics; Fig. 2:
     # triangle-based paths are smoother than edge-based ones
     inst = build_config("c1")
-    mesh = tp.Mesh(inst.triangles, np.column_stack([inst.z.real, inst.z.imag]))
+    mesh = tp.Mesh(*inst.interior_mesh())
     ts, ss = targets_sources(0, inst.N, 4)
     gap_tri, gap_edge = [], []
     for s, t in zip(ss, ts):

@@ -24,6 +24,10 @@ class DiskInstance:
     adj_idx: np.ndarray    # int32 [nnz]
     triangles: np.ndarray  # int64 [F, 3]
 
+    def interior_mesh(self):
+        """(faces [F, 3], xy [N, 2]) of the Delaunay triangulation of the points."""
+        return self.triangles, np.column_stack([self.z.real, self.z.imag])
+
     @property
     def N(self):
         return self.P.shape[0]

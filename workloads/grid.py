@@ -58,6 +58,14 @@ class GridDomain:
         g = np.arange(self.G * self.G)
         return np.column_stack([(g % self.G) * self.h, (g // self.G) * self.h])
 
+    def interior_mesh(self):
+        """(faces [F, 3] interior-local ids, xy [N, 2]): the triangles whose three
+        vertices are interior, and the interior vertex coordinates."""
+        loc = -np.ones(self.G * self.G, dtype=np.int64)
+        loc[self.interior] = np.arange(self.N)
+        f = loc[self.triangles]
+        return f[(f >= 0).all(axis=1)], self.xy()[self.interior]
+
     def poisson_kernel(self, dtype=np.float64, workers=None, progress=None):
         if self._P is None or self._P.dtype != dtype:
             self._P = harmonic_measure_5pt(self, dtype=dtype, workers=workers, progress=progress)
