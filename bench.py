@@ -466,6 +466,19 @@ def main():
         rows[f"a6_paths_kl_T{T}"] = {"avg_us": round(us, 2), "paths_per_s": round(T / (us * 1e-6), 1),
                                      "mean_vertices": float(lens.mean()),
                                      "fp64_rechecks": int(res[3].sum().item())}
+        # triangle-based paths (the method of the paper's figures) on the same fields
+        kd.attach_mesh(*g.interior_mesh())
+        for _ in range(2):
+            kd.trace_paths_triangles(ss, ts, D, 20000)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            res = tm.run("tri_T", lambda: kd.trace_paths_triangles(ss, ts, D, 20000), True)
+        torch.cuda.synchronize()
+        us = tm.avg_us("tri_T")
+        rows[f"triangle_paths_kl_T{T}"] = {
+            "avg_us": round(us, 2), "paths_per_s": round(T / (us * 1e-6), 1),
+            "mean_points": float(res[2].float().mean().item()),
+            "reached": int((res[3] == 0).sum().item())}
         # on-demand walks: FP64 distances only where the path needs them
         for TT in (1, T):
             for _ in range(2):

@@ -12,7 +12,9 @@
   Appendix table lists (1 + r^2)/(1 - r^2), which is off by the constant 1:
   g(0) must be 0); for f(x) = (sqrt x - 1)^2 it is
   2 - (4/pi) sqrt(1 - r^2) K(r), K the complete elliptic integral of the first
-  kind with modulus r (scipy's ellipk takes the parameter r^2).
+  kind with modulus r (scipy's ellipk takes the parameter r^2).  For
+  f(x) = |1 - x|^k with even k and for the alpha-divergences, g follows from
+  the moments (1/2pi) int h^s dphi = (1 - r^2)^s 2F1(s, s; 1; r^2).
 * Gradient-descent paths on the disk are hyperbolic geodesics: arcs of the
   circle through source and target orthogonal to the unit circle (Appendix
   Section 2.2), which also passes through 1/conj(source).
@@ -48,6 +50,27 @@ def hellinger_closed(x, t):
     from scipy.special import ellipk
     r = rho(x, t)
     return 2.0 - (4.0 / np.pi) * np.sqrt(1.0 - r * r) * ellipk(r * r)
+
+
+def _poisson_moment(i, r):
+    """(1/2pi) int h(r, phi)^i dphi = (1 - r^2)^i 2F1(i, i; 1; r^2), h the disk
+    Poisson kernel ratio (1 - r^2) / (1 - 2 r cos phi + r^2)."""
+    from scipy.special import hyp2f1
+    return (1.0 - r * r) ** i * hyp2f1(i, i, 1.0, r * r)
+
+
+def power_closed(x, t, k):
+    """f(x) = |1 - x|^k for even k: binomial expansion of (1 - h)^k (Theorem A5)."""
+    from scipy.special import comb
+    assert k % 2 == 0
+    r = rho(x, t)
+    return sum(comb(k, i, exact=True) * (-1) ** i * _poisson_moment(i, r) for i in range(k + 1))
+
+
+def alpha_closed(x, t, alpha):
+    """alpha-divergence: 4/(1-a^2) (1 - (1/2pi) int h^s), s = (1+a)/2 (Theorem A5)."""
+    s = (1.0 + alpha) / 2.0
+    return 4.0 / (1.0 - alpha * alpha) * (1.0 - _poisson_moment(s, rho(x, t)))
 
 
 def geodesic_distance(points, s, t):

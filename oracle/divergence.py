@@ -14,6 +14,10 @@ Two more members of the f-divergence family named in the paper's conclusion
 * chi-squared, f(x) = (x - 1)^2:    d(x) = sum_b (q_b - p_b)^2 / p_b   (+inf if some
                                     p_b = 0 < q_b)
 * Hellinger,   f(x) = (sqrt x - 1)^2: d(x) = sum_b (sqrt q_b - sqrt p_b)^2
+* power k,     f(x) = |1 - x|^k, integer k >= 1 (k = 1 is TV, k = 2 chi-squared):
+               d(x) = sum_b |q_b - p_b|^k / p_b^(k-1)   (+inf if some p_b = 0 < q_b, k > 1)
+* alpha,       f(x) = 4/(1 - a^2) (1 - x^((1+a)/2)), a != +-1:
+               d(x) = 4/(1 - a^2) sum_b (p_b - p_b^((1-a)/2) q_b^((1+a)/2))
 
 Truncated (sparsified) kernels follow the sparsification remark of Section V
 ("Precision"): entries of a row below a threshold are dropped, with no
@@ -120,6 +124,14 @@ def kl_support_field(P, t, tau, relative=True):
 FIELDS = {"tv": tv_field, "kl": kl_field, "chi2": chi2_field, "hellinger": hellinger_field}
 
 
+def field(P, t, kind):
+    """Field of a kind name: "tv", "kl", "chi2", "hellinger", ("power", k),
+    ("alpha", a)."""
+    if isinstance(kind, tuple):
+        return power_field(P, t, kind[1]) if kind[0] == "power" else alpha_field(P, t, kind[1])
+    return FIELDS[kind](P, t)
+
+
 def distances(P, t, xs, kind, tau=0.0, relative=True):
     """Distances of the rows xs to the target row t: the field functions
     applied to the stacked rows [P[t]; P[xs]] (equal to the field entries up
@@ -128,7 +140,35 @@ def distances(P, t, xs, kind, tau=0.0, relative=True):
     sub = np.vstack([P[t][None, :], P[np.asarray(xs, dtype=np.int64)]])
     if kind == "kl_s":
         return kl_support_field(sub, 0, tau, relative)[1:]
-    return FIELDS[kind](sub, 0)[1:]
+    return field(sub, 0, kind)[1:]
+
+
+def power_field(P, t, k):
+    """f(x) = |1 - x|^k (Section VI): sum_b |q_b - p_b|^k / p_b^(k-1)."""
+    P = np.asarray(P, dtype=np.float64)
+    k = int(k)
+    p = P[t]
+    sup = p > 0
+    ps = p[sup]
+    d = np.empty(P.shape[0])
+    for lo, hi in _row_chunks(P.shape[0], P.shape[1]):
+        q = P[lo:hi]
+        d[lo:hi] = (np.abs(q[:, sup] - ps[None, :]) ** k / ps[None, :] ** (k - 1)).sum(axis=1)
+        off = q[:, ~sup].sum(axis=1)     # p_b = 0: |q_b| for k = 1, +inf for k > 1 if q_b > 0
+        d[lo:hi] += off if k == 1 else np.where(off > 0, np.inf, 0.0)
+    return d
+
+
+def alpha_field(P, t, alpha):
+    """alpha-divergence (Section VI): 4/(1-a^2) sum_b (p_b - p_b^((1-a)/2) q_b^((1+a)/2))."""
+    P = np.asarray(P, dtype=np.float64)
+    a = float(alpha)
+    p = P[t]
+    d = np.empty(P.shape[0])
+    for lo, hi in _row_chunks(P.shape[0], P.shape[1]):
+        q = P[lo:hi]
+        d[lo:hi] = (p[None, :] - p[None, :] ** ((1 - a) / 2) * q ** ((1 + a) / 2)).sum(axis=1)
+    return 4.0 / (1.0 - a * a) * d
 
 
 def truncate(P, tau, relative=True):

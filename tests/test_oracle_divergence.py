@@ -234,3 +234,55 @@ def test_row_distances_equal_field_entries(grid_P):
                            rtol=1e-14, atol=0)
     assert np.allclose(dv.distances(grid_P, t, xs, "kl_s", 1e-3),
                        dv.kl_support_field(grid_P, t, 1e-3)[xs], rtol=1e-14, atol=0)
+
+
+def test_power_family_special_cases(grid_P):
+    t = 99
+    assert np.allclose(dv.power_field(grid_P, t, 1), dv.tv_field(grid_P, t), rtol=1e-13, atol=0)
+    assert np.allclose(dv.power_field(grid_P, t, 2), dv.chi2_field(grid_P, t), rtol=1e-13, atol=0)
+
+
+def test_alpha_family_special_cases(grid_P):
+    # alpha = 0 is twice the squared Hellinger distance (rows sum to 1)
+    t = 99
+    W = grid_P.sum(axis=1)
+    assert np.allclose(W, 1.0, atol=1e-12)
+    assert np.allclose(dv.alpha_field(grid_P, t, 0.0), 2 * dv.hellinger_field(grid_P, t),
+                       rtol=1e-10, atol=1e-13)
+    # alpha = 3 is half the chi-squared distance
+    assert np.allclose(dv.alpha_field(grid_P, t, 3.0), 0.5 * dv.chi2_field(grid_P, t),
+                       rtol=1e-10, atol=1e-13)
+
+
+def test_power_and_alpha_brute_force():
+    g = np.random.default_rng(17)
+    P = g.random((7, 9)) ** 2
+    P[1, 3] = 0.0
+    P /= P.sum(axis=1, keepdims=True)
+    t = 2
+    for k in (1, 3, 4):
+        d = dv.power_field(P, t, k)
+        for x in range(7):
+            s = sum(P[t, b] * abs(1 - P[x, b] / P[t, b]) ** k for b in range(9))
+            assert d[x] == pytest.approx(s, rel=1e-12, abs=1e-15)
+    for a in (-0.75, 0.25, 0.875):
+        d = dv.alpha_field(P, t, a)
+        for x in range(7):
+            s = sum(P[t, b] * 4 / (1 - a * a) * (1 - (P[x, b] / P[t, b]) ** ((1 + a) / 2))
+                    for b in range(9))
+            assert d[x] == pytest.approx(s, rel=1e-12, abs=1e-14)
+
+
+@pytest.mark.parametrize("k", range(2))
+def test_disk_power_and_alpha_closed_forms(c1, k):
+    # Theorem A5 with f(x) = |1-x|^4 and the alpha-divergences, through the
+    # Moebius map (A10) and conformal invariance (A2); moments by 2F1
+    # (the B-point rule converges more slowly for |1-x|^4, whose integrand
+    # carries fourth powers of the kernel: 1.1e-3 relative at worst here)
+    t = int(rng(0, "targets").integers(0, c1.N, size=2)[k])
+    ref = odisk.power_closed(c1.z, c1.z[t], 4)
+    got = dv.power_field(c1.P, t, 4)
+    assert np.max(np.abs(got - ref) / np.maximum(ref, 1e-3)) < 5e-3
+    for a in (-0.5, 0.25, 0.75):
+        ref = odisk.alpha_closed(c1.z, c1.z[t], a)
+        assert np.abs(dv.alpha_field(c1.P, t, a) - ref).max() < 2e-5
