@@ -62,6 +62,16 @@ typedef enum {
                        sum_b (sqrt P_xb - sqrt P_tb)^2, range [0, 2] */
 } dd_kind;
 
+/* The two families Section VI names, as kind values (dense handles only):
+ *   DD_KIND_POWER(k)         f(u) = |1 - u|^k, integer 1 <= k <= 16:
+ *                            sum_b |P_xb - P_tb|^k / P_tb^(k-1) (k = 1 is TV,
+ *                            k = 2 chi-squared; +inf as for chi-squared)
+ *   DD_KIND_ALPHA_EIGHTHS(m) alpha-divergence with alpha = m/8, -7 <= m <= 7:
+ *                            4/(1 - alpha^2) sum_b (P_tb - P_tb^((1-alpha)/2)
+ *                            P_xb^((1+alpha)/2)) (m = 0 is twice Hellinger) */
+#define DD_KIND_POWER(k) (100 + (k))
+#define DD_KIND_ALPHA_EIGHTHS(m) (208 + (m))
+
 /* Operand form of the batched-KL contraction (see dd_batch_distance_fields). */
 typedef enum {
   DD_FORM_NONE = -1,   /* do not build a batched-KL operand */

@@ -32,9 +32,21 @@ def _stream_handle(stream):
 
 
 def _kind(kind):
+    """Kind value of a name ("tv", "kl", "chi2", "hellinger"), a family tuple
+    ("power", k) with integer 1 <= k <= 16 or ("alpha", a) with a = m/8,
+    |m| <= 7, or a kind value."""
+    if isinstance(kind, tuple) and len(kind) == 2:
+        fam, val = kind
+        if fam == "power" and float(val).is_integer() and 1 <= int(val) <= 16:
+            return 100 + int(val)
+        if fam == "alpha" and float(val * 8).is_integer() and -7 <= int(val * 8) <= 7:
+            return 208 + int(val * 8)
+        raise ValueError(f"unsupported family member {kind!r}")
     try:
         return KINDS[kind.lower() if isinstance(kind, str) else kind]
-    except KeyError:
+    except (KeyError, TypeError):
+        if isinstance(kind, int) and not isinstance(kind, bool):
+            return kind      # a kind value; the library validates it
         raise ValueError(f"unknown kind {kind!r}") from None
 
 

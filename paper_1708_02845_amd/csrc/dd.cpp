@@ -213,7 +213,8 @@ dd_status check_free(size_t need) {
 // truncated one.
 dd_status check_kind(const dd_kernel* k, int32_t kind) {
   if (kind == DD_TV || kind == DD_KL) return DD_OK;
-  if (kind == DD_CHI2 || kind == DD_HELLINGER) {
+  if (kind == DD_CHI2 || kind == DD_HELLINGER || (kind >= DD_KIND_POWER(1) && kind <= DD_KIND_POWER(16)) ||
+      (kind >= DD_KIND_ALPHA_EIGHTHS(-7) && kind <= DD_KIND_ALPHA_EIGHTHS(7))) {
     if (k->is_csr) return fail(DD_EINVAL, "kind %d needs a dense handle", kind);
     return DD_OK;
   }
@@ -237,6 +238,23 @@ dd_error_bound field_bound(const dd_kernel* k, int kind, int32_t t) {
       // sum (q + p)^2 / p = chi2 + 4 sum q bounds the sum by 3u chi2 + 4u.
       b.rel = 8.0 * kU + (k->is_f64 ? 3.0 * kU : 0.0);
       b.abs = (k->is_f64 ? 4.0 * kU : 0.0) + 1e-300;
+    } else if (kind >= DD_KIND_POWER(1) && kind <= DD_KIND_POWER(16)) {
+      // |d| (|d| r)^(k-1), r = fl(1/p): about 4u per factor, sums 2u, output u.
+      // FP32 copies of FP64 rows move a term by at most k u (q + p) (|d|/p)^(k-1),
+      // in sum k u (2 d_(k-1) + d_k) <= k u (3 d + 2 W) (Hoelder).
+      const double kk = (double)(kind - DD_KIND_POWER(0));
+      b.rel = (4.0 * kk + 3.0) * kU + (k->is_f64 ? 3.0 * kk * kU : 0.0);
+      b.abs = (k->is_f64 ? 2.0 * kk * kU * W : 0.0) + 1e-300;
+    } else if (kind >= DD_KIND_ALPHA_EIGHTHS(-7) && kind <= DD_KIND_ALPHA_EIGHTHS(7)) {
+      // p (1 - z^j), z = (q fl(1/p))^(1/16) by four 1-ulp square roots, z^j by
+      // squaring: (4j + 7)u relative on p z^j, whose sum is at most
+      // (1 - s) W + s sum q <= W + 1 (weighted AM-GM), times 4/(1 - alpha^2).
+      const int j = kind - DD_KIND_ALPHA_EIGHTHS(-8);
+      const double al = (double)(kind - DD_KIND_ALPHA_EIGHTHS(0)) / 8.0;
+      const double c = 4.0 / (1.0 - al * al);
+      b.rel = 2.0 * kU;
+      b.abs = c * ((4.0 * j + 7.0) * kU * (W + 1.0) + 3.0 * kU) +
+              (k->is_f64 ? 2.0 * c * kU * (W + 1.0) : 0.0);
     } else if (kind == DD_HELLINGER) {
       // ((q - p) * rcp(sqrt q + sqrt p))^2 with 1-ulp hardware sqrt and rcp:
       // 15u per term, sums 2u, output u.  FP32 copies of FP64 rows move a

@@ -139,15 +139,36 @@ __global__ __launch_bounds__(256) void neighbor_values_kernel(PathArgs a, int32_
 // staged FP64 target row p, its logarithms lp and constants tc.  The KL
 // terms are p (log p - log q); chi-squared (q - p)^2 / p (+inf for q > 0 on
 // p = 0); Hellinger (q - p)^2 / (sqrt q + sqrt p)^2, the cancellation-free
-// form of (sqrt q - sqrt p)^2.  Truncated handles carry TV and KL only.
+// form of (sqrt q - sqrt p)^2; the power and alpha families as in term64.
+// Truncated handles carry TV and KL only.
+// Kinds: 0 TV, 1 KL, 2 chi-squared, 3 Hellinger, 100 + k the power family
+// |q - p|^k / p^(k-1), 200 + j the alpha-divergence term p (1 - (q/p)^(j/16))
+// (its factor 4/(1 - alpha^2) is applied to the sum).
 __device__ __forceinline__ double term64(int kind, double pb, double lpb, double q) {
   const double df = q - pb;
   if (kind == 0) return fabs(df);
   if (kind == 1) return pb > 0.0 ? pb * (lpb - log(q)) : 0.0;
+  if (kind > 200) return pb > 0.0 ? pb * (1.0 - pow(q / pb, (double)(kind - 200) / 16.0)) : 0.0;
   if (df == 0.0) return 0.0;
+  if (kind > 100) {
+    const int k = kind - 100;
+    if (!(pb > 0.0)) return k == 1 ? fabs(df) : __builtin_inf();
+    const double r = fabs(df) / pb;
+    double t = fabs(df);
+    for (int j = 1; j < k; ++j) t *= r;
+    return t;
+  }
   if (kind == 2) return pb > 0.0 ? df * df / pb : __builtin_inf();
   const double e = df / (sqrt(q) + sqrt(pb));
   return e * e;
+}
+
+__device__ __forceinline__ double kind_factor(int kind) {
+  if (kind > 200) {
+    const double al = (double)(kind - 208) / 8.0;
+    return 4.0 / (1.0 - al * al);
+  }
+  return 1.0;
 }
 
 // Loads are issued kU at a time per lane (indices clamped into the row, the
@@ -175,7 +196,7 @@ __device__ __noinline__ double exact_distance(const DenseView& dv, const CsrView
       for (int u = 0; u < kU; ++u)
         if (b0 + 64 * u < dv.B) acc += term64(kind, pb[u], lpb[u], q[u]);
     }
-    return wsum(acc);
+    return wsum(acc) * kind_factor(kind);
   }
   const int64_t s = cv.start[x];
   const int n = cv.len[x];

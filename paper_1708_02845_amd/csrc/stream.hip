@@ -4,6 +4,8 @@
 // KL (Section IV, eq. 35):  d(x) = sum_b p_b log(p_b / q_b), p = target row
 // chi-squared and squared Hellinger (f-divergences, Section VI):
 //   d(x) = sum_b (q_b - p_b)^2 / p_b,   d(x) = sum_b (sqrt q_b - sqrt p_b)^2
+// and the two families Section VI names: f(u) = |1 - u|^k for integer k, and
+// the alpha-divergences f(u) = 4/(1 - alpha^2) (1 - u^((1+alpha)/2)).
 //
 // Mapping (gfx950): a group of LPR lanes (16, 32 or 64) owns one row x and
 // sweeps it with 16-byte loads, UNROLL loads in flight per lane; the target
@@ -54,16 +56,43 @@ __device__ __forceinline__ float hel_term(float p, float sp, float q) {
   return d != 0.f ? e * e : 0.f;
 }
 
-// Second LDS array per kind: log2 p (KL), 1/p (chi-squared), sqrt p (Hellinger).
+// f(u) = |1 - u|^k, integer k >= 1: |q - p|^k / p^(k-1) as |d| (|d| / p)^(k-1)
+// with r = 1/p (+inf for p = 0); 0 whenever q == p.
+__device__ __forceinline__ float power_term(float p, float r, float q, int k) {
+  const float d = fabsf(q - p);
+  const float x = d * r;
+  float t = d;
+  for (int j = 1; j < k; ++j) t *= x;
+  return d != 0.f ? t : 0.f;
+}
+
+// alpha-divergence with (1 + alpha)/2 = j/16: p (1 - (q/p)^(j/16)), the
+// sixteenth root by four hardware square roots and the power by squaring;
+// exactly 0 when q == p.  The factor 4/(1 - alpha^2) is applied per row.
+__device__ __forceinline__ float alpha_term(float p, float r, float q, int j) {
+  float z = q * r;
+  z = __builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(z))));
+  float pw = 1.f;
+  for (int e = j; e; e >>= 1) {
+    if (e & 1) pw *= z;
+    z *= z;
+  }
+  return p > 0.f ? p * (1.f - pw) : 0.f;
+}
+
+// Second LDS array per kind: log2 p (KL), 1/p (chi-squared, power, alpha),
+// sqrt p (Hellinger).
 template <int KIND>
 __device__ __forceinline__ float stage_aux(float p) {
   if (KIND == 1) return p > 0.f ? hw_log2(p) : 0.f;
-  if (KIND == 2) return p > 0.f ? 1.0f / p : __builtin_inff();
+  if (KIND == 2 || KIND == 4) return p > 0.f ? 1.0f / p : __builtin_inff();
+  if (KIND == 5) return p > 0.f ? 1.0f / p : 0.f;
   return sqrtf(p);
 }
 
 template <int KIND>
-__device__ __forceinline__ float term4(const float4& p, const float4& a, const float4& q) {
+__device__ __forceinline__ float term4(const float4& p, const float4& a, const float4& q,
+                                       int param) {
   if (KIND == 0)
     return (fabsf(p.x - q.x) + fabsf(p.y - q.y)) + (fabsf(p.z - q.z) + fabsf(p.w - q.w));
   if (KIND == 1)
@@ -72,13 +101,31 @@ __device__ __forceinline__ float term4(const float4& p, const float4& a, const f
   if (KIND == 2)
     return (chi2_term(p.x, a.x, q.x) + chi2_term(p.y, a.y, q.y)) +
            (chi2_term(p.z, a.z, q.z) + chi2_term(p.w, a.w, q.w));
+  if (KIND == 4)
+    return (power_term(p.x, a.x, q.x, param) + power_term(p.y, a.y, q.y, param)) +
+           (power_term(p.z, a.z, q.z, param) + power_term(p.w, a.w, q.w, param));
+  if (KIND == 5)
+    return (alpha_term(p.x, a.x, q.x, param) + alpha_term(p.y, a.y, q.y, param)) +
+           (alpha_term(p.z, a.z, q.z, param) + alpha_term(p.w, a.w, q.w, param));
   return (hel_term(p.x, a.x, q.x) + hel_term(p.y, a.y, q.y)) +
          (hel_term(p.z, a.z, q.z) + hel_term(p.w, a.w, q.w));
 }
 
+// Per-row factor of the FP64 sum: ln 2 for KL (log2 terms), 4/(1 - alpha^2)
+// for the alpha-divergence, 1 otherwise.
+template <int KIND>
+__device__ __forceinline__ double row_factor(int param) {
+  if (KIND == 1) return 0.69314718055994530942;
+  if (KIND == 5) {
+    const double al = (double)(param - 8) / 8.0;
+    return 4.0 / (1.0 - al * al);
+  }
+  return 1.0;
+}
+
 template <int LPR, int KIND, int UNROLL>
 __global__ __launch_bounds__(512) void dense_field_kernel(const float* __restrict__ P, int64_t ld,
-                                                          int32_t N, int32_t target,
+                                                          int32_t N, int32_t target, int param,
                                                           float* __restrict__ out) {
   extern __shared__ float4 smem4[];
   const int nv = (int)(ld >> 2);
@@ -113,13 +160,13 @@ __global__ __launch_bounds__(512) void dense_field_kernel(const float* __restric
         if (i < nv) {
           const float4 p = sp[i];
           const float4 aux = KIND != 0 ? sl[i] : p;
-          acc += (double)term4<KIND>(p, aux, v[u]);
+          acc += (double)term4<KIND>(p, aux, v[u], param);
         }
       }
     }
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
-    if (lane == 0) out[row] = (float)(KIND == 1 ? acc * 0.69314718055994530942 : acc);
+    if (lane == 0) out[row] = (float)(KIND == 1 || KIND == 5 ? acc * row_factor<KIND>(param) : acc);
   }
 }
 
@@ -191,7 +238,7 @@ __global__ __launch_bounds__(512) void support_kl_kernel(const float* __restrict
         const int i = base + u * LPR;
         if (i < nv) {
           const float4 qv = make_float4(v[u].x, v[u].y, v[u].z, v[u].w);
-          acc += (double)term4<1>(sp[i], sl[i], qv);
+          acc += (double)term4<1>(sp[i], sl[i], qv, 0);
         }
       }
     }
@@ -347,7 +394,7 @@ static int grid_for(int64_t groups_needed, int gpb, size_t lds) {
 }
 
 template <int LPR, int KIND>
-static hipError_t dense_launch(DenseView v, int32_t target, float* out, hipStream_t s) {
+static hipError_t dense_launch(DenseView v, int32_t target, int param, float* out, hipStream_t s) {
   constexpr int UNROLL = (LPR == 64) ? 4 : (LPR == 32 ? 4 : 4);
   auto kern = dense_field_kernel<LPR, KIND, UNROLL>;
   const size_t lds = (size_t)v.ld * sizeof(float) * (KIND != 0 ? 2 : 1);
@@ -355,24 +402,29 @@ static hipError_t dense_launch(DenseView v, int32_t target, float* out, hipStrea
   if (e != hipSuccess) return e;
   const int threads = block_threads(lds);
   const int grid = grid_for(v.N, threads / LPR, lds);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v.P, v.ld, v.N, target, out);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v.P, v.ld, v.N, target, param, out);
   return hipGetLastError();
 }
 
 template <int KIND>
-static hipError_t dense_dispatch(DenseView v, int32_t target, float* out, hipStream_t s) {
+static hipError_t dense_dispatch(DenseView v, int32_t target, int param, float* out,
+                                 hipStream_t s) {
   const int64_t nv = v.ld / 4;
-  if (nv >= 256) return dense_launch<64, KIND>(v, target, out, s);
-  if (nv >= 128) return dense_launch<32, KIND>(v, target, out, s);
-  return dense_launch<16, KIND>(v, target, out, s);
+  if (nv >= 256) return dense_launch<64, KIND>(v, target, param, out, s);
+  if (nv >= 128) return dense_launch<32, KIND>(v, target, param, out, s);
+  return dense_launch<16, KIND>(v, target, param, out, s);
 }
 
+// kind: 0 TV, 1 KL, 2 chi-squared, 3 Hellinger, 100 + k power k (1..16),
+// 200 + j alpha-divergence with (1 + alpha)/2 = j/16 (1..15)
 hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out, hipStream_t s) {
+  if (kind > 100 && kind <= 116) return dense_dispatch<4>(v, target, kind - 100, out, s);
+  if (kind > 200 && kind < 216) return dense_dispatch<5>(v, target, kind - 200, out, s);
   switch (kind) {
-    case 0: return dense_dispatch<0>(v, target, out, s);
-    case 1: return dense_dispatch<1>(v, target, out, s);
-    case 2: return dense_dispatch<2>(v, target, out, s);
-    case 3: return dense_dispatch<3>(v, target, out, s);
+    case 0: return dense_dispatch<0>(v, target, 0, out, s);
+    case 1: return dense_dispatch<1>(v, target, 0, out, s);
+    case 2: return dense_dispatch<2>(v, target, 0, out, s);
+    case 3: return dense_dispatch<3>(v, target, 0, out, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -228,3 +228,52 @@ def test_hellinger_bound_is_relative_near_the_target(grid65):
     ref = oracle_field(P, t, "hellinger")
     nz = ref > 0
     assert np.max(np.abs(d[nz] - ref[nz]) / ref[nz]) <= 2 * b[1]
+
+
+FAMILY = [("power", 1), ("power", 3), ("power", 4), ("power", 16),
+          ("alpha", -0.875), ("alpha", -0.25), ("alpha", 0.0), ("alpha", 0.5), ("alpha", 0.875)]
+
+
+@pytest.mark.parametrize("member", FAMILY)
+def test_family_members_match_oracle(grid65, disk_kernel, member):
+    g, P, k = grid65
+    for t in (0, 321, g.N - 1):
+        d, b = k.field(t, member)
+        d = d.cpu().numpy()
+        ref = dv.field(P.astype(np.float64), t, member)
+        assert d[t] == 0.0
+        assert normwise(d, ref) <= TOL and within_bound(d, ref, b), (member, t)
+    inst, kd = disk_kernel
+    t = int(targets_sources(0, inst.N, 1)[0][0])
+    d, b = kd.field(t, member)
+    d = d.cpu().numpy()
+    ref = dv.field(inst.P, t, member)
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(d), fin)
+    assert normwise(d[fin], ref[fin]) <= TOL and within_bound(d[fin], ref[fin], b), member
+
+
+def test_family_special_members_equal_named_kinds(grid65):
+    # k = 1 is TV and k = 2 chi-squared term for term, so bit for bit
+    g, P, k = grid65
+    for t in (5, 900):
+        assert np.array_equal(k.field(t, ("power", 1))[0].cpu().numpy(),
+                              k.field(t, "tv")[0].cpu().numpy())
+        assert np.array_equal(k.field(t, ("power", 2))[0].cpu().numpy(),
+                              k.field(t, "chi2")[0].cpu().numpy())
+
+
+def test_family_members_rejected_on_truncated_handles(gpu_ctx, grid65):
+    from paper_1708_02845_amd import DDError, Kernel
+    g, P, _ = grid65
+    kc = Kernel.load_dense(gpu_ctx, P, tau=1e-3)
+    try:
+        for m in (("power", 3), ("alpha", 0.5)):
+            with pytest.raises(DDError, match="dense handle"):
+                kc.field(0, m)
+    finally:
+        kc.free()
+    with pytest.raises(ValueError):
+        grid65[2].field(0, ("power", 17))
+    with pytest.raises(ValueError):
+        grid65[2].field(0, ("alpha", 1.0))

@@ -49,14 +49,14 @@ def grid(gpu_ctx):
     k.free()
 
 
-@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("kind", KINDS + [("power", 3), ("alpha", -0.5)])
 def test_disk_on_demand_paths(disk, kind):
     inst, k = disk
     ts, ss = targets_sources(0, inst.N, 8)
     res = run_on_demand(k, ss, ts, kind, 4000)
     deg = int(np.diff(inst.adj_ptr).max())
     for (got, st, n_eval), s, t in zip(res, ss, ts):
-        ref, ref_st = op.steepest_descent_path(dv.FIELDS[kind](inst.P, int(t)), inst.adj_ptr,
+        ref, ref_st = op.steepest_descent_path(dv.field(inst.P, int(t), kind), inst.adj_ptr,
                                                inst.adj_idx, int(s), int(t), 4000)
         assert got == ref and st == STATUS[ref_st] == "reached"
         assert n_eval <= 1 + (len(got) - 1) * deg and n_eval < inst.N // 10

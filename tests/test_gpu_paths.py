@@ -15,8 +15,7 @@ STATUS = {op.REACHED: "reached", op.STUCK: "stuck", op.MAX_STEPS: "max_steps"}
 
 def oracle_path(P, adj_ptr, adj_idx, s, t, kind, max_steps):
     P64 = np.asarray(P, dtype=np.float64)
-    d = {"tv": dv.tv_field, "kl": dv.kl_field, "chi2": dv.chi2_field,
-         "hellinger": dv.hellinger_field}[kind](P64, t)
+    d = dv.field(P64, t, kind)
     path, status = op.steepest_descent_path(d, adj_ptr, adj_idx, s, t, max_steps)
     return path, STATUS[status]
 
@@ -30,7 +29,7 @@ def disk(gpu_ctx):
     k.free()
 
 
-@pytest.mark.parametrize("kind", ["kl", "tv", "chi2", "hellinger"])
+@pytest.mark.parametrize("kind", ["kl", "tv", "chi2", "hellinger", ("power", 3), ("alpha", 0.5)])
 def test_disk_paths_identical(disk, kind):
     inst, k = disk
     ts, ss = targets_sources(0, inst.N, 8)
