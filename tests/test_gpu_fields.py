@@ -234,6 +234,16 @@ FAMILY = [("power", 1), ("power", 3), ("power", 4), ("power", 16),
           ("alpha", -0.875), ("alpha", -0.25), ("alpha", 0.0), ("alpha", 0.5), ("alpha", 0.875)]
 
 
+def check_member(d, ref, b, what):
+    # values beyond the FP32 range can only come back as +inf (|1-u|^16 on the
+    # grid reaches 1e110); the rest meet the tolerance and the bound
+    big = ref > np.finfo(np.float32).max
+    assert np.all(np.isinf(d[big])), what
+    fin = ~big
+    assert np.all(np.isfinite(d[fin])), what
+    assert normwise(d[fin], ref[fin]) <= TOL and within_bound(d[fin], ref[fin], b), what
+
+
 @pytest.mark.parametrize("member", FAMILY)
 def test_family_members_match_oracle(grid65, disk_kernel, member):
     g, P, k = grid65
@@ -242,15 +252,11 @@ def test_family_members_match_oracle(grid65, disk_kernel, member):
         d = d.cpu().numpy()
         ref = dv.field(P.astype(np.float64), t, member)
         assert d[t] == 0.0
-        assert normwise(d, ref) <= TOL and within_bound(d, ref, b), (member, t)
+        check_member(d, ref, b, (member, t))
     inst, kd = disk_kernel
     t = int(targets_sources(0, inst.N, 1)[0][0])
     d, b = kd.field(t, member)
-    d = d.cpu().numpy()
-    ref = dv.field(inst.P, t, member)
-    fin = np.isfinite(ref)
-    assert np.array_equal(np.isfinite(d), fin)
-    assert normwise(d[fin], ref[fin]) <= TOL and within_bound(d[fin], ref[fin], b), member
+    check_member(d.cpu().numpy(), dv.field(inst.P, t, member), b, member)
 
 
 def test_family_special_members_equal_named_kinds(grid65):
