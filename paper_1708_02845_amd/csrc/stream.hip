@@ -68,7 +68,8 @@ __device__ __forceinline__ float power_term(float p, float r, float q, int k) {
 
 // alpha-divergence with (1 + alpha)/2 = j/16: p (1 - (q/p)^(j/16)), the
 // sixteenth root by four hardware square roots and the power by squaring;
-// exactly 0 when q == p.  The factor 4/(1 - alpha^2) is applied per row.
+// 0 when q == p (q * fl(1/p) need not be 1 there).  The factor
+// 4/(1 - alpha^2) is applied per row.
 __device__ __forceinline__ float alpha_term(float p, float r, float q, int j) {
   float z = q * r;
   z = __builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(z))));
@@ -77,7 +78,7 @@ __device__ __forceinline__ float alpha_term(float p, float r, float q, int j) {
     if (e & 1) pw *= z;
     z *= z;
   }
-  return p > 0.f ? p * (1.f - pw) : 0.f;
+  return (p > 0.f && q != p) ? p * (1.f - pw) : 0.f;
 }
 
 // Second LDS array per kind: log2 p (KL), 1/p (chi-squared, power, alpha),
