@@ -135,69 +135,72 @@ __global__ __launch_bounds__(256) void neighbor_values_kernel(PathArgs a, int32_
   }
 }
 
-// FP64 distance of row x to the target, computed by one wave, from the
-// staged FP64 target row p, its logarithms lp and constants tc.  The KL
-// terms are p (log p - log q); chi-squared (q - p)^2 / p (+inf for q > 0 on
-// p = 0); Hellinger (q - p)^2 / (sqrt q + sqrt p)^2, the cancellation-free
-// form of (sqrt q - sqrt p)^2; the power and alpha families as in term64.
-// Truncated handles carry TV and KL only.
-// Kinds: 0 TV, 1 KL, 2 chi-squared, 3 Hellinger, 100 + k the power family
-// |q - p|^k / p^(k-1), 200 + j the alpha-divergence term p (1 - (q/p)^(j/16))
-// (its factor 4/(1 - alpha^2) is applied to the sum).
-__device__ __forceinline__ double term64(int kind, double pb, double lpb, double q) {
+// The KL terms are p (log p - log q); chi-squared (q - p)^2 / p (+inf for
+// q > 0 on p = 0); Hellinger (q - p)^2 / (sqrt q + sqrt p)^2, the
+// cancellation-free form of (sqrt q - sqrt p)^2.
+// Terms per kind family F: 0 TV, 1 KL, 2 chi-squared, 3 Hellinger, 4 the
+// power family |q - p|^k / p^(k-1) (k = param), 5 the alpha-divergence term
+// p (1 - (q/p)^(param/16)) (its factor 4/(1 - alpha^2) is applied to the sum).
+template <int F>
+__device__ __forceinline__ double term64(double pb, double lpb, double q, int param) {
   const double df = q - pb;
-  if (kind == 0) return fabs(df);
-  if (kind == 1) return pb > 0.0 ? pb * (lpb - log(q)) : 0.0;
-  if (kind > 200) return pb > 0.0 ? pb * (1.0 - pow(q / pb, (double)(kind - 200) / 16.0)) : 0.0;
+  if (F == 0) return fabs(df);
+  if (F == 1) return pb > 0.0 ? pb * (lpb - log(q)) : 0.0;
+  if (F == 5) return pb > 0.0 ? pb * (1.0 - pow(q / pb, (double)param / 16.0)) : 0.0;
   if (df == 0.0) return 0.0;
-  if (kind > 100) {
-    const int k = kind - 100;
-    if (!(pb > 0.0)) return k == 1 ? fabs(df) : __builtin_inf();
+  if (F == 4) {
+    if (!(pb > 0.0)) return param == 1 ? fabs(df) : __builtin_inf();
     const double r = fabs(df) / pb;
     double t = fabs(df);
-    for (int j = 1; j < k; ++j) t *= r;
+    for (int j = 1; j < param; ++j) t *= r;
     return t;
   }
-  if (kind == 2) return pb > 0.0 ? df * df / pb : __builtin_inf();
+  if (F == 2) return pb > 0.0 ? df * df / pb : __builtin_inf();
   const double e = df / (sqrt(q) + sqrt(pb));
   return e * e;
 }
 
-__device__ __forceinline__ double kind_factor(int kind) {
-  if (kind > 200) {
-    const double al = (double)(kind - 208) / 8.0;
-    return 4.0 / (1.0 - al * al);
+// FP64 distance of dense row x, one wave.  Loads are issued kU at a time per
+// lane (indices clamped into the row, the clamped slots are not summed), so a
+// row costs a few memory round trips rather than one per 64 entries.  One
+// instance per kind family keeps each instance's code small: the walk and the
+// one instance a path uses stay in the instruction cache.
+constexpr int kU = 8;
+
+template <int F>
+__device__ __noinline__ double exact_dense(const DenseView& dv, const double* p, const double* lp,
+                                           int x, int param) {
+  const int lane = threadIdx.x & 63;
+  double acc = 0.0;
+  const bool f64 = dv.P64 != nullptr;
+  const double* q64 = dv.P64 + (int64_t)x * dv.B;
+  const float* q32 = dv.P + (int64_t)x * dv.ld;
+  for (int b0 = lane; b0 < dv.B; b0 += 64 * kU) {
+    double q[kU], pb[kU], lpb[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int b = b0 + 64 * u < dv.B ? b0 + 64 * u : 0;
+      q[u] = f64 ? q64[b] : (double)q32[b];
+      pb[u] = p[b];
+      lpb[u] = F == 1 ? lp[b] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (b0 + 64 * u < dv.B) acc += term64<F>(pb[u], lpb[u], q[u], param);
   }
-  return 1.0;
+  acc = wsum(acc);
+  if (F == 5) {
+    const double al = (double)(param - 8) / 8.0;
+    acc *= 4.0 / (1.0 - al * al);
+  }
+  return acc;
 }
 
-// Loads are issued kU at a time per lane (indices clamped into the row, the
-// clamped slots are not summed), so a row costs a few memory round trips
-// rather than one per 64 entries.
-__device__ __noinline__ double exact_distance(const DenseView& dv, const CsrView& cv, int is_csr, int kind,
-                                 const double* p, const double* lp, const double* tc, int x) {
-  constexpr int kU = 8;
+// FP64 distance of truncated row x (TV or KL of the truncated rows), one wave.
+template <int F>
+__device__ __noinline__ double exact_csr(const CsrView& cv, const double* p, const double* lp,
+                                         const double* tc, int x) {
   const int lane = threadIdx.x & 63;
-  if (!is_csr) {
-    double acc = 0.0;
-    const bool f64 = dv.P64 != nullptr;
-    const double* q64 = dv.P64 + (int64_t)x * dv.B;
-    const float* q32 = dv.P + (int64_t)x * dv.ld;
-    for (int b0 = lane; b0 < dv.B; b0 += 64 * kU) {
-      double q[kU], pb[kU], lpb[kU];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int b = b0 + 64 * u < dv.B ? b0 + 64 * u : 0;
-        q[u] = f64 ? q64[b] : (double)q32[b];
-        pb[u] = p[b];
-        lpb[u] = lp[b];
-      }
-#pragma unroll
-      for (int u = 0; u < kU; ++u)
-        if (b0 + 64 * u < dv.B) acc += term64(kind, pb[u], lpb[u], q[u]);
-    }
-    return wsum(acc) * kind_factor(kind);
-  }
   const int64_t s = cv.start[x];
   const int n = cv.len[x];
   double acc = 0.0, A = 0.0, E = 0.0, c = 0.0;
@@ -220,8 +223,8 @@ __device__ __noinline__ double exact_distance(const DenseView& dv, const CsrView
     for (int u = 0; u < kU; ++u) {
       if (i0 + 64 * u < n) {
         A += pb[u];
-        acc += term64(kind, pb[u], lpb[u], q[u]);
-        if (kind == 1 && pb[u] > 0.0) E += pb[u] * lpb[u];
+        acc += term64<F>(pb[u], lpb[u], q[u], 0);
+        if (F == 1 && pb[u] > 0.0) E += pb[u] * lpb[u];
         c += pb[u] > 0.0 ? 1.0 : 0.0;
       }
     }
@@ -231,8 +234,26 @@ __device__ __noinline__ double exact_distance(const DenseView& dv, const CsrView
   E = wsum(E);
   c = wsum(c);
   if (c == tc[2]) return acc;
-  if (kind == 0) return acc + (tc[0] - A);
+  if (F == 0) return acc + (tc[0] - A);
   return acc + (tc[1] - E) - log(cv.phi[x]) * (tc[0] - A);
+}
+
+// FP64 distance of row x to the target, computed by one wave, from the
+// staged FP64 target row p, its logarithms lp and constants tc.  kind is the
+// library's kind value (0..3, 100 + k, 200 + j); truncated handles carry TV
+// and KL only.
+__device__ __forceinline__ double exact_distance(const DenseView& dv, const CsrView& cv,
+                                                 int is_csr, int kind, const double* p,
+                                                 const double* lp, const double* tc, int x) {
+  if (is_csr) return kind == 0 ? exact_csr<0>(cv, p, lp, tc, x) : exact_csr<1>(cv, p, lp, tc, x);
+  if (kind > 200) return exact_dense<5>(dv, p, lp, x, kind - 200);
+  if (kind > 100) return exact_dense<4>(dv, p, lp, x, kind - 100);
+  switch (kind) {
+    case 0: return exact_dense<0>(dv, p, lp, x, 0);
+    case 1: return exact_dense<1>(dv, p, lp, x, 0);
+    case 2: return exact_dense<2>(dv, p, lp, x, 0);
+    default: return exact_dense<3>(dv, p, lp, x, 0);
+  }
 }
 
 __device__ __forceinline__ double uniform(double x) {

