@@ -111,6 +111,7 @@ struct PathArgs {
   // of the row when tau_relative, else tau
   double tgt_tau;
   int32_t tgt_tau_relative;
+  int32_t tgt_in_lds;       // set by the launcher: trow/tlog staged in LDS
 };
 hipError_t launch_target_rows(DenseView dv, CsrView cv, PathArgs a, double* trow, double* tlog,
                               double* tconst, hipStream_t s);

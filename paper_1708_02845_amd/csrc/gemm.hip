@@ -202,7 +202,7 @@ __device__ __forceinline__ void write_fields(const GemmView& gv, const BatchOper
 }
 
 template <int NT>
-__global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o, int32_t T,
+__global__ __launch_bounds__(256, 2) void kl_gemm_f16x3(GemmView gv, BatchOperand o, int32_t T,
                                                      int32_t groups, float* __restrict__ out) {
   int rb, grp;
   block_tile(groups, rb, grp);
@@ -234,24 +234,57 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
   // assigned staging array is placed in scratch memory by the compiler
   static_assert(SEGS % 256 == 0, "B segments must divide evenly over the workgroup");
 
-  // Chunk c's A fragment is loaded into nh/nl during chunk c-1 and copied
-  // into ah/al at the top of chunk c, so the registers the MFMAs read are
-  // never the destination of a load in flight; otherwise the compiler's wait
-  // counting merges the loop edges and makes the MFMAs of chunk c wait for
-  // the loads of chunk c+1.
-  u32x4 ah[4], al[4], nh[4], nl[4], bh[SPT], bl[SPT];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    nh[q] = *reinterpret_cast<const u32x4*>(ahp + q * 8);
-    nl[q] = *reinterpret_cast<const u32x4*>(alp + q * 8);
-  }
+  // Software pipeline.  The A fragment of chunk c is loaded three chunks
+  // ahead into one of three register sets (c mod 3) that the MFMAs of chunk c
+  // read directly; the next load into a set is issued after the MFMAs that
+  // read it.  The B segments of chunk c are loaded two chunks ahead into one
+  // of two staging sets (c mod 2) and written to LDS at the top of chunk c.
+  // Every chunk issues, in this order, B(c+2) after its LDS write and A(c+3)
+  // after its MFMAs, so at the top of chunk c the loads still in flight are
+  // A(c+1), B(c+1) and A(c+2): waiting for B(c) (and, being older, A(c))
+  // leaves two chunks of A, 64 KB per workgroup, in flight while chunk c
+  // computes.  All loads are unconditional (chunk indices clamped to the last
+  // chunk, whose re-reads hit the cache), the loop is unrolled six chunks
+  // deep so that every set is a fixed register range, and the prologue issues
+  // the loads in the loop's order: the compiler's count of loads in flight is
+  // the same on every path into a chunk.  Chunks past the end only load.
+  u32x4 s0h[4], s0l[4], s1h[4], s1l[4], s2h[4], s2l[4];
+  u32x4 t0h[SPT], t0l[SPT], t1h[SPT], t1l[SPT];
+  const int last = nchunks - 1;
+  // addresses as a wave-uniform base plus a 32-bit lane offset, so the loads
+  // take the scalar-base form and keep few vector registers for addresses
+  const uint16_t* abh = gv.lhi + tile0;
+  const uint16_t* abl = gv.llo + tile0;
+  const int a_lane = (int)lane_off;
+  int b_lane[SPT];
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
     const int sg = threadIdx.x + q * 256;
-    const int64_t g = (int64_t)(sg >> 3) * gv.lda + (sg & 7) * 8;
-    bh[q] = *reinterpret_cast<const u32x4*>(bhp + g);
-    bl[q] = *reinterpret_cast<const u32x4*>(blp + g);
+    b_lane[q] = (sg >> 3) * (int)gv.lda + (sg & 7) * 8;
   }
+  auto load_a = [&](int c, u32x4 (&dh)[4], u32x4 (&dl)[4]) {
+    const uint16_t* bh_ = abh + (int64_t)c * CHUNK;
+    const uint16_t* bl_ = abl + (int64_t)c * CHUNK;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      dh[q] = *reinterpret_cast<const u32x4*>(bh_ + (a_lane + q * 8));
+      dl[q] = *reinterpret_cast<const u32x4*>(bl_ + (a_lane + q * 8));
+    }
+  };
+  auto load_b = [&](int c, u32x4 (&dh)[SPT], u32x4 (&dl)[SPT]) {
+    const uint16_t* bh_ = bhp + (int64_t)c * KC;
+    const uint16_t* bl_ = blp + (int64_t)c * KC;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      dh[q] = *reinterpret_cast<const u32x4*>(bh_ + b_lane[q]);
+      dl[q] = *reinterpret_cast<const u32x4*>(bl_ + b_lane[q]);
+    }
+  };
+  load_a(0, s0h, s0l);
+  load_b(0, t0h, t0l);
+  load_a(min(1, last), s1h, s1l);
+  load_b(min(1, last), t1h, t1l);
+  load_a(min(2, last), s2h, s2l);
   floatx16 acc[NT];
   double accd[NT][16];
 #pragma unroll
@@ -262,56 +295,49 @@ __global__ __launch_bounds__(256) void kl_gemm_f16x3(GemmView gv, BatchOperand o
       accd[n][i] = 0.0;
     }
 
-  for (int c = 0; c < nchunks; ++c) {
+  auto step = [&](int c, u32x4 (&sh)[4], u32x4 (&sl)[4], u32x4 (&th)[SPT], u32x4 (&tl)[SPT]) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       const int sg = threadIdx.x + q * 256;
-      *reinterpret_cast<u32x4*>(&sbh[sg >> 3][(sg & 7) * 8]) = bh[q];
-      *reinterpret_cast<u32x4*>(&sbl[sg >> 3][(sg & 7) * 8]) = bl[q];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ah[q] = nh[q];
-      al[q] = nl[q];
+      *reinterpret_cast<u32x4*>(&sbh[sg >> 3][(sg & 7) * 8]) = th[q];
+      *reinterpret_cast<u32x4*>(&sbl[sg >> 3][(sg & 7) * 8]) = tl[q];
     }
     __syncthreads();
-    if (c + 1 < nchunks) {
-      const int64_t ko = (int64_t)(c + 1) * KC;
-      const int64_t ao = (int64_t)(c + 1) * CHUNK;
+    load_b(min(c + 2, last), th, tl);
+    if (c < nchunks) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        nh[q] = *reinterpret_cast<const u32x4*>(ahp + ao + q * 8);
-        nl[q] = *reinterpret_cast<const u32x4*>(alp + ao + q * 8);
+      for (int j = 0; j < 4; ++j) {
+        const half8 a_h = __builtin_bit_cast(half8, sh[j]);
+        const half8 a_l = __builtin_bit_cast(half8, sl[j]);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          const half8 b_h = *reinterpret_cast<const half8*>(&sbh[n * 32 + r][h * 32 + j * 8]);
+          const half8 b_l = *reinterpret_cast<const half8*>(&sbl[n * 32 + r][h * 32 + j * 8]);
+          acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_h, b_h, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_h, b_l, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_l, b_h, acc[n], 0, 0, 0);
+        }
+        // keep the B fragments of one K step live at a time (register budget)
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
-      for (int q = 0; q < SPT; ++q) {
-        const int sg = threadIdx.x + q * 256;
-        const int64_t g = (int64_t)(sg >> 3) * gv.lda + ko + (sg & 7) * 8;
-        bh[q] = *reinterpret_cast<const u32x4*>(bhp + g);
-        bl[q] = *reinterpret_cast<const u32x4*>(blp + g);
-      }
+      for (int n = 0; n < NT; ++n)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          accd[n][i] += (double)acc[n][i];
+          acc[n][i] = 0.f;
+        }
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const half8 a_h = __builtin_bit_cast(half8, ah[j]);
-      const half8 a_l = __builtin_bit_cast(half8, al[j]);
-#pragma unroll
-      for (int n = 0; n < NT; ++n) {
-        const half8 b_h = *reinterpret_cast<const half8*>(&sbh[n * 32 + r][h * 32 + j * 8]);
-        const half8 b_l = *reinterpret_cast<const half8*>(&sbl[n * 32 + r][h * 32 + j * 8]);
-        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_h, b_h, acc[n], 0, 0, 0);
-        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_h, b_l, acc[n], 0, 0, 0);
-        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_l, b_h, acc[n], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int n = 0; n < NT; ++n)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        accd[n][i] += (double)acc[n][i];
-        acc[n][i] = 0.f;
-      }
+    load_a(min(c + 3, last), sh, sl);
+  };
+  for (int c = 0; c < nchunks; c += 6) {
+    step(c, s0h, s0l, t0h, t0l);
+    step(c + 1, s1h, s1l, t1h, t1l);
+    step(c + 2, s2h, s2l, t0h, t0l);
+    step(c + 3, s0h, s0l, t1h, t1l);
+    step(c + 4, s1h, s1l, t0h, t0l);
+    step(c + 5, s2h, s2l, t1h, t1l);
   }
   __syncthreads();   // every wave is done with the staged target tiles
   write_fields<NT>(gv, o, T, tbase, row0, lane, accd, reinterpret_cast<float*>(lds), out);

@@ -160,12 +160,14 @@ __device__ __forceinline__ double term64(double pb, double lpb, double q, int pa
   return e * e;
 }
 
-// FP64 distance of dense row x, one wave.  Loads are issued kU at a time per
-// lane (indices clamped into the row, the clamped slots are not summed), so a
-// row costs a few memory round trips rather than one per 64 entries.  One
+// FP64 distance of dense row x, one wave.  The row's entries are loaded kQ
+// per lane at a time (indices clamped into the row, clamped slots not
+// summed): one memory round trip per 64 * kQ entries.  The target row p and
+// its logs lp are read from LDS when the block staged them there.  One
 // instance per kind family keeps each instance's code small: the walk and the
 // one instance a path uses stay in the instruction cache.
 constexpr int kU = 8;
+constexpr int kQ = 24;
 
 template <int F>
 __device__ __noinline__ double exact_dense(const DenseView& dv, const double* p, const double* lp,
@@ -175,18 +177,20 @@ __device__ __noinline__ double exact_dense(const DenseView& dv, const double* p,
   const bool f64 = dv.P64 != nullptr;
   const double* q64 = dv.P64 + (int64_t)x * dv.B;
   const float* q32 = dv.P + (int64_t)x * dv.ld;
-  for (int b0 = lane; b0 < dv.B; b0 += 64 * kU) {
-    double q[kU], pb[kU], lpb[kU];
+  for (int b0 = lane; b0 < dv.B; b0 += 64 * kQ) {
+    double q[kQ];
+    if (f64) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int b = b0 + 64 * u < dv.B ? b0 + 64 * u : 0;
-      q[u] = f64 ? q64[b] : (double)q32[b];
-      pb[u] = p[b];
-      lpb[u] = F == 1 ? lp[b] : 0.0;
+      for (int u = 0; u < kQ; ++u) q[u] = q64[b0 + 64 * u < dv.B ? b0 + 64 * u : 0];
+    } else {
+#pragma unroll
+      for (int u = 0; u < kQ; ++u) q[u] = (double)q32[b0 + 64 * u < dv.B ? b0 + 64 * u : 0];
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (b0 + 64 * u < dv.B) acc += term64<F>(pb[u], lpb[u], q[u], param);
+    for (int u = 0; u < kQ; ++u) {
+      const int b = b0 + 64 * u;
+      if (b < dv.B) acc += term64<F>(p[b], F == 1 ? lp[b] : 0.0, q[u], param);
+    }
   }
   acc = wsum(acc);
   if (F == 5) {
@@ -314,6 +318,17 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
   const int Bt = a.is_csr ? cv.B : dv.B;
   const double* p = a.trow + (int64_t)i * Bt;
   const double* lpt = a.tlog + (int64_t)i * Bt;
+  if (a.tgt_in_lds) {
+    // FP64 target row and its logs in LDS for the row evaluations
+    extern __shared__ double tsh[];
+    for (int b = threadIdx.x; b < Bt; b += blockDim.x) {
+      tsh[b] = p[b];
+      tsh[Bt + b] = lpt[b];
+    }
+    __syncthreads();
+    p = tsh;
+    lpt = tsh + Bt;
+  }
   const double* tc = a.tconst + (int64_t)i * 4;
   int32_t* path = a.path + (int64_t)i * (a.max_steps + 1);
   const int t = __builtin_amdgcn_readfirstlane(path_target(a, i));
@@ -468,6 +483,17 @@ __global__ __launch_bounds__(256) void paths_on_demand_kernel(DenseView dv, CsrV
   const int Bt = a.is_csr ? cv.B : dv.B;
   const double* p = a.trow + (int64_t)i * Bt;
   const double* lpt = a.tlog + (int64_t)i * Bt;
+  if (a.tgt_in_lds) {
+    // FP64 target row and its logs in LDS for the row evaluations
+    extern __shared__ double tsh[];
+    for (int b = threadIdx.x; b < Bt; b += blockDim.x) {
+      tsh[b] = p[b];
+      tsh[Bt + b] = lpt[b];
+    }
+    __syncthreads();
+    p = tsh;
+    lpt = tsh + Bt;
+  }
   const double* tc = a.tconst + (int64_t)i * 4;
   int32_t* path = a.path + (int64_t)i * (a.max_steps + 1);
   const int32_t* __restrict__ adj = a.adj;
@@ -638,14 +664,30 @@ hipError_t launch_neighbor_values(PathArgs a, int32_t N, float* nv, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_paths(DenseView dv, CsrView cv, PathArgs a, hipStream_t s) {
-  hipLaunchKernelGGL(paths_kernel, dim3(a.T), dim3(256), 0, s, dv, cv, a);
+// Target rows of up to kLdsTargetMax entries are staged in LDS (16 bytes per
+// entry: the row and its logs).
+constexpr int kLdsTargetMax = 8192;
+
+template <typename K>
+static hipError_t launch_with_target(K kern, DenseView dv, CsrView cv, PathArgs a, hipStream_t s) {
+  const int B = a.is_csr ? cv.B : dv.B;
+  a.tgt_in_lds = B <= kLdsTargetMax ? 1 : 0;
+  const size_t lds = a.tgt_in_lds ? 16 * (size_t)B : 0;
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(a.T), dim3(256), lds, s, dv, cv, a);
   return hipGetLastError();
 }
 
+hipError_t launch_paths(DenseView dv, CsrView cv, PathArgs a, hipStream_t s) {
+  return launch_with_target(paths_kernel, dv, cv, a, s);
+}
+
 hipError_t launch_paths_on_demand(DenseView dv, CsrView cv, PathArgs a, hipStream_t s) {
-  hipLaunchKernelGGL(paths_on_demand_kernel, dim3(a.T), dim3(256), 0, s, dv, cv, a);
-  return hipGetLastError();
+  return launch_with_target(paths_on_demand_kernel, dv, cv, a, s);
 }
 
 }  // namespace dd
