@@ -31,6 +31,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+# source file of each measured kernel, for matching counter records to the code
+KERNEL_SOURCE = {"dense_tv": "stream.hip", "dense_kl": "stream.hip", "csr_tv": "stream.hip",
+                 "csr_kl": "stream.hip", "gemm_kl_T1": "gemm.hip", "kl_gemm_f16x3": "gemm.hip"}
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch (fetched + written) from the rocprofv3 counter record in
+    profiles/hbm_traffic.txt, or None when there is none for this kernel or the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    src = KERNEL_SOURCE.get(kernel)
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if src is None or not os.path.exists(path):
+        return None
+    with open(os.path.join(ROOT, "paper_1708_02845_amd", "csrc", src), "rb") as f:
+        sha = hashlib.sha1(f.read()).hexdigest()[:12]
+    with open(path) as f:
+        for line in f:
+            t = line.split()
+            if len(t) == 5 and t[0] == workload and t[1] == kernel and t[4] == sha:
+                return int(t[2]) + int(t[3])
+    return None
 MFMA_PEAK_TFLOPS = {"f16x3": 2500.0, "f32": 157.3}
 METRIC = "kernel entries/sec (N·B·targets/s)"
 
@@ -204,7 +227,7 @@ def run_grid1025(args):
                       "kernel_matrix_build_s": round(build_s, 1)},
            "roofline": {"bound": "hbm", "kernel": "kl_gemm_f16x3", "achieved": main_row["GB/s"],
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": main_row["hbm_frac"],
-                        "traffic": None},
+                        "traffic": measured_traffic("grid1025_T64", "kl_gemm_f16x3")},
            "rows": res}
     print(json.dumps(out), flush=True)
 
@@ -548,7 +571,7 @@ def main():
                      "achieved": round(gbs(traffic[dom], kernels[dom]["avg_us"]), 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs(traffic[dom], kernels[dom]["avg_us"]) / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": measured_traffic("grid257", dom)},
         "kernels": kernels,
         "rows": rows,
         "wall_s_timed": round(wall, 3),
