@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void trunc_fill_kernel(DenseView v, const doub
 }
 
 // l_xb = log P_xb - o_x with o_x = log max_b P_xb (natural log, FP64 then
-// rounded): FP32, or an FP16 hi + lo split, written in the tile-major layout
+// rounded): FP32, or an FP16 hi + lo split, written in the tiled layout
 // of the contraction operand (padding rows are zeroed by the caller).
 __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, int64_t lda,
                                                         float* l32, uint16_t* lhi, uint16_t* llo,
@@ -156,10 +156,10 @@ __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, i
   if (lane == 0) offset[row] = (float)o;
   const double of = (double)(float)o;   // the offset the epilogue will use
   int nz = 0;
-  const int64_t nch = lda / kGemmK;
-  const int64_t tile_base = (row / kGemmRows) * nch * kGemmRows * kGemmK + (row % kGemmRows) * kGemmK;
+  const int64_t R = gemm_row_tiles(v.N);
+  const int64_t tile_base = (row / kGemmRows) * kGemmRows * kGemmK + (row % kGemmRows) * kGemmK;
   for (int64_t b = lane; b < lda; b += 64) {
-    const int64_t at = tile_base + (b / kGemmK) * kGemmRows * kGemmK + (b % kGemmK);
+    const int64_t at = tile_base + (b / kGemmK) * R * kGemmRows * kGemmK + (b % kGemmK);
     double l = 0.0;
     if (b < v.B) {
       const double p = master_at(v, row, (int)b);

@@ -55,23 +55,27 @@ hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out,
 hipError_t launch_csr_field(CsrView v, int32_t target, int kind, float* out, hipStream_t s);
 
 // ---- batched KL contraction (gemm.hip) ----
-// The log-kernel operand is stored tile-major: rows in tiles of kGemmRows,
-// columns in chunks of kGemmK, element (x, b) at
-//   ((x / kGemmRows) * (lda / kGemmK) + b / kGemmK) * kGemmRows * kGemmK
+// The log-kernel operand is stored in tiles of kGemmRows rows by kGemmK
+// columns, chunk-major: with R = rows padded / kGemmRows, element (x, b) at
+//   ((b / kGemmK) * R + x / kGemmRows) * kGemmRows * kGemmK
 //     + (x % kGemmRows) * kGemmK + b % kGemmK,
-// so one workgroup's chunk is one contiguous block.  Rows are padded to a
-// multiple of kGemmRows and columns to lda; padding holds zeros.
+// so one workgroup's chunk is one contiguous block, and the workgroups that
+// run together (consecutive row tiles, all at about the same chunk) read one
+// contiguous window of memory rather than blocks a fixed stride apart, which
+// would load the same memory channels.  Rows are padded to a multiple of
+// kGemmRows and columns to lda; padding holds zeros.
 constexpr int kGemmRows = 128;
 constexpr int kGemmK = 64;
 struct GemmView {
-  const float* l32;      // tile-major log P - o_x  (form F32)
-  const uint16_t* lhi;   // tile-major FP16 bits    (form F16X3)
+  const float* l32;      // tiled log P - o_x  (form F32)
+  const uint16_t* lhi;   // tiled FP16 bits    (form F16X3)
   const uint16_t* llo;
   const float* offset;   // [N] o_x = log max_b P_xb
   int64_t lda;           // a multiple of kGemmK
   int32_t N, B, form;
 };
 inline int64_t gemm_rows_padded(int64_t N) { return (N + kGemmRows - 1) / kGemmRows * kGemmRows; }
+__host__ __device__ inline int64_t gemm_row_tiles(int64_t N) { return (N + kGemmRows - 1) / kGemmRows; }
 constexpr int kMaxBatch = 256;  // targets per contraction launch (groups of 64 per workgroup)
 struct TargetList {
   int32_t t[kMaxBatch];

@@ -28,9 +28,10 @@
 // so the FP32 accumulation error is that of 64-term partial sums; H_t, W_t and
 // the final combination are FP64.
 //
-// The operand is stored tile-major (128 rows x 64 columns per contiguous
-// block, see dd_internal.h), so a workgroup's K-chunk is one 16 KB (FP16) or
-// 32 KB (FP32) block and a wave's loads cover 4-8 KB contiguously.  The order
+// The operand is stored in 128-row x 64-column blocks, chunk-major (see
+// dd_internal.h), so a workgroup's K-chunk is one 16 KB (FP16) or 32 KB (FP32)
+// block, a wave's loads cover 4-8 KB contiguously, and the workgroups running
+// together read adjacent blocks.  The order
 // of K inside a chunk is a free choice, as long as both operands use the same
 // one: lane half h of a wave reads the contiguous K range [32h, 32h+32) of
 // its row in the chunk.
@@ -219,15 +220,14 @@ __global__ __launch_bounds__(256, 2) void kl_gemm_f16x3(GemmView gv, BatchOperan
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
   const int64_t row0 = (int64_t)rb * GROWS + wv * 32;
   const int nchunks = (int)(gv.lda / KC);
-  // tile-major operand: this workgroup's chunk c is one contiguous block of
-  // GROWS x KC; rows past N are zero in memory
-  const int64_t tile0 = (int64_t)rb * nchunks * (GROWS * KC);
+  // tiled operand: this workgroup's chunk c is one contiguous block of
+  // GROWS x KC, the blocks of one chunk index adjacent across row tiles;
+  // rows past N are zero in memory
+  const int64_t tile0 = (int64_t)rb * (GROWS * KC);
+  const int64_t cstride = gemm_row_tiles(gv.N) * (GROWS * KC);
   const uint16_t* bhp = o.bhi + (int64_t)tbase * gv.lda;
   const uint16_t* blp = o.blo + (int64_t)tbase * gv.lda;
   const int64_t lane_off = (int64_t)(wv * 32 + r) * KC + h * 32;
-  const uint16_t* ahp = gv.lhi + tile0 + lane_off;
-  const uint16_t* alp = gv.llo + tile0 + lane_off;
-  constexpr int64_t CHUNK = GROWS * KC;
   constexpr int SEGS = NT * 32 * 8;          // 16-byte segments per chunk per array
   constexpr int SPT = SEGS / 256;            // per thread
   // every thread stages whole segments unconditionally: a guarded, partly
@@ -263,8 +263,8 @@ __global__ __launch_bounds__(256, 2) void kl_gemm_f16x3(GemmView gv, BatchOperan
     b_lane[q] = (sg >> 3) * (int)gv.lda + (sg & 7) * 8;
   }
   auto load_a = [&](int c, u32x4 (&dh)[4], u32x4 (&dl)[4]) {
-    const uint16_t* bh_ = abh + (int64_t)c * CHUNK;
-    const uint16_t* bl_ = abl + (int64_t)c * CHUNK;
+    const uint16_t* bh_ = abh + (int64_t)c * cstride;
+    const uint16_t* bl_ = abl + (int64_t)c * cstride;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       dh[q] = *reinterpret_cast<const u32x4*>(bh_ + (a_lane + q * 8));
@@ -356,10 +356,10 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
   const int64_t row0 = (int64_t)rb * GROWS + wv * 32;
   const int nchunks = (int)(gv.lda / KC);
-  const int64_t tile0 = (int64_t)rb * nchunks * (GROWS * KC);
+  const int64_t tile0 = (int64_t)rb * (GROWS * KC);
+  const int64_t cstride = gemm_row_tiles(gv.N) * (GROWS * KC);
   const float* ap = gv.l32 + tile0 + (int64_t)(wv * 32 + r) * KC + h * 32;
   const float* bp = o.b32 + (int64_t)tbase * gv.lda;
-  constexpr int64_t CHUNK = GROWS * KC;
   constexpr int SEGS = NT * 32 * 16;          // 16-byte segments per chunk
   constexpr int SPT = SEGS / 256;
   static_assert(SEGS % 256 == 0, "B segments must divide evenly over the workgroup");
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
     __syncthreads();
     if (c + 1 < nchunks) {
       const int64_t ko = (int64_t)(c + 1) * KC;
-      const int64_t ao = (int64_t)(c + 1) * CHUNK;
+      const int64_t ao = (int64_t)(c + 1) * cstride;
 #pragma unroll
       for (int q = 0; q < 8; ++q) na[q] = *reinterpret_cast<const f32x4*>(ap + ao + q * 4);
 #pragma unroll
