@@ -413,6 +413,7 @@ dd_status dd_create(int device, dd_ctx** out) {
   HIP_OR(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return fail(DD_EINVAL, "device %d of %d", device, n);
   HIP_OR(hipSetDevice(device));
+  HIP_OR(dd::init_log_table());
   dd_ctx* c = new (std::nothrow) dd_ctx;
   if (!c) return fail(DD_ENOMEM, "host allocation failed");
   c->device = device;

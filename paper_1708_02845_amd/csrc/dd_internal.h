@@ -152,6 +152,9 @@ struct TriArgs {
 };
 hipError_t launch_triangle_paths(TriArgs a, hipStream_t s);
 
+// Device table of the FP64 log used by the path kernels; once per device.
+hipError_t init_log_table();
+
 int num_cus();
 
 }  // namespace dd

@@ -16,6 +16,8 @@
 // neighbour that could be the minimum, and of the current vertex, are
 // recomputed in FP64 from the resident master rows and the decision is taken
 // on those.
+#include <cmath>
+
 #include "dd_internal.h"
 
 namespace dd {
@@ -138,6 +140,49 @@ __global__ __launch_bounds__(256) void neighbor_values_kernel(PathArgs a, int32_
 // The KL terms are p (log p - log q); chi-squared (q - p)^2 / p (+inf for
 // q > 0 on p = 0); Hellinger (q - p)^2 / (sqrt q + sqrt p)^2, the
 // cancellation-free form of (sqrt q - sqrt p)^2.
+// log c_i and 1/c_i for the centres c_i = 1 + (i + 1/2)/128 of the 128
+// intervals of [1, 2), set by init_log_table (host logs, below 1 ulp).
+__device__ double g_logtab[256];
+
+// Natural log of a positive normal double: x = m 2^e with m in [1, 2) falls
+// in interval i; with r = m/c_i - 1 (|r| < 2^-8), log x = e ln 2 + log c_i +
+// log1p(r), and the series of log1p to r^7 leaves an error below 2^-67.  ln 2
+// is split so that e * ln2_hi is exact.  The error is within a few units of
+// 1e-16 absolute (about 1 ulp where |log x| > 1).  A quarter of the FP64
+// operations of the library log, which bounds the cost of the FP64
+// re-decisions and on-demand rows for KL.
+__device__ __forceinline__ double log_pos(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  // within 2^-8 of 1, r = x - 1 is exact and the table term is dropped, so a
+  // result near 0 keeps its relative accuracy
+  const bool near1 = fabs(x - 1.0) < 0.00390625;
+  const double e = near1 ? 0.0 : (double)((int)((b >> 52) & 0x7ff) - 1023);
+  const int i = (int)((b >> 45) & 127);
+  const double m =
+      __longlong_as_double((long long)((b & 0x000fffffffffffffull) | 0x3ff0000000000000ull));
+  const double r = near1 ? x - 1.0 : fma(m, g_logtab[128 + i], -1.0);
+  const double t = near1 ? 0.0 : g_logtab[i];
+  double q = 1.0 / 7.0;
+  q = fma(q, r, -1.0 / 6.0);
+  q = fma(q, r, 1.0 / 5.0);
+  q = fma(q, r, -0.25);
+  q = fma(q, r, 1.0 / 3.0);
+  q = fma(q, r, -0.5);
+  q = fma(q, r, 1.0);
+  const double ln2_hi = 6.93147180369123816490e-01, ln2_lo = 1.90821492927058770002e-10;
+  return e * ln2_hi + (t + fma(e, ln2_lo, q * r));
+}
+
+hipError_t init_log_table() {
+  double h[256];
+  for (int i = 0; i < 128; ++i) {
+    const double c = 1.0 + (i + 0.5) / 128.0;
+    h[i] = std::log(c);
+    h[128 + i] = 1.0 / c;
+  }
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_logtab), h, sizeof h);
+}
+
 // Terms per kind family F: 0 TV, 1 KL, 2 chi-squared, 3 Hellinger, 4 the
 // power family |q - p|^k / p^(k-1) (k = param), 5 the alpha-divergence term
 // p (1 - (q/p)^(param/16)) (its factor 4/(1 - alpha^2) is applied to the sum).
@@ -145,7 +190,7 @@ template <int F>
 __device__ __forceinline__ double term64(double pb, double lpb, double q, int param) {
   const double df = q - pb;
   if (F == 0) return fabs(df);
-  if (F == 1) return pb > 0.0 ? pb * (lpb - log(q)) : 0.0;
+  if (F == 1) return pb > 0.0 ? pb * (lpb - (q > 0.0 ? log_pos(q) : -__builtin_inf())) : 0.0;
   if (F == 5) return pb > 0.0 ? pb * (1.0 - pow(q / pb, (double)param / 16.0)) : 0.0;
   if (df == 0.0) return 0.0;
   if (F == 4) {
