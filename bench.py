@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-ROOT = os.path.dirname(os.path.abspath(__file__))
+MFMA_PEAK_TFLOPS = {"f16x3": 2500.0, "f32": 157.3}
 # source file of each measured kernel, for matching counter records to the code
 KERNEL_SOURCE = {"dense_tv": "stream.hip", "dense_kl": "stream.hip", "csr_tv": "stream.hip",
                  "csr_kl": "stream.hip", "gemm_kl_T1": "gemm.hip", "kl_gemm_f16x3": "gemm.hip"}
@@ -54,7 +54,8 @@ def measured_traffic(workload, kernel):
             if len(t) == 5 and t[0] == workload and t[1] == kernel and t[4] == sha:
                 return int(t[2]) + int(t[3])
     return None
-MFMA_PEAK_TFLOPS = {"f16x3": 2500.0, "f32": 157.3}
+
+
 METRIC = "kernel entries/sec (N·B·targets/s)"
 
 
