@@ -215,6 +215,15 @@ def run_grid1025(args):
             "local_minima_certain": int(counts[0, 0].item()),
             "local_minima_undecided": int(counts[0, 1].item())}
         log(f"csr {kind}: {us:.0f} us, minima {counts[0].tolist()}")
+    res.update(csr_batch_rows(kc, ts_all, "tau1e-5"))
+    kc.free()
+    torch.cuda.empty_cache()
+    # second truncation point: an absolute threshold that keeps about 5% of the entries
+    tau_abs = 4e-4
+    log(f"loading the absolute tau={tau_abs:g} truncation")
+    kc = Kernel.load_dense(ctx, P, tau=tau_abs, tau_relative=False,
+                           adjacency=(g.adj_ptr, g.adj_idx))
+    res.update(csr_batch_rows(kc, ts_all, f"abs{tau_abs:g}"))
     kc.free()
     ctx.close()
     main_row = res["a5_batched_kl_f16x3_T64"]
@@ -231,6 +240,51 @@ def run_grid1025(args):
                         "traffic": measured_traffic("grid1025_T64", "kl_gemm_f16x3")},
            "rows": res}
     print(json.dumps(out), flush=True)
+
+
+def csr_batch_rows(kc, ts_all, label):
+    """The many-target pass over the truncated rows at T = 256 (TV and KL),
+    with the local-minimum census of the 256 fields.
+
+    Per stored entry and target it reads 4 bytes of target weights from LDS
+    (peak 128 B per clock per CU: 78.6 TB/s at 256 CUs and 2.4 GHz) and issues
+    2 (TV: min, add) or 1 (KL: FMA) VALU operations (non-packed FP32 peak
+    256 x 64 lanes x 2.4 GHz = 39.3e12 per second)."""
+    import torch
+    N, B, nnz = kc.N, kc.B, kc.nnz
+    T = 256
+    ts = ts_all[:T]
+    D = torch.empty((T, N), dtype=torch.float32, device="cuda:0")
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    out = {}
+    for kind in ("tv", "kl"):
+        kc.batch_fields(ts, kind, out=D)
+        torch.cuda.synchronize()
+        reps = 3
+        a.record()
+        for _ in range(reps):
+            _, bounds = kc.batch_fields(ts, kind, out=D)
+        b.record()
+        torch.cuda.synchronize()
+        us = 1000.0 * a.elapsed_time(b) / reps
+        upd = nnz * T / (us * 1e-6)
+        byts = nnz * 6 + N * 16 + T * N * 4
+        ops = 2 if kind == "tv" else 1
+        cls, counts = kc.local_minima(ts, D, bounds)
+        c = counts.cpu().numpy()
+        out[f"a4_csr_batch_{kind}_{label}_T{T}"] = {
+            "avg_us": round(us, 1), "nnz": nnz, "nnz_frac": round(nnz / (N * B), 4),
+            "entry_updates_per_s": upd, "entries_per_s": N * B * T / (us * 1e-6),
+            "lds_frac": round(upd * 4 / 78.6e12, 4),
+            "valu_frac": round(upd * ops / 39.3e12, 4),
+            "GB/s": round(gbs(byts, us), 1),
+            "local_minima_per_field": {"certain_mean": float(c[:, 0].mean()),
+                                       "certain_max": int(c[:, 0].max()),
+                                       "undecided_mean": float(c[:, 1].mean())}}
+        log(f"csr batch {kind} {label}: {us:.0f} us for {T} targets")
+    del D
+    return out
 
 
 def cpu_baseline(P32, tau, t, s, adj, max_steps, entries_per_step):

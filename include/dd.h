@@ -185,8 +185,15 @@ dd_status dd_distance_field(dd_kernel* k, int32_t target, int32_t kind, float* o
  * built with a gemm_form the fields come from one contraction,
  *     d(x,t) = H_t - o_x W_t - sum_b P_tb l_xb,
  * with l_xb = log P_xb - o_x, o_x = log max_b P_xb, H_t = sum_b P_tb log P_tb
- * and W_t = sum_b P_tb (eq. 35 expanded).  Otherwise one streaming pass per
- * target.  bounds: nullable host [T].  Asynchronous on `stream`. */
+ * and W_t = sum_b P_tb (eq. 35 expanded).  On a truncated (CSR) handle with
+ * T >= 8, TV or KL, the fields come from one pass over the stored rows per
+ * group of up to 256 targets, with
+ *     TV_tau(x,t) = W_t + Q_x - 2 sum_{b in S_x} min(P~_xb, P~_tb),
+ *     KL_tau(x,t) = H_t - log(phi_x) W_t - sum_{b in S_x} P~_tb log(P~_xb / phi_x)
+ * (Q_x = sum_{b in S_x} P~_xb; the truncated fields of dd_load_kernel_csr
+ * rearranged); a target's field is then bit-identical in every such batch.
+ * Otherwise one streaming pass per target.  bounds: nullable host [T].
+ * Asynchronous on `stream`. */
 dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t T,
                                    int32_t kind, float* out_dev, dd_error_bound* bounds,
                                    void* stream);

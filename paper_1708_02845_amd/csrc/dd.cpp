@@ -22,6 +22,8 @@ constexpr uint32_t kKernelMagic = 0xDD0E4E11u;
 constexpr uint32_t kDead = 0xDEADDEADu;
 constexpr double kU = 5.9604644775390625e-08;   // 2^-24, FP32 unit roundoff
 constexpr int kMaxDegree = 64;
+// a truncated handle takes the many-target pass from this many targets up
+constexpr int32_t kCsrBatchMin = 8;
 constexpr int32_t kMaxB = 16384;                // the target row must fit in LDS
 
 thread_local std::string g_err;
@@ -111,6 +113,7 @@ struct dd_kernel {
   DevBuf start, len, col, val, val64, phi, lphi;
   int64_t nnz = 0;
   std::vector<double> Ht_host, Wt_host;   // per row over the stored entries
+  double lphi_absmax = 0.0;               // max_x |log2 phi_x|
   // adjacency
   DevBuf adj;          // [N][adj_w] int32, -1 padded
   int32_t adj_w = 0;
@@ -304,10 +307,36 @@ dd_error_bound gemm_bound(const dd_kernel* k, int32_t t) {
   return b;
 }
 
+// Bound of a truncated field from the many-target pass.  Per chunk of 32
+// columns FP32 partial sums (31u of their magnitude), then FP64.
+//   TV: d = W_t + Q_x - 2M, M = sum_{S_x} min(q, p~) <= W_t: 62u W_t.
+//   KL: d = ln2 (Hb_t - log2(phi_x) W_t - S), S = sum_{S_x} p~ g with
+//       g = hw_log2(q * fl(1/phi_x)): 2u relative in the argument (2.9u
+//       absolute in g), hardware log2 4u|g| + 4u, product u, partial sums
+//       31u; S <= |Hb_t| + max|log2 phi| W_t since d >= 0.
+dd_error_bound csr_batch_bound(const dd_kernel* k, int kind, int32_t t) {
+  const double H = std::fabs(k->Ht_host[t]);
+  const double W = k->Wt_host[t];
+  const double ln2 = 0.69314718055994530942;
+  dd_error_bound b;
+  b.rel = kU;
+  if (kind == DD_TV)
+    b.abs = 62.0 * kU * W;
+  else
+    b.abs = ln2 * 6.9 * kU * W + 36.0 * kU * (H + ln2 * k->lphi_absmax * W);
+  b.abs = 2.0 * b.abs + 1e-300;
+  b.rel *= 2.0;
+  return b;
+}
+
 // log2 of each row's floor, for the streaming kernel's missing-support term.
 dd_status upload_log2_floor(dd_kernel* k, const std::vector<double>& phi) {
   std::vector<double> l(phi.size());
-  for (size_t i = 0; i < phi.size(); ++i) l[i] = std::log2(phi[i]);
+  k->lphi_absmax = 0.0;
+  for (size_t i = 0; i < phi.size(); ++i) {
+    l[i] = std::log2(phi[i]);
+    k->lphi_absmax = std::max(k->lphi_absmax, std::fabs(l[i]));
+  }
   HIP_OR(k->lphi.alloc(8 * l.size()));
   HIP_OR(hipMemcpy(k->lphi.p, l.data(), 8 * l.size(), hipMemcpyHostToDevice));
   return DD_OK;
@@ -739,6 +768,21 @@ dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t
     }
     if (bounds)
       for (int32_t i = 0; i < T; ++i) bounds[i] = gemm_bound(k, targets[i]);
+    return DD_OK;
+  }
+  if (k->is_csr && T >= kCsrBatchMin) {
+    // one pass over the stored rows per group of up to 256 targets
+    AsyncBuf ws(s);
+    HIP_OR(ws.alloc(dd::csr_batch_workspace(k->csr(), std::min<int32_t>(T, dd::kMaxBatch))));
+    for (int32_t g0 = 0; g0 < T; g0 += dd::kMaxBatch) {
+      const int32_t n = std::min<int32_t>(dd::kMaxBatch, T - g0);
+      dd::TargetList tl;
+      std::memset(&tl, 0, sizeof tl);
+      for (int32_t i = 0; i < n; ++i) tl.t[i] = targets[g0 + i];
+      HIP_OR(dd::launch_csr_batch(k->csr(), tl, n, kind, ws.p, out_dev + (int64_t)g0 * k->N, s));
+    }
+    if (bounds)
+      for (int32_t i = 0; i < T; ++i) bounds[i] = csr_batch_bound(k, kind, targets[i]);
     return DD_OK;
   }
   for (int32_t i = 0; i < T; ++i) {

@@ -81,6 +81,13 @@ struct TargetList {
   int32_t t[kMaxBatch];
 };
 size_t batch_kl_workspace(GemmView gv, int32_t T);
+
+// Truncated fields of many targets in one pass over the stored rows
+// (csr_batch.hip).  Up to kMaxBatch targets per launch; ws holds
+// csr_batch_workspace(v, T) bytes.
+size_t csr_batch_workspace(CsrView v, int32_t T);
+hipError_t launch_csr_batch(CsrView v, TargetList tl, int32_t T, int kind, void* ws, float* out,
+                            hipStream_t s);
 hipError_t launch_batch_kl(DenseView dv, GemmView gv, TargetList tl, int32_t T, void* ws,
                            float* out, hipStream_t s);
 
