@@ -218,6 +218,30 @@ def run_grid1025(args):
     res.update(csr_batch_rows(kc, ts_all, "tau1e-5"))
     kc.free()
     torch.cuda.empty_cache()
+    # the same truncation with FP16 stored values (4 bytes per stored entry)
+    log(f"loading the tau={tau:g} truncation with FP16 values")
+    kc = Kernel.load_dense(ctx, P, tau=tau, adjacency=(g.adj_ptr, g.adj_idx), csr_values="f16")
+    for kind in ("tv", "kl"):
+        kc.field(t0_, kind, out=f[0])
+        torch.cuda.synchronize()
+        reps = 5
+        a.record()
+        for _ in range(reps):
+            _, bd = kc.field(t0_, kind, out=f[0])
+        b.record()
+        torch.cuda.synchronize()
+        us = 1000.0 * a.elapsed_time(b) / reps
+        byts = nnz * 4 + N * (20 if kind == "tv" else 28)
+        cls, counts = kc.local_minima([t0_], f, [bd])
+        res[f"a4_csr_{kind}_tau1e-5_f16"] = {
+            "avg_us": round(us, 1), "nnz": nnz, "alg_bytes": byts, "GB/s": round(gbs(byts, us), 1),
+            "hbm_frac": round(gbs(byts, us) / HBM_PEAK_GBS, 4), "bound_abs": bd[0],
+            "local_minima_certain": int(counts[0, 0].item()),
+            "local_minima_undecided": int(counts[0, 1].item())}
+        log(f"csr f16 {kind}: {us:.0f} us, minima {counts[0].tolist()}")
+    res.update(csr_batch_rows(kc, ts_all, "tau1e-5_f16"))
+    kc.free()
+    torch.cuda.empty_cache()
     # second truncation point: an absolute threshold that keeps about 5% of the entries
     tau_abs = 4e-4
     log(f"loading the absolute tau={tau_abs:g} truncation")

@@ -79,6 +79,18 @@ typedef enum {
   DD_FORM_F16X3 = 1    /* FP16 hi+lo split of the log-kernel and of the targets, 3 MFMA products */
 } dd_form;
 
+/* Storage of the stored values of a truncated (CSR) handle, as read by the
+ * field entry points.  The FP32 values stay resident in both forms: the path
+ * entry points re-decide near-ties from them (or from the FP64 input). */
+typedef enum {
+  DD_CSR_F32 = 0,   /* FP32 values: 6 bytes per stored entry with the column */
+  DD_CSR_F16 = 1    /* FP16 values scaled per row by a power of two (row max in
+                       [2^14, 2^15)): 4 bytes per stored entry; each value is
+                       within 2^-11 relative of the FP32 value, and the stated
+                       bounds include that rounding.  Needs every row's floor
+                       phi_x >= 2^-28 max_b P_xb and max_b P_xb >= 2^-100. */
+} dd_csr_values;
+
 typedef enum {
   DD_PATH_REACHED = 0,   /* the walk arrived at the target */
   DD_PATH_STUCK = 1,     /* no neighbour strictly lower: a local minimum (or plateau) */
@@ -102,6 +114,7 @@ typedef struct {
   double tau;            /* > 0: keep only the truncation of P (CSR form); 0: dense */
   int32_t tau_relative;  /* 1: keep P_xb >= tau * max_b P_xb; 0: keep P_xb >= tau */
   int32_t validate;      /* 1: reject rows that are not probability vectors */
+  int32_t csr_values;    /* dd_csr_values of a truncated handle (ignored when dense) */
 } dd_load_opts;
 
 typedef struct {
@@ -118,6 +131,7 @@ typedef struct {
   int32_t gemm_form;   /* dd_form built, or DD_FORM_NONE */
   int32_t has_adjacency;
   size_t hbm_bytes;    /* device memory held by the handle */
+  int32_t csr_values;  /* dd_csr_values read by the field entry points (truncated handles) */
 } dd_kernel_info;
 
 /* Create a context on HIP device `device`.  *out receives the handle. */
@@ -135,7 +149,8 @@ dd_status dd_destroy(dd_ctx* ctx);
  *   P           host or device pointer to N*B values, FP32 (p_is_f64 == 0) or
  *               FP64 (p_is_f64 == 1); p_on_device says which memory it is.
  *   adj         nullable; needed by the path entry points.
- *   opts        nullable (defaults: gemm_form DD_FORM_NONE, tau 0, validate 1).
+ *   opts        nullable (defaults: gemm_form DD_FORM_NONE, tau 0, validate 1,
+ *               csr_values DD_CSR_F32).
  * Entries must be finite and >= 0; positive entries below the FP32 normal
  * range (1.17549435e-38) are rejected.  With validate, every row sum must be
  * 1 within 1e-5 (FP32 input) or 1e-9 (FP64 input).  All-zero columns are

@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libdd.so")
 DD_OK, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ESTATE = range(5)
 DD_TV, DD_KL, DD_CHI2, DD_HELLINGER = 0, 1, 2, 3
 DD_FORM_NONE, DD_FORM_F32, DD_FORM_F16X3 = -1, 0, 1
+DD_CSR_F32, DD_CSR_F16 = 0, 1
 DD_PATH_REACHED, DD_PATH_STUCK, DD_PATH_MAX_STEPS = 0, 1, 2
 
 STATUS_NAMES = {0: "DD_OK", 1: "DD_EINVAL", 2: "DD_ENOMEM", 3: "DD_EDEVICE", 4: "DD_ESTATE"}
@@ -26,7 +27,7 @@ class dd_adjacency(C.Structure):
 
 class dd_load_opts(C.Structure):
     _fields_ = [("gemm_form", C.c_int32), ("tau", C.c_double), ("tau_relative", C.c_int32),
-                ("validate", C.c_int32)]
+                ("validate", C.c_int32), ("csr_values", C.c_int32)]
 
 
 class dd_error_bound(C.Structure):
@@ -36,7 +37,7 @@ class dd_error_bound(C.Structure):
 class dd_kernel_info(C.Structure):
     _fields_ = [("n", C.c_int32), ("b_in", C.c_int32), ("b", C.c_int32), ("is_csr", C.c_int32),
                 ("nnz", C.c_int64), ("gemm_form", C.c_int32), ("has_adjacency", C.c_int32),
-                ("hbm_bytes", C.c_size_t)]
+                ("hbm_bytes", C.c_size_t), ("csr_values", C.c_int32)]
 
 
 EXPORTS = {

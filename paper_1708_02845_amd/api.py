@@ -15,6 +15,7 @@ KINDS = {"tv": L.DD_TV, "kl": L.DD_KL, "chi2": L.DD_CHI2, "hellinger": L.DD_HELL
 KINDS.update({v: v for v in list(KINDS.values())})
 FORMS = {None: L.DD_FORM_NONE, "none": L.DD_FORM_NONE, "f32": L.DD_FORM_F32,
          "f16x3": L.DD_FORM_F16X3}
+CSR_VALUES = {"f32": L.DD_CSR_F32, "f16": L.DD_CSR_F16}
 PATH_STATUS = {L.DD_PATH_REACHED: "reached", L.DD_PATH_STUCK: "stuck",
                L.DD_PATH_MAX_STEPS: "max_steps"}
 
@@ -100,12 +101,15 @@ class Kernel:
         self.gemm_form = info.gemm_form
         self.has_adjacency = bool(info.has_adjacency)
         self.hbm_bytes = info.hbm_bytes
+        self.csr_values = {0: "f32", 1: "f16"}[info.csr_values] if self.is_csr else None
 
     # ---- loading ----
     @classmethod
     def load_dense(cls, ctx, P, adjacency=None, gemm_form=None, tau=0.0, tau_relative=True,
-                   validate=True):
-        """Load an N x B matrix given as a numpy array or a torch tensor (any device)."""
+                   validate=True, csr_values="f32"):
+        """Load an N x B matrix given as a numpy array or a torch tensor (any device).
+        With tau > 0 the handle keeps the truncation, its values read as FP32 or,
+        with csr_values="f16", as FP16 scaled per row."""
         torch = _torch()
         keep = []
         if isinstance(P, np.ndarray):
@@ -124,7 +128,7 @@ class Kernel:
             N, B = t.shape
         adj, adj_keep = _adjacency(adjacency, N)
         opts = L.dd_load_opts(FORMS[gemm_form], float(tau), int(bool(tau_relative)),
-                              int(bool(validate)))
+                              int(bool(validate)), CSR_VALUES[csr_values])
         h = C.c_void_p()
         L.check(ctx._lib.dd_load_kernel_dense(ctx.handle, int(N), int(B), C.c_void_p(ptr), f64,
                                               on_dev, C.byref(adj) if adj else None,
@@ -134,7 +138,7 @@ class Kernel:
 
     @classmethod
     def load_csr(cls, ctx, N, B, row_ptr, col, val, row_max, tau, tau_relative=True,
-                 adjacency=None):
+                 adjacency=None, csr_values="f32"):
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
         cl = np.ascontiguousarray(col, dtype=np.int32)
         vl = np.ascontiguousarray(val)
@@ -143,17 +147,19 @@ class Kernel:
         rm = np.ascontiguousarray(row_max, dtype=np.float64)
         adj, adj_keep = _adjacency(adjacency, N)
         h = C.c_void_p()
+        opts = L.dd_load_opts(L.DD_FORM_NONE, 0.0, 1, 1, CSR_VALUES[csr_values])
         L.check(ctx._lib.dd_load_kernel_csr(
             ctx.handle, int(N), int(B), C.c_void_p(rp.ctypes.data), C.c_void_p(cl.ctypes.data),
             C.c_void_p(vl.ctypes.data), int(vl.dtype == np.float64), C.c_void_p(rm.ctypes.data),
-            float(tau), int(bool(tau_relative)), C.byref(adj) if adj else None, None, C.byref(h)))
+            float(tau), int(bool(tau_relative)), C.byref(adj) if adj else None, C.byref(opts),
+            C.byref(h)))
         del adj_keep
         return cls(ctx, h)
 
     @staticmethod
     def dense_footprint(N, B, f64=False, gemm_form=None):
         lib = L.load()
-        opts = L.dd_load_opts(FORMS[gemm_form], 0.0, 1, 1)
+        opts = L.dd_load_opts(FORMS[gemm_form], 0.0, 1, 1, 0)
         out = C.c_size_t()
         L.check(lib.dd_dense_footprint(int(N), int(B), int(bool(f64)), C.byref(opts), C.byref(out)))
         return out.value

@@ -180,6 +180,24 @@ __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, i
   if (__ballot(nz) != 0ull && lane == 0) atomicAdd(zeros, 1);
 }
 
+// One wave per row: val16 = FP16(val * 2^e_x), round to nearest even; the
+// scaling is exact (a power of two, no overflow: the row max lands in
+// [2^14, 2^15)).
+__global__ __launch_bounds__(256) void csr_f16_kernel(const int64_t* start, const int32_t* len,
+                                                      const float* val, const float* rscale,
+                                                      int32_t N, uint16_t* val16) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= N) return;
+  const int64_t s = start[row];
+  const int n = len[row];
+  const float sc = 1.0f / rscale[row];
+  for (int i = lane; i < n; i += 64) {
+    const _Float16 h = (_Float16)(val[s + i] * sc);
+    val16[s + i] = __builtin_bit_cast(uint16_t, h);
+  }
+}
+
 static int rows_grid(int64_t N) { return (int)((N + 3) / 4); }
 
 hipError_t launch_row_stats(const void* raw, int is_f64, int32_t N, int32_t B, double* row_sum,
@@ -219,6 +237,13 @@ hipError_t launch_trunc_fill(DenseView v, const double* thr, const int64_t* star
                              float* val, double* val64, hipStream_t s) {
   hipLaunchKernelGGL(trunc_fill_kernel, dim3(rows_grid(v.N)), dim3(256), 0, s, v, thr, start, col,
                      val, val64);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_f16(const int64_t* start, const int32_t* len, const float* val,
+                          const float* rscale, int32_t N, uint16_t* val16, hipStream_t s) {
+  hipLaunchKernelGGL(csr_f16_kernel, dim3(rows_grid(N)), dim3(256), 0, s, start, len, val, rscale,
+                     N, val16);
   return hipGetLastError();
 }
 

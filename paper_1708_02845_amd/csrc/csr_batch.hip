@@ -34,6 +34,11 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
 
+// Stored value of the FP16 form: FP16 bits times the row's 2^-e_x.
+__device__ __forceinline__ float f16_value(uint16_t h, float rs) {
+  return (float)__builtin_bit_cast(_Float16, h) * rs;
+}
+
 __device__ __forceinline__ int rdlane(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
 __device__ __forceinline__ float rdlane(float v, int j) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
@@ -56,10 +61,11 @@ __global__ __launch_bounds__(256) void csr_targets_kernel(CsrView v, TargetList 
   const int32_t t = tl.t[slot];
   const int64_t s = v.start[t];
   const int n = v.len[t];
+  const float rs = v.val16 ? v.rscale[t] : 1.f;
   double w = 0.0, hb = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int b = v.col[s + i];
-    const float p = v.val[s + i];
+    const float p = v.val16 ? f16_value(v.val16[s + i], rs) : v.val[s + i];
     tb[(int64_t)b * Tp + slot] = p;
     w += (double)p;
     hb += (double)(p * hw_log2(p));
@@ -90,20 +96,25 @@ __global__ __launch_bounds__(256) void csr_targets_kernel(CsrView v, TargetList 
 // clamped into the row, so every lane loads and no result is consumed yet);
 // take_window turns the fetched column and value into the working form:
 // column kEnd past the row's end, and q (TV) or g = log2(q / phi) (KL).
+// With F16 the fetched value is the FP16 bits (carried in a float register)
+// and q = FP16 value times the row's 2^-e_x.
 // The loaders reject rows without entries; the rows past N of the last
 // workgroup (n = 0) read entry 0 of the arrays and mark every lane past the end.
+template <int F16>
 __device__ __forceinline__ void fetch_window(const CsrView& v, int64_t s, int n, int base,
                                              int lane, int& rc, float& rq) {
   const int64_t i = n > 0 ? s + min(base + lane, n - 1) : 0;
   rc = v.col[i];
-  rq = v.val[i];
+  rq = F16 ? __int_as_float((int)v.val16[i]) : v.val[i];
 }
 
-template <int KIND>
-__device__ __forceinline__ void take_window(int n, int base, int lane, float rphi, int rc,
-                                            float rq, int& col, float& val, double& qsum) {
+template <int KIND, int F16>
+__device__ __forceinline__ void take_window(int n, int base, int lane, float rphi, float rs,
+                                            int rc, float rq, int& col, float& val,
+                                            double& qsum) {
   const bool ok = base + lane < n;
   col = ok ? rc : kEnd;
+  if (F16) rq = f16_value((uint16_t)__float_as_int(rq), rs);
   if (KIND == 0) {
     val = rq;
     qsum += ok ? (double)rq : 0.0;
@@ -142,7 +153,7 @@ __device__ __forceinline__ void accumulate(const float (&p)[TPL], float g, float
   }
 }
 
-template <int KIND, int TPL, int R>
+template <int KIND, int TPL, int R, int F16>
 __global__ __launch_bounds__(kWaves * 64) void csr_batch_kernel(CsrView v,
                                                                const float* __restrict__ tb,
                                                                const double* __restrict__ wt,
@@ -161,7 +172,7 @@ __global__ __launch_bounds__(kWaves * 64) void csr_batch_kernel(CsrView v,
 
   int64_t rs[R];
   int rn[R], wnext[R], j0[R], col[R], ncol[R];
-  float val[R], nval[R], rphi[R];
+  float val[R], nval[R], rphi[R], rsc[R];
   double qsum[R];
   float a32[R][TPL];
   double a64[R][TPL];
@@ -172,13 +183,14 @@ __global__ __launch_bounds__(kWaves * 64) void csr_batch_kernel(CsrView v,
     rs[r] = ok ? v.start[row] : 0;
     rn[r] = ok ? v.len[row] : 0;
     rphi[r] = ok && KIND == 1 ? (float)(1.0 / v.phi[row]) : 0.f;
+    rsc[r] = ok && F16 ? v.rscale[row] : 1.f;
     qsum[r] = 0.0;
     j0[r] = 0;
     int rc;
     float rq;
-    fetch_window(v, rs[r], rn[r], 0, lane, rc, rq);
-    take_window<KIND>(rn[r], 0, lane, rphi[r], rc, rq, col[r], val[r], qsum[r]);
-    fetch_window(v, rs[r], rn[r], 64, lane, ncol[r], nval[r]);
+    fetch_window<F16>(v, rs[r], rn[r], 0, lane, rc, rq);
+    take_window<KIND, F16>(rn[r], 0, lane, rphi[r], rsc[r], rc, rq, col[r], val[r], qsum[r]);
+    fetch_window<F16>(v, rs[r], rn[r], 64, lane, ncol[r], nval[r]);
     wnext[r] = 128;
 #pragma unroll
     for (int i = 0; i < TPL; ++i) {
@@ -254,10 +266,10 @@ __global__ __launch_bounds__(kWaves * 64) void csr_batch_kernel(CsrView v,
         j0[r] = j1;
         // the whole window consumed and more entries left: move to the next
         if (j1 == 64 && wnext[r] - 64 < rn[r]) {
-          take_window<KIND>(rn[r], wnext[r] - 64, lane, rphi[r], ncol[r], nval[r], col[r],
-                            val[r], qsum[r]);
+          take_window<KIND, F16>(rn[r], wnext[r] - 64, lane, rphi[r], rsc[r], ncol[r], nval[r],
+                                 col[r], val[r], qsum[r]);
           j0[r] = 0;
-          fetch_window(v, rs[r], rn[r], wnext[r], lane, ncol[r], nval[r]);
+          fetch_window<F16>(v, rs[r], rn[r], wnext[r], lane, ncol[r], nval[r]);
           wnext[r] += 64;
           continue;
         }
@@ -321,8 +333,12 @@ hipError_t batch_launch(CsrView v, const float* tb, const double* wt, const doub
   constexpr int R = rows_per_wave(TPL);
   const int64_t rows_per_block = (int64_t)kWaves * R;
   const int64_t grid = (v.N + rows_per_block - 1) / rows_per_block;
-  hipLaunchKernelGGL((csr_batch_kernel<KIND, TPL, R>), dim3((unsigned)grid), dim3(kWaves * 64), 0,
-                     s, v, tb, wt, hbt, tl, T, out);
+  if (v.val16)
+    hipLaunchKernelGGL((csr_batch_kernel<KIND, TPL, R, 1>), dim3((unsigned)grid),
+                       dim3(kWaves * 64), 0, s, v, tb, wt, hbt, tl, T, out);
+  else
+    hipLaunchKernelGGL((csr_batch_kernel<KIND, TPL, R, 0>), dim3((unsigned)grid),
+                       dim3(kWaves * 64), 0, s, v, tb, wt, hbt, tl, T, out);
   return hipGetLastError();
 }
 

@@ -111,6 +111,9 @@ struct dd_kernel {
   DevBuf L32, Lhi, Llo, Off;
   // truncated
   DevBuf start, len, col, val, val64, phi, lphi;
+  DevBuf val16, rsc;   // FP16 form of the stored values and 2^-e_x per row
+  int csr_values = DD_CSR_F32;
+  double qmax = 0.0;   // max_x of the stored row sums
   int64_t nnz = 0;
   std::vector<double> Ht_host, Wt_host;   // per row over the stored entries
   double lphi_absmax = 0.0;               // max_x |log2 phi_x|
@@ -126,6 +129,7 @@ struct dd_kernel {
   size_t footprint() const {
     return P32.bytes + P64.bytes + H.bytes + L32.bytes + Lhi.bytes + Llo.bytes + Off.bytes +
            start.bytes + len.bytes + col.bytes + val.bytes + val64.bytes + phi.bytes + lphi.bytes +
+           val16.bytes + rsc.bytes +
            adj.bytes + mesh_faces.bytes + mesh_xy.bytes + mesh_vf.bytes;
   }
   dd::DenseView dense() const {
@@ -135,7 +139,8 @@ struct dd_kernel {
     return dd::CsrView{start.as<const int64_t>(), len.as<const int32_t>(),
                        col.as<const uint16_t>(),  val.as<const float>(),
                        val64.as<const double>(),  phi.as<const double>(),
-                       lphi.as<const double>(),   N, B};
+                       lphi.as<const double>(),   val16.as<const uint16_t>(),
+                       rsc.as<const float>(),     N, B};
   }
 };
 
@@ -150,6 +155,7 @@ dd_load_opts default_opts() {
   o.tau = 0.0;
   o.tau_relative = 1;
   o.validate = 1;
+  o.csr_values = DD_CSR_F32;
   return o;
 }
 
@@ -224,6 +230,24 @@ dd_status check_kind(const dd_kernel* k, int32_t kind) {
   return fail(DD_EINVAL, "unknown kind %d", kind);
 }
 
+// FP16 storage of a truncated handle's values (DD_CSR_F16): every stored
+// value, target row included, moves by at most eps = 2^-11 + 2^-24 of itself
+// (FP16 rounding of the FP32 value, itself within 2^-24 of an FP64 input).
+//   TV: sum |q - p| moves by at most eps (Q_x + W_t) <= eps (Qmax + W_t).
+//   KL: p (log p - log q) moves by at most eps p |log(p/q)| + 2.002 eps p, and
+//       sum_{S_t} p |log(p/q)| <= d + 2 sum_{q > p} (q - p) <= d + 2 Qmax
+//       (p log(q/p) <= q - p), so eps d + eps (2 Qmax + 2.002 W_t).
+void add_f16_storage(const dd_kernel* k, int kind, double W, dd_error_bound& b) {
+  if (k->csr_values != DD_CSR_F16) return;
+  const double eps = std::ldexp(1.0, -11) + kU;
+  if (kind == DD_TV) {
+    b.abs += eps * (k->qmax + W);
+  } else {
+    b.rel += eps;
+    b.abs += eps * (2.0 * k->qmax + 2.002 * W);
+  }
+}
+
 // Error bound of a field, in the sense of include/dd.h.  u is the FP32 unit
 // roundoff; hardware log2 is taken to be within 4u*|log2 y| + 4u of log2 y.
 dd_error_bound field_bound(const dd_kernel* k, int kind, int32_t t) {
@@ -278,6 +302,7 @@ dd_error_bound field_bound(const dd_kernel* k, int kind, int32_t t) {
       b.rel = 11.0 * kU;
       b.abs = 40.0 * kU * H + 12.0 * kU * W;
     }
+    add_f16_storage(k, kind, W, b);
   }
   // FP64 accumulation over B terms: negligible next to the FP32 terms, kept
   // for completeness.
@@ -315,6 +340,9 @@ dd_error_bound gemm_bound(const dd_kernel* k, int32_t t) {
 //       absolute in g), hardware log2 4u|g| + 4u, product u, partial sums
 //       31u; S <= |Hb_t| + max|log2 phi| W_t since d >= 0.
 dd_error_bound csr_batch_bound(const dd_kernel* k, int kind, int32_t t) {
+  dd_error_bound f16;
+  f16.abs = f16.rel = 0.0;
+  add_f16_storage(k, kind, k->Wt_host[t], f16);
   const double H = std::fabs(k->Ht_host[t]);
   const double W = k->Wt_host[t];
   const double ln2 = 0.69314718055994530942;
@@ -324,8 +352,8 @@ dd_error_bound csr_batch_bound(const dd_kernel* k, int kind, int32_t t) {
     b.abs = 62.0 * kU * W;
   else
     b.abs = ln2 * 6.9 * kU * W + 36.0 * kU * (H + ln2 * k->lphi_absmax * W);
-  b.abs = 2.0 * b.abs + 1e-300;
-  b.rel *= 2.0;
+  b.abs = 2.0 * (b.abs + f16.abs) + 1e-300;
+  b.rel = 2.0 * (b.rel + f16.rel);
   return b;
 }
 
@@ -391,8 +419,37 @@ dd_status build_csr_from_dense(dd_kernel* k, dd::DenseView dv, const DevBuf& row
   return DD_OK;
 }
 
+// FP16 form of the stored values (DD_CSR_F16): row x scaled by 2^e_x with
+// its max in [2^14, 2^15), so every kept value (>= phi_x >= 2^-28 max) is an
+// FP16 normal number.  rowmax: the max stored value of each row.
+dd_status build_csr_f16(dd_kernel* k, const std::vector<double>& rowmax,
+                        const std::vector<double>& phi) {
+  const int32_t N = k->N;
+  std::vector<float> rs(N);
+  for (int32_t x = 0; x < N; ++x) {
+    if (!(rowmax[x] >= std::ldexp(1.0, -100)))
+      return fail(DD_EINVAL, "FP16 values: row %d has max %g below 2^-100", x, rowmax[x]);
+    if (!(phi[x] >= std::ldexp(rowmax[x], -28)))
+      return fail(DD_EINVAL, "FP16 values: row %d keeps entries below 2^-28 of its max", x);
+    int E = 0;
+    (void)std::frexp(rowmax[x], &E);   // rowmax in [2^(E-1), 2^E)
+    rs[x] = std::ldexp(1.0f, E - 15);  // 2^-e_x with e_x = 15 - E
+  }
+  const size_t pos = k->col.bytes / sizeof(uint16_t);
+  HIP_OR(k->rsc.alloc(sizeof(float) * (size_t)N));
+  HIP_OR(k->val16.alloc(sizeof(uint16_t) * pos));
+  HIP_OR(hipMemcpy(k->rsc.p, rs.data(), sizeof(float) * (size_t)N, hipMemcpyHostToDevice));
+  HIP_OR(hipMemset(k->val16.p, 0, sizeof(uint16_t) * pos));
+  HIP_OR(dd::launch_csr_f16(k->start.as<const int64_t>(), k->len.as<const int32_t>(),
+                            k->val.as<const float>(), k->rsc.as<const float>(), N,
+                            k->val16.as<uint16_t>(), nullptr));
+  HIP_OR(hipDeviceSynchronize());
+  k->csr_values = DD_CSR_F16;
+  return DD_OK;
+}
+
 // Per-row W and H over the stored entries of a CSR handle (host copies).
-dd_status csr_row_constants(dd_kernel* k) {
+dd_status csr_row_constants(dd_kernel* k, std::vector<double>* rowmax) {
   const int32_t N = k->N;
   std::vector<int64_t> st(N);
   std::vector<int32_t> ln(N);
@@ -409,15 +466,20 @@ dd_status csr_row_constants(dd_kernel* k) {
   }
   k->Ht_host.assign(N, 0.0);
   k->Wt_host.assign(N, 0.0);
+  k->qmax = 0.0;
+  if (rowmax) rowmax->assign(N, 0.0);
   for (int32_t x = 0; x < N; ++x) {
-    double w = 0.0, h = 0.0;
+    double w = 0.0, h = 0.0, m = 0.0;
     for (int32_t i = 0; i < ln[x]; ++i) {
       const double p = v[st[x] + i];
       w += p;
+      m = std::max(m, p);
       if (p > 0.0) h += p * std::log(p);
     }
     k->Wt_host[x] = w;
     k->Ht_host[x] = h;
+    k->qmax = std::max(k->qmax, w);
+    if (rowmax) (*rowmax)[x] = m;
   }
   return DD_OK;
 }
@@ -481,6 +543,8 @@ dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P,
     return fail(DD_EINVAL, "tau must be in [0, 1]");
   if (o.tau > 0.0 && o.gemm_form != DD_FORM_NONE)
     return fail(DD_EINVAL, "a truncated load has no batched-KL operand");
+  if (o.csr_values != DD_CSR_F32 && o.csr_values != DD_CSR_F16)
+    return fail(DD_EINVAL, "unknown csr_values %d", o.csr_values);
   if (dd_status s = check_adjacency(N, adj)) return s;
   HIP_OR(hipSetDevice(ctx->device));
 
@@ -571,7 +635,14 @@ dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P,
   if (o.tau > 0.0) {
     if (k->B > 65535) return bail(fail(DD_EINVAL, "CSR columns are 16-bit: B=%d", k->B));
     if (dd_status s = build_csr_from_dense(k, k->dense(), rmax)) return bail(s);
-    if (dd_status s = csr_row_constants(k)) return bail(s);
+    std::vector<double> smax;
+    if (dd_status s = csr_row_constants(k, &smax)) return bail(s);
+    if (o.csr_values == DD_CSR_F16) {
+      std::vector<double> phi(N);
+      hipError_t e = hipMemcpy(phi.data(), k->phi.p, 8 * (size_t)N, hipMemcpyDeviceToHost);
+      if (e) return bail(fail(DD_EDEVICE, "floor copy: %s", hipGetErrorString(e)));
+      if (dd_status s = build_csr_f16(k, smax, phi)) return bail(s);
+    }
     k->P32.release();
     k->P64.release();
   } else {
@@ -631,6 +702,8 @@ dd_status dd_load_kernel_csr(dd_ctx* ctx, int32_t N, int32_t B, const int64_t* r
   const dd_load_opts o = opts ? *opts : default_opts();
   if (o.gemm_form != DD_FORM_NONE)
     return fail(DD_EINVAL, "a truncated load has no batched-KL operand");
+  if (o.csr_values != DD_CSR_F32 && o.csr_values != DD_CSR_F16)
+    return fail(DD_EINVAL, "unknown csr_values %d", o.csr_values);
   if (dd_status s = check_adjacency(N, adj)) return s;
   if (row_ptr[0] != 0) return fail(DD_EINVAL, "row_ptr[0] != 0");
   std::vector<int64_t> st(N);
@@ -672,7 +745,7 @@ dd_status dd_load_kernel_csr(dd_ctx* ctx, int32_t N, int32_t B, const int64_t* r
   std::vector<uint16_t> colp((size_t)pos, 0);
   std::vector<float> valp((size_t)pos, 0.f);
   std::vector<double> val64p(val_is_f64 ? (size_t)pos : 0, 0.0);
-  std::vector<double> phi(N);
+  std::vector<double> phi(N), smax(N, 0.0);
   k->Ht_host.assign(N, 0.0);
   k->Wt_host.assign(N, 0.0);
   for (int32_t x = 0; x < N; ++x) {
@@ -686,9 +759,11 @@ dd_status dd_load_kernel_csr(dd_ctx* ctx, int32_t N, int32_t B, const int64_t* r
       if (val_is_f64) val64p[st[x] + i] = v;
       w += v;
       h += v * std::log(v);
+      smax[x] = std::max(smax[x], v);
     }
     k->Wt_host[x] = w;
     k->Ht_host[x] = h;
+    k->qmax = std::max(k->qmax, w);
     phi[x] = tau_relative ? tau * row_max[x] : tau;
   }
   auto bail = [&](dd_status s) {
@@ -709,6 +784,8 @@ dd_status dd_load_kernel_csr(dd_ctx* ctx, int32_t N, int32_t B, const int64_t* r
   if (!e) e = hipMemcpy(k->phi.p, phi.data(), 8 * (size_t)N, hipMemcpyHostToDevice);
   if (e) return bail(fail(DD_EDEVICE, "CSR upload: %s", hipGetErrorString(e)));
   if (dd_status st = upload_log2_floor(k, phi)) return bail(st);
+  if (o.csr_values == DD_CSR_F16)
+    if (dd_status st = build_csr_f16(k, smax, phi)) return bail(st);
   if (dd_status s = upload_adjacency(k, adj)) return bail(s);
   return finish_handle(k, ctx, out);
 }
@@ -721,6 +798,7 @@ dd_status dd_kernel_get_info(const dd_kernel* k, dd_kernel_info* info) {
   info->b = k->B;
   info->is_csr = k->is_csr;
   info->nnz = k->nnz;
+  info->csr_values = k->csr_values;
   info->gemm_form = k->gemm_form;
   info->has_adjacency = k->has_adj;
   info->hbm_bytes = k->footprint();

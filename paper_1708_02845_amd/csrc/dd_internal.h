@@ -28,6 +28,8 @@ struct CsrView {
   const double* val64;   // [nnz_padded] or nullptr
   const double* phi;     // [N] floor of each row (the truncation threshold)
   const double* lphi;    // [N] log2 of the floor
+  const uint16_t* val16; // [nnz_padded] FP16 bits of val * 2^e_x, or nullptr
+  const float* rscale;   // [N] 2^-e_x (with val16)
   int32_t N, B;
 };
 
@@ -47,6 +49,9 @@ hipError_t launch_row_entropy(DenseView v, double* H, hipStream_t s);
 hipError_t launch_trunc_count(DenseView v, const double* thr, int32_t* counts, hipStream_t s);
 hipError_t launch_trunc_fill(DenseView v, const double* thr, const int64_t* start, uint16_t* col,
                              float* val, double* val64, hipStream_t s);
+// FP16 copy of the stored values, row x scaled by 2^e_x (rscale[x] = 2^-e_x).
+hipError_t launch_csr_f16(const int64_t* start, const int32_t* len, const float* val,
+                          const float* rscale, int32_t N, uint16_t* val16, hipStream_t s);
 hipError_t launch_log_forms(DenseView v, int form, int64_t lda, float* l32, uint16_t* lhi,
                             uint16_t* llo, float* offset, int32_t* zeros, hipStream_t s);
 

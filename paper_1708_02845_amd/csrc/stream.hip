@@ -260,8 +260,13 @@ __global__ __launch_bounds__(512) void support_kl_kernel(const float* __restrict
 // with A_x, E_x the sums of p~_b and p~_b log2 p~_b over S_x, all in FP64;
 // when S_x covers S_t they are FP64 round-off (far inside the stated bound),
 // and the target's own row is set to exactly 0.  Stored values are positive,
-// so the KL terms need no zero guard.
-template <int LPR, int KIND, int UNROLL>
+// so the KL terms need no zero guard.  With F16, the values come from the
+// FP16 form (4 per 8 bytes), times the row's 2^-e_x.
+__device__ __forceinline__ float f16_value(uint16_t h, float rs) {
+  return (float)__builtin_bit_cast(_Float16, h) * rs;
+}
+
+template <int LPR, int KIND, int UNROLL, int F16>
 __global__ __launch_bounds__(512) void csr_field_kernel(CsrView v, int32_t target,
                                                         float* __restrict__ out) {
   // LDS: the truncated target row as (p, log2 p) pairs, zeros where dropped
@@ -273,10 +278,11 @@ __global__ __launch_bounds__(512) void csr_field_kernel(CsrView v, int32_t targe
   __syncthreads();
   const int64_t ts = v.start[target];
   const int tl = v.len[target];
+  const float trs = F16 ? v.rscale[target] : 1.f;
   double w = 0.0, hb = 0.0;
   for (int i = threadIdx.x; i < tl; i += blockDim.x) {
     const int b = v.col[ts + i];
-    const float p = v.val[ts + i];
+    const float p = F16 ? f16_value(v.val16[ts + i], trs) : v.val[ts + i];
     const float l = hw_log2(p);
     spl[b] = make_float2(p, l);
     w += (double)p;
@@ -305,6 +311,8 @@ __global__ __launch_bounds__(512) void csr_field_kernel(CsrView v, int32_t targe
     const int64_t s = v.start[row];
     const int n = v.len[row];
     const float4* val4 = reinterpret_cast<const float4*>(v.val + s);
+    const ushort4* h4 = reinterpret_cast<const ushort4*>((F16 ? v.val16 : v.col) + s);
+    const float rs = F16 ? v.rscale[row] : 1.f;
     const ushort4* col4 = reinterpret_cast<const ushort4*>(v.col + s);
     const int nv = (n + 3) >> 2;
     double acc = 0.0, A = 0.0, E = 0.0;
@@ -315,7 +323,13 @@ __global__ __launch_bounds__(512) void csr_field_kernel(CsrView v, int32_t targe
       for (int u = 0; u < UNROLL; ++u) {
         const int i = base + u * LPR;
         if (i < nv) {
-          q[u] = ld_stream(val4 + i);
+          if (F16) {
+            const ushort4 hq = h4[i];
+            q[u] = make_float4(f16_value(hq.x, rs), f16_value(hq.y, rs), f16_value(hq.z, rs),
+                               f16_value(hq.w, rs));
+          } else {
+            q[u] = ld_stream(val4 + i);
+          }
           cb[u] = col4[i];
         }
       }
@@ -452,9 +466,9 @@ hipError_t launch_support_kl_field(DenseView v, int32_t target, double tau, int 
   return support_launch<16>(v, target, tau, tau_relative, out, s);
 }
 
-template <int LPR, int KIND>
+template <int LPR, int KIND, int F16>
 static hipError_t csr_launch(CsrView v, int32_t target, float* out, hipStream_t s) {
-  auto kern = csr_field_kernel<LPR, KIND, 2>;
+  auto kern = csr_field_kernel<LPR, KIND, 2, F16>;
   const size_t lds = (size_t)((v.B + 3) & ~3) * sizeof(float) * 2;
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
@@ -466,8 +480,12 @@ static hipError_t csr_launch(CsrView v, int32_t target, float* out, hipStream_t 
 
 hipError_t launch_csr_field(CsrView v, int32_t target, int kind, float* out, hipStream_t s) {
   // lanes per row from the mean stored row length
-  if (kind == 0) return csr_launch<64, 0>(v, target, out, s);
-  return csr_launch<64, 1>(v, target, out, s);
+  if (v.val16) {
+    if (kind == 0) return csr_launch<64, 0, 1>(v, target, out, s);
+    return csr_launch<64, 1, 1>(v, target, out, s);
+  }
+  if (kind == 0) return csr_launch<64, 0, 0>(v, target, out, s);
+  return csr_launch<64, 1, 0>(v, target, out, s);
 }
 
 }  // namespace dd

@@ -74,3 +74,33 @@ def test_python_layer_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         _lib.load()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and offsetof of every struct the binding mirrors, from a C program
+    compiled against include/dd.h, equal the ctypes layouts."""
+    import shutil
+    import subprocess
+    from paper_1708_02845_amd import _lib as L
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"dd_load_opts": L.dd_load_opts, "dd_error_bound": L.dd_error_bound,
+               "dd_kernel_info": L.dd_kernel_info, "dd_adjacency": L.dd_adjacency}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dd.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(x.split()[:2]): int(x.split()[2]) for x in out if x.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
