@@ -157,9 +157,11 @@ __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, i
   const double of = (double)(float)o;   // the offset the epilogue will use
   int nz = 0;
   const int64_t R = gemm_row_tiles(v.N);
-  const int64_t tile_base = (row / kGemmRows) * kGemmRows * kGemmK + (row % kGemmRows) * kGemmK;
+  const int64_t tile_base = (row / kGemmRows) * kGemmRows * kGemmK;
+  const int xr = (int)(row % kGemmRows);
   for (int64_t b = lane; b < lda; b += 64) {
-    const int64_t at = tile_base + (b / kGemmK) * R * kGemmRows * kGemmK + (b % kGemmK);
+    const int64_t at = tile_base + (b / kGemmK) * R * kGemmRows * kGemmK +
+                       gemm_tile_offset(form == 0, xr, (int)(b % kGemmK));
     double l = 0.0;
     if (b < v.B) {
       const double p = master_at(v, row, (int)b);

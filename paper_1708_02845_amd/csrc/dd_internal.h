@@ -61,16 +61,25 @@ hipError_t launch_csr_field(CsrView v, int32_t target, int kind, float* out, hip
 
 // ---- batched KL contraction (gemm.hip) ----
 // The log-kernel operand is stored in tiles of kGemmRows rows by kGemmK
-// columns, chunk-major: with R = rows padded / kGemmRows, element (x, b) at
-//   ((b / kGemmK) * R + x / kGemmRows) * kGemmRows * kGemmK
-//     + (x % kGemmRows) * kGemmK + b % kGemmK,
+// columns, chunk-major: with R = rows padded / kGemmRows, the tile of element
+// (x, b) starts at
+//   ((b / kGemmK) * R + x / kGemmRows) * kGemmRows * kGemmK,
 // so one workgroup's chunk is one contiguous block, and the workgroups that
 // run together (consecutive row tiles, all at about the same chunk) read one
 // contiguous window of memory rather than blocks a fixed stride apart, which
-// would load the same memory channels.  Rows are padded to a multiple of
-// kGemmRows and columns to lda; padding holds zeros.
+// would load the same memory channels.  Inside a tile the elements are in the
+// order the contraction's waves load them (gemm_tile_offset): a wave owns 32
+// rows, lane r + 32 h holds row r, columns h*32 + q*V .. + V for its load q
+// (V = 8 FP16 values or 4 FP32 values: 16 bytes), and load q of a wave reads
+// one contiguous kilobyte.  Rows are padded to a multiple of kGemmRows and
+// columns to lda; padding holds zeros.
 constexpr int kGemmRows = 128;
 constexpr int kGemmK = 64;
+__host__ __device__ inline int64_t gemm_tile_offset(int form_f32, int xr, int k) {
+  const int w = xr >> 5, r = xr & 31, h = k >> 5, lane = h * 32 + r;
+  if (form_f32) return ((int64_t)(w * 8 + ((k & 31) >> 2)) * 64 + lane) * 4 + (k & 3);
+  return ((int64_t)(w * 4 + ((k & 31) >> 3)) * 64 + lane) * 8 + (k & 7);
+}
 struct GemmView {
   const float* l32;      // tiled log P - o_x  (form F32)
   const uint16_t* lhi;   // tiled FP16 bits    (form F16X3)

@@ -227,7 +227,9 @@ __global__ __launch_bounds__(256, 2) void kl_gemm_f16x3(GemmView gv, BatchOperan
   const int64_t cstride = gemm_row_tiles(gv.N) * (GROWS * KC);
   const uint16_t* bhp = o.bhi + (int64_t)tbase * gv.lda;
   const uint16_t* blp = o.blo + (int64_t)tbase * gv.lda;
-  const int64_t lane_off = (int64_t)(wv * 32 + r) * KC + h * 32;
+  // load q of this lane: row r, columns h*32 + q*8 .. + 8 of the tile (one
+  // contiguous kilobyte per wave and load)
+  const int64_t lane_off = (int64_t)(wv * 4 * 64 + lane) * 8;
   constexpr int SEGS = NT * 32 * 8;          // 16-byte segments per chunk per array
   constexpr int SPT = SEGS / 256;            // per thread
   // every thread stages whole segments unconditionally: a guarded, partly
@@ -267,8 +269,8 @@ __global__ __launch_bounds__(256, 2) void kl_gemm_f16x3(GemmView gv, BatchOperan
     const uint16_t* bl_ = abl + (int64_t)c * cstride;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      dh[q] = *reinterpret_cast<const u32x4*>(bh_ + (a_lane + q * 8));
-      dl[q] = *reinterpret_cast<const u32x4*>(bl_ + (a_lane + q * 8));
+      dh[q] = *reinterpret_cast<const u32x4*>(bh_ + (a_lane + q * 512));
+      dl[q] = *reinterpret_cast<const u32x4*>(bl_ + (a_lane + q * 512));
     }
   };
   auto load_b = [&](int c, u32x4 (&dh)[SPT], u32x4 (&dl)[SPT]) {
@@ -358,7 +360,8 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
   const int nchunks = (int)(gv.lda / KC);
   const int64_t tile0 = (int64_t)rb * (GROWS * KC);
   const int64_t cstride = gemm_row_tiles(gv.N) * (GROWS * KC);
-  const float* ap = gv.l32 + tile0 + (int64_t)(wv * 32 + r) * KC + h * 32;
+  // load q of this lane: row r, columns h*32 + q*4 .. + 4 of the tile
+  const float* ap = gv.l32 + tile0 + (int64_t)(wv * 8 * 64 + lane) * 4;
   const float* bp = o.b32 + (int64_t)tbase * gv.lda;
   constexpr int SEGS = NT * 32 * 16;          // 16-byte segments per chunk
   constexpr int SPT = SEGS / 256;
@@ -367,7 +370,7 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
   // A fragments are staged as in kl_gemm_f16x3: loaded into na, copied into a.
   f32x4 a[8], na[8], bq[SPT];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) na[q] = *reinterpret_cast<const f32x4*>(ap + q * 4);
+  for (int q = 0; q < 8; ++q) na[q] = *reinterpret_cast<const f32x4*>(ap + q * 256);
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
     const int sg = threadIdx.x + q * 256;
@@ -397,7 +400,7 @@ __global__ __launch_bounds__(256) void kl_gemm_f32(GemmView gv, BatchOperand o, 
       const int64_t ko = (int64_t)(c + 1) * KC;
       const int64_t ao = (int64_t)(c + 1) * cstride;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) na[q] = *reinterpret_cast<const f32x4*>(ap + ao + q * 4);
+      for (int q = 0; q < 8; ++q) na[q] = *reinterpret_cast<const f32x4*>(ap + ao + q * 256);
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
         const int sg = threadIdx.x + q * 256;

@@ -316,48 +316,47 @@ __global__ __launch_bounds__(512) void csr_field_kernel(CsrView v, int32_t targe
     const ushort4* col4 = reinterpret_cast<const ushort4*>(v.col + s);
     const int nv = (n + 3) >> 2;
     double acc = 0.0, A = 0.0, E = 0.0;
+    // Loads are unconditional (index clamped into the row) and entries past
+    // the row's end are masked arithmetically, so the loop has no divergent
+    // branch that would make the loads wait.  Padding slots hold column 0.
     for (int base = lane; base < nv; base += LPR * UNROLL) {
       float4 q[UNROLL];
       ushort4 cb[UNROLL];
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
-        const int i = base + u * LPR;
-        if (i < nv) {
-          if (F16) {
-            const ushort4 hq = h4[i];
-            q[u] = make_float4(f16_value(hq.x, rs), f16_value(hq.y, rs), f16_value(hq.z, rs),
-                               f16_value(hq.w, rs));
-          } else {
-            q[u] = ld_stream(val4 + i);
-          }
-          cb[u] = col4[i];
+        const int i = min(base + u * LPR, nv - 1);
+        if (F16) {
+          const ushort4 hq = h4[i];
+          q[u] = make_float4(f16_value(hq.x, rs), f16_value(hq.y, rs), f16_value(hq.z, rs),
+                             f16_value(hq.w, rs));
+        } else {
+          q[u] = ld_stream(val4 + i);
         }
+        cb[u] = col4[i];
       }
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
         const int i = base + u * LPR;
-        if (i < nv) {
-          const int rem = n - 4 * i;
-          const float qv[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
-          const int bv[4] = {cb[u].x, cb[u].y, cb[u].z, cb[u].w};
-          float ts4 = 0.f, as4 = 0.f, es4 = 0.f;
+        const int rem = i < nv ? n - 4 * i : 0;
+        const float qv[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+        const int bv[4] = {cb[u].x, cb[u].y, cb[u].z, cb[u].w};
+        float ts4 = 0.f, as4 = 0.f, es4 = 0.f;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            if (e < rem) {
-              const float2 pl = spl[bv[e]];
-              as4 += pl.x;
-              if (KIND == 0) {
-                ts4 += fabsf(qv[e] - pl.x);
-              } else {
-                ts4 += pl.x * (pl.y - hw_log2(qv[e]));
-                es4 += pl.x * pl.y;
-              }
-            }
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = e < rem;
+          const float2 pl = spl[bv[e]];
+          const float p = ok ? pl.x : 0.f;
+          as4 += p;
+          if (KIND == 0) {
+            ts4 += fabsf((ok ? qv[e] : 0.f) - p);
+          } else {
+            ts4 += p * (pl.y - hw_log2(ok ? qv[e] : 1.f));
+            es4 += p * pl.y;
           }
-          acc += (double)ts4;
-          A += (double)as4;
-          if (KIND == 1) E += (double)es4;
         }
+        acc += (double)ts4;
+        A += (double)as4;
+        if (KIND == 1) E += (double)es4;
       }
     }
 #pragma unroll
