@@ -52,7 +52,7 @@ struct DevBuf {
   size_t bytes = 0;
   ~DevBuf() { release(); }
   void release() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);   // a destructor has no caller to report to
     p = nullptr;
     bytes = 0;
   }
@@ -75,7 +75,7 @@ struct AsyncBuf {
   hipStream_t s = nullptr;
   explicit AsyncBuf(hipStream_t st) : s(st) {}
   ~AsyncBuf() {
-    if (p) hipFreeAsync(p, s);
+    if (p) (void)hipFreeAsync(p, s);   // stream-ordered after the launches that use it
   }
   hipError_t alloc(size_t n) { return hipMallocAsync(&p, n ? n : 1, s); }
   template <typename T>
@@ -1232,11 +1232,14 @@ dd_status dd_plan_path(dd_kernel* k, int32_t source, int32_t target, int32_t kin
 
 dd_status dd_free_kernel(dd_kernel* k) {
   if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
-  hipSetDevice(k->ctx->device);
-  hipDeviceSynchronize();
+  // work in flight may still read the handle's memory: wait for it, then free
+  hipError_t e = hipSetDevice(k->ctx->device);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
   k->ctx->live_kernels--;
   k->magic = kDead;
   delete k;
+  if (e != hipSuccess)
+    return fail(DD_EDEVICE, "freed after a device error: %s", hipGetErrorString(e));
   return DD_OK;
 }
 
