@@ -24,6 +24,8 @@
 // (sqrt q - sqrt p)^2 but has no cancellation: every term carries a small
 // relative error, so the field has a relative error bound, also next to the
 // target.  sqrt p sits in LDS beside p.
+#include <algorithm>
+
 #include "dd_internal.h"
 
 namespace dd {
@@ -398,24 +400,30 @@ static hipError_t allow_lds(K kern, size_t bytes) {
 // those launches use 512-thread workgroups: twice the waves share one copy.
 static int block_threads(size_t lds) { return lds > 32 * 1024 ? 512 : 256; }
 
-static int grid_for(int64_t groups_needed, int gpb, size_t lds) {
+// Persistent grid: as many workgroups as the LDS allows, keeping four wave
+// slots of each CU (of 32) free for concurrent work on other streams, such
+// as a path walk beside a field: a workgroup that cannot start until another
+// finishes would end the pass late.
+static int grid_for(int64_t groups_needed, int gpb, int threads, size_t lds) {
   const int64_t need = (groups_needed + gpb - 1) / gpb;
   int per_cu = lds > 0 ? (int)((160 * 1024) / (lds + 1024)) : 8;
-  if (per_cu < 1) per_cu = 1;
-  if (per_cu > 8) per_cu = 8;
+  per_cu = std::min(per_cu, (32 - 4) / (threads / 64));
+  per_cu = std::max(1, std::min(per_cu, 8));
   const int64_t cap = (int64_t)num_cus() * per_cu;
   return (int)(need < cap ? (need > 0 ? need : 1) : cap);
 }
 
 template <int LPR, int KIND>
 static hipError_t dense_launch(DenseView v, int32_t target, int param, float* out, hipStream_t s) {
-  constexpr int UNROLL = (LPR == 64) ? 4 : (LPR == 32 ? 4 : 4);
+  // TV and KL: six 16-byte loads per lane in flight (a 257^2 row in one round
+  // trip); the other kinds carry more per-entry state
+  constexpr int UNROLL = KIND <= 1 ? 6 : 4;
   auto kern = dense_field_kernel<LPR, KIND, UNROLL>;
   const size_t lds = (size_t)v.ld * sizeof(float) * (KIND != 0 ? 2 : 1);
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int threads = block_threads(lds);
-  const int grid = grid_for(v.N, threads / LPR, lds);
+  const int grid = grid_for(v.N, threads / LPR, threads, lds);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v.P, v.ld, v.N, target, param, out);
   return hipGetLastError();
 }
@@ -451,7 +459,7 @@ static hipError_t support_launch(DenseView v, int32_t target, double tau, int ta
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int threads = block_threads(lds);
-  const int grid = grid_for(v.N, threads / LPR, lds);
+  const int grid = grid_for(v.N, threads / LPR, threads, lds);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v.P, v.P64, v.ld, v.B, v.N, target,
                      tau, tau_relative, out);
   return hipGetLastError();
@@ -472,7 +480,7 @@ static hipError_t csr_launch(CsrView v, int32_t target, float* out, hipStream_t 
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int threads = block_threads(lds);
-  const int grid = grid_for(v.N, threads / LPR, lds);
+  const int grid = grid_for(v.N, threads / LPR, threads, lds);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v, target, out);
   return hipGetLastError();
 }
