@@ -121,7 +121,7 @@ def run_grid1025(args):
     from workloads import build_config
     from workloads.seeds import targets_sources
 
-    g = build_config("c3")
+    g = build_config("grid1025")
     log(f"grid1025: N={g.N} K={g.K}; building the kernel matrix")
     t0 = time.perf_counter()
     last = [0.0]
@@ -379,7 +379,7 @@ def run_serving(args):
     from workloads import CONFIGS, grid_domain
     from workloads.serving import poisson_arrivals
 
-    c = CONFIGS["c4"]
+    c = CONFIGS["serving4"]
     sizes = [int(x) for x in args.serving_grids.split(",")]
     ctx = Context(0)
     srv = Server(ctx, max_batch=c["max_batch"], slots_per_domain=args.slots,
@@ -388,7 +388,7 @@ def run_serving(args):
     for (G, k, sides) in c["domains"]:
         if G not in sizes:
             continue
-        g = grid_domain(G, k, sides, config_id=c["config_id"] + G)
+        g = grid_domain(G, k, sides, seed_id=c["seed_id"] + G)
         log(f"serving: building {G}x{G} ({g.N} x {g.K})")
         t0 = time.perf_counter()
         last = [0.0]
@@ -409,7 +409,7 @@ def run_serving(args):
     srv.drain()
     srv.completed.clear()
     srv.batch_sizes.clear()
-    arr = poisson_arrivals(c["config_id"], [(nm, n) for nm, n, _ in doms], args.qps, args.duration)
+    arr = poisson_arrivals(c["seed_id"], [(nm, n) for nm, n, _ in doms], args.qps, args.duration)
     log(f"serving: {len(arr)} arrivals over {args.duration:.0f} s at {args.qps:.0f} QPS")
     t0 = time.perf_counter()
     qs = srv.run_open_loop(arr, timeout=args.duration * 10 + 60)
@@ -444,7 +444,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by rows, see DESIGN.md)", file=sys.stderr)
+              "(the path shards by rows)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "grid1025":
         run_grid1025(args)
@@ -460,7 +460,7 @@ def main():
     from workloads.seeds import targets_sources
 
     tau = 1e-6
-    g = build_config("c2")
+    g = build_config("grid257")
     P = kernel_matrix(g, args)
     t_arr, s_arr = targets_sources(1, g.N, max(1, args.batch))
     t, s = int(t_arr[0]), int(s_arr[0])

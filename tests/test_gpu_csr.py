@@ -23,7 +23,7 @@ def oracle_trunc(P32, tau, relative, t, kind):
 
 @pytest.fixture(scope="module")
 def grid(gpu_ctx):
-    g = grid_domain(81, 3, (0.1, 0.25), config_id=41)
+    g = grid_domain(81, 3, (0.1, 0.25), seed_id=41)
     return g, g.poisson_kernel().astype(np.float32)
 
 
@@ -101,7 +101,7 @@ def test_truncated_paths_identical(gpu_ctx, grid, kind):
 @pytest.mark.parametrize("kind", ["tv", "kl"])
 def test_grid257_truncated_full_size(gpu_ctx, kind):
     from paper_1708_02845_amd import Kernel
-    g = build_config("c2")
+    g = build_config("grid257")
     P = g.poisson_kernel(dtype=np.float32)
     k = Kernel.load_dense(gpu_ctx, P, tau=1e-6)
     try:

@@ -30,7 +30,7 @@ def oracle_trunc(P32, tau, relative, t, kind):
 
 @pytest.fixture(scope="module")
 def grid(gpu_ctx):
-    g = grid_domain(81, 3, (0.1, 0.25), config_id=41)
+    g = grid_domain(81, 3, (0.1, 0.25), seed_id=41)
     return g, g.poisson_kernel().astype(np.float32)
 
 
@@ -137,7 +137,7 @@ def test_grid257_batch_full_size(gpu_ctx, kind):
     """The 257^2 domain truncated at 1e-6 relative, 64 targets in one pass;
     the oracle on two of them."""
     from paper_1708_02845_amd import Kernel
-    g = build_config("c2")
+    g = build_config("grid257")
     P = g.poisson_kernel(dtype=np.float32)
     k = Kernel.load_dense(gpu_ctx, P, tau=1e-6)
     try:

@@ -29,7 +29,7 @@ def oracle_trunc(P32, tau, relative, t, kind):
 
 @pytest.fixture(scope="module")
 def grid(gpu_ctx):
-    g = grid_domain(81, 3, (0.1, 0.25), config_id=41)
+    g = grid_domain(81, 3, (0.1, 0.25), seed_id=41)
     return g, g.poisson_kernel().astype(np.float32)
 
 

@@ -74,7 +74,7 @@ def test_ragged_row_counts(gpu_ctx, N):
 @pytest.fixture(scope="module")
 def disk_kernel(gpu_ctx):
     from paper_1708_02845_amd import Kernel
-    inst = build_config("c1")
+    inst = build_config("disk4096")
     k = Kernel.load_dense(gpu_ctx, inst.P, adjacency=(inst.adj_ptr, inst.adj_idx))
     yield inst, k
     k.free()
@@ -96,7 +96,7 @@ def test_unit_disk_fp64_input(disk_kernel, kind):
 @pytest.fixture(scope="module")
 def grid65(gpu_ctx):
     from paper_1708_02845_amd import Kernel
-    g = grid_domain(65, 2, (0.1, 0.3), config_id=21)
+    g = grid_domain(65, 2, (0.1, 0.3), seed_id=21)
     P = g.poisson_kernel().astype(np.float32)
     k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
     yield g, P, k
@@ -176,7 +176,7 @@ def test_invalid_inputs_are_rejected(gpu_ctx, grid65):
 def grid257(gpu_ctx):
     """The 257x257, 3-obstacle workload at its full size (FP32 dense)."""
     from paper_1708_02845_amd import Kernel
-    g = build_config("c2")
+    g = build_config("grid257")
     P = g.poisson_kernel(dtype=np.float32)
     k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
     yield g, P, k

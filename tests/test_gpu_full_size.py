@@ -22,7 +22,7 @@ T = 64
 
 @pytest.fixture(scope="module")
 def full():
-    g = build_config("c3")
+    g = build_config("grid1025")
     P = g.poisson_kernel(dtype=np.float32)
     ts = targets_sources(2, g.N, T)[0]
     sample = np.sort(rng(2, "sample").choice(g.N, size=g.N // 1000, replace=False))

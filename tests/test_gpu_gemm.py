@@ -17,7 +17,7 @@ FORMS = ["f32", "f16x3"]
 
 @pytest.fixture(scope="module")
 def grid(gpu_ctx):
-    g = grid_domain(71, 2, (0.1, 0.3), config_id=51)     # N, B not multiples of 128 / 64
+    g = grid_domain(71, 2, (0.1, 0.3), seed_id=51)     # N, B not multiples of 128 / 64
     return g, g.poisson_kernel().astype(np.float32)
 
 
@@ -83,7 +83,7 @@ def test_paths_on_contraction_fields(grid, gemm_kernel):
 @pytest.mark.parametrize("form", FORMS)
 def test_unit_disk_fp64_input(gpu_ctx, form):
     from paper_1708_02845_amd import Kernel
-    inst = build_config("c1")
+    inst = build_config("disk4096")
     k = Kernel.load_dense(gpu_ctx, inst.P, gemm_form=form)
     try:
         ts = targets_sources(0, inst.N, 16)[0]
@@ -112,7 +112,7 @@ def test_zero_entry_cannot_build_operand(gpu_ctx):
 @pytest.mark.parametrize("form", FORMS)
 def test_grid257_batch_of_256(gpu_ctx, form):
     from paper_1708_02845_amd import Kernel
-    g = build_config("c2")
+    g = build_config("grid257")
     P = g.poisson_kernel(dtype=np.float32)
     k = Kernel.load_dense(gpu_ctx, P, gemm_form=form)
     try:

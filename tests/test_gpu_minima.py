@@ -22,7 +22,7 @@ def check_against_oracle(cls, ref_field, adj_ptr, adj_idx, t):
 @pytest.mark.parametrize("kind", ["kl", "tv"])
 def test_disk_fields_have_no_minima(gpu_ctx, kind):
     from paper_1708_02845_amd import Kernel
-    inst = build_config("c1")
+    inst = build_config("disk4096")
     k = Kernel.load_dense(gpu_ctx, inst.P, adjacency=(inst.adj_ptr, inst.adj_idx))
     try:
         ts = targets_sources(0, inst.N, 3)[0]
@@ -40,7 +40,7 @@ def test_disk_fields_have_no_minima(gpu_ctx, kind):
 @pytest.mark.parametrize("kind", ["kl", "tv"])
 def test_truncated_grid_fields(gpu_ctx, kind):
     from paper_1708_02845_amd import Kernel
-    g = grid_domain(97, 3, (0.1, 0.25), config_id=71)
+    g = grid_domain(97, 3, (0.1, 0.25), seed_id=71)
     P = g.poisson_kernel().astype(np.float32)
     tau = 1e-3
     k = Kernel.load_dense(gpu_ctx, P, tau=tau, adjacency=(g.adj_ptr, g.adj_idx))
@@ -61,7 +61,7 @@ def test_truncated_grid_fields(gpu_ctx, kind):
 def test_planted_minima_exact(gpu_ctx):
     import torch
     from paper_1708_02845_amd import Kernel
-    g = grid_domain(41, 1, (0.1, 0.2), config_id=72)
+    g = grid_domain(41, 1, (0.1, 0.2), seed_id=72)
     P = g.poisson_kernel().astype(np.float32)
     k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
     try:

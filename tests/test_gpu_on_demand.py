@@ -33,7 +33,7 @@ def run_on_demand(k, ss, ts, kind, max_steps, **kw):
 @pytest.fixture(scope="module")
 def disk(gpu_ctx):
     from paper_1708_02845_amd import Kernel
-    inst = build_config("c1")
+    inst = build_config("disk4096")
     k = Kernel.load_dense(gpu_ctx, inst.P, adjacency=(inst.adj_ptr, inst.adj_idx))
     yield inst, k
     k.free()
@@ -42,7 +42,7 @@ def disk(gpu_ctx):
 @pytest.fixture(scope="module")
 def grid(gpu_ctx):
     from paper_1708_02845_amd import Kernel
-    g = grid_domain(97, 3, (0.1, 0.25), config_id=31)
+    g = grid_domain(97, 3, (0.1, 0.25), seed_id=31)
     P = g.poisson_kernel().astype(np.float32)
     k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
     yield g, P, k
@@ -170,7 +170,7 @@ def test_support_kl_fp64_input(disk):
 
 def test_support_kl_full_size_257(gpu_ctx):
     from paper_1708_02845_amd import Kernel
-    g = build_config("c2")
+    g = build_config("grid257")
     P = g.poisson_kernel(dtype=np.float32)
     k = Kernel.load_dense(gpu_ctx, P)
     try:

@@ -23,7 +23,7 @@ def oracle_path(P, adj_ptr, adj_idx, s, t, kind, max_steps):
 @pytest.fixture(scope="module")
 def disk(gpu_ctx):
     from paper_1708_02845_amd import Kernel
-    inst = build_config("c1")
+    inst = build_config("disk4096")
     k = Kernel.load_dense(gpu_ctx, inst.P, adjacency=(inst.adj_ptr, inst.adj_idx))
     yield inst, k
     k.free()
@@ -43,7 +43,7 @@ def test_disk_paths_identical(disk, kind):
 @pytest.fixture(scope="module")
 def grid(gpu_ctx):
     from paper_1708_02845_amd import Kernel
-    g = grid_domain(97, 3, (0.1, 0.25), config_id=31)
+    g = grid_domain(97, 3, (0.1, 0.25), seed_id=31)
     P = g.poisson_kernel().astype(np.float32)
     k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
     yield g, P, k
@@ -117,7 +117,7 @@ def test_path_without_adjacency_is_rejected(gpu_ctx):
 
 def test_grid257_paths(gpu_ctx):
     from paper_1708_02845_amd import Kernel
-    g = build_config("c2")
+    g = build_config("grid257")
     P = g.poisson_kernel(dtype=np.float32)
     k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
     try:

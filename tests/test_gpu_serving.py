@@ -13,9 +13,9 @@ pytestmark = pytest.mark.gpu
 def domains():
     out = {}
     for name, (G, k, cid) in {"g49": (49, 2, 61), "g65": (65, 3, 62), "g81": (81, 4, 63)}.items():
-        g = grid_domain(G, k, (0.1, 0.25), config_id=cid)
+        g = grid_domain(G, k, (0.1, 0.25), seed_id=cid)
         out[name] = (g.poisson_kernel().astype(np.float32), (g.adj_ptr, g.adj_idx))
-    disk = build_config("c1", N=1500, B=128)
+    disk = build_config("disk4096", N=1500, B=128)
     out["disk"] = (disk.P, (disk.adj_ptr, disk.adj_idx))
     return out
 

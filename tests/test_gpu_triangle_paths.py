@@ -39,7 +39,7 @@ def check_same(got, ref):
 @pytest.fixture(scope="module")
 def grid(gpu_ctx):
     from paper_1708_02845_amd import Kernel
-    g = grid_domain(97, 3, (0.1, 0.25), config_id=31)
+    g = grid_domain(97, 3, (0.1, 0.25), seed_id=31)
     P = g.poisson_kernel().astype(np.float32)
     k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
     faces, xy = g.interior_mesh()
@@ -65,7 +65,7 @@ def test_grid_triangle_paths_match_oracle(grid, kind):
 
 def test_disk_triangle_paths_match_oracle(gpu_ctx):
     from paper_1708_02845_amd import Kernel
-    inst = build_config("c1")
+    inst = build_config("disk4096")
     k = Kernel.load_dense(gpu_ctx, inst.P, adjacency=(inst.adj_ptr, inst.adj_idx))
     try:
         faces, xy = inst.interior_mesh()

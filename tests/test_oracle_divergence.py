@@ -14,12 +14,12 @@ from workloads.seeds import rng
 
 @pytest.fixture(scope="module")
 def c1():
-    return build_config("c1")
+    return build_config("disk4096")
 
 
 @pytest.fixture(scope="module")
 def grid_P():
-    g = grid_domain(49, 2, (0.1, 0.3), config_id=11)
+    g = grid_domain(49, 2, (0.1, 0.3), seed_id=11)
     P = g.poisson_kernel()
     keep = P.max(axis=0) > 0
     return P[:, keep]

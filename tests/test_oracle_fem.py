@@ -26,7 +26,7 @@ def disk_mesh(n_interior=300, n_boundary=64, seed=0):
 
 @pytest.fixture(scope="module")
 def small_grid():
-    return grid_domain(33, 2, (0.1, 0.3), config_id=7)
+    return grid_domain(33, 2, (0.1, 0.3), seed_id=7)
 
 
 def test_cotan_weights_on_right_triangle_grid_are_five_point(small_grid):

@@ -28,7 +28,7 @@ def grid_graph(rows, cols):
 
 @pytest.fixture(scope="module")
 def c1():
-    return build_config("c1")
+    return build_config("disk4096")
 
 
 def test_hand_traced_paths_on_small_grid():

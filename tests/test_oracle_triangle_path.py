@@ -38,7 +38,7 @@ def test_hand_traced_square():
 
 @pytest.fixture(scope="module")
 def open_grid():
-    return grid_domain(41, 0, config_id=61)
+    return grid_domain(41, 0, seed_id=61)
 
 
 def test_linear_field_gives_a_straight_ray(open_grid):
@@ -89,7 +89,7 @@ def test_values_decrease_along_the_path(open_grid):
 def test_disk_triangle_paths_follow_geodesics_better_than_edge_paths(kind):
     # Appendix 2.2: descent paths on the disk are hyperbolic geodesics; Fig. 2:
     # triangle-based paths are smoother than edge-based ones
-    inst = build_config("c1")
+    inst = build_config("disk4096")
     mesh = tp.Mesh(*inst.interior_mesh())
     ts, ss = targets_sources(0, inst.N, 4)
     gap_tri, gap_edge = [], []

@@ -8,11 +8,11 @@ from workloads.serving import poisson_arrivals
 
 
 def test_generators_are_seeded():
-    a = build_config("c1")
-    b = build_config("c1")
+    a = build_config("disk4096")
+    b = build_config("disk4096")
     assert np.array_equal(a.P, b.P) and np.array_equal(a.adj_idx, b.adj_idx)
-    g1 = grid_domain(65, 2, config_id=9)
-    g2 = grid_domain(65, 2, config_id=9)
+    g1 = grid_domain(65, 2, seed_id=9)
+    g2 = grid_domain(65, 2, seed_id=9)
     assert g1.rects == g2.rects and np.array_equal(g1.interior, g2.interior)
     t1, s1 = targets_sources(4, 1000, 50)
     t2, s2 = targets_sources(4, 1000, 50)
@@ -20,7 +20,7 @@ def test_generators_are_seeded():
 
 
 def test_grid_geometry_invariants():
-    g = grid_domain(97, 3, (0.1, 0.25), config_id=5)
+    g = grid_domain(97, 3, (0.1, 0.25), seed_id=5)
     G = g.G
     assert g.N + g.K + sum((r[2] - r[0] - 1) * (r[3] - r[1] - 1) for r in g.rects) == G * G
     deg = np.diff(g.adj_ptr)
@@ -34,7 +34,7 @@ def test_grid_geometry_invariants():
 
 
 def test_c2_sizes():
-    g = build_config("c2")
+    g = build_config("grid257")
     assert (g.N, g.K) == (60695, 1482)
 
 

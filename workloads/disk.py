@@ -48,8 +48,8 @@ def edges_to_csr(n, edges):
     return ptr, e[:, 1].astype(np.int32)
 
 
-def disk_instance(N=4096, B=256, r_max=0.95, config_id=0) -> DiskInstance:
-    g = rng(config_id, "geometry")
+def disk_instance(N=4096, B=256, r_max=0.95, seed_id=0) -> DiskInstance:
+    g = rng(seed_id, "geometry")
     u = g.random(N)
     v = g.random(N)
     z = r_max * np.sqrt(u) * np.exp(2j * np.pi * v)

@@ -38,7 +38,7 @@ class GridDomain:
     triangles: np.ndarray         # int64 [F, 3] global ids, counter-clockwise
     adj_ptr: np.ndarray           # int64 [N+1] interior-only triangulation edges
     adj_idx: np.ndarray           # int32
-    config_id: int = 0
+    seed_id: int = 0
     _P: np.ndarray = field(default=None, repr=False)
 
     @property
@@ -72,8 +72,8 @@ class GridDomain:
         return self._P
 
 
-def _sample_rects(G, n_obstacles, side_range, config_id, gap):
-    g = rng(config_id, "geometry")
+def _sample_rects(G, n_obstacles, side_range, seed_id, gap):
+    g = rng(seed_id, "geometry")
     h = 1.0 / (G - 1)
     rects = []
     tries = 0
@@ -102,8 +102,8 @@ def _sample_rects(G, n_obstacles, side_range, config_id, gap):
     return rects
 
 
-def grid_domain(G, n_obstacles, side_range=(0.05, 0.2), config_id=0, gap=2) -> GridDomain:
-    rects = _sample_rects(G, n_obstacles, side_range, config_id, gap)
+def grid_domain(G, n_obstacles, side_range=(0.05, 0.2), seed_id=0, gap=2) -> GridDomain:
+    rects = _sample_rects(G, n_obstacles, side_range, seed_id, gap)
     I, J = np.meshgrid(np.arange(G), np.arange(G), indexing="xy")  # I[j,i] = i
     removed = np.zeros((G, G), dtype=bool)       # indexed [j, i]
     bnd = np.zeros((G, G), dtype=bool)
@@ -142,7 +142,7 @@ def grid_domain(G, n_obstacles, side_range=(0.05, 0.2), config_id=0, gap=2) -> G
     ptr, idx = edges_to_csr(len(interior), np.concatenate(edges))
 
     dom = GridDomain(G=G, rects=rects, interior=interior, boundary=boundary,
-                     triangles=triangles, adj_ptr=ptr, adj_idx=idx, config_id=config_id)
+                     triangles=triangles, adj_ptr=ptr, adj_idx=idx, seed_id=seed_id)
     _check_connected(dom)
     return dom
 

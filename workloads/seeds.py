@@ -1,4 +1,4 @@
-"""Seed streams: every random draw comes from SeedSequence([config_id, stream])."""
+"""Seed streams: every random draw comes from SeedSequence([seed_id, stream])."""
 
 import numpy as np
 
@@ -12,16 +12,16 @@ SEED_STREAMS = {
 }
 
 
-def rng(config_id: int, stream) -> np.random.Generator:
+def rng(seed_id: int, stream) -> np.random.Generator:
     """Independent generator for (config, stream); ``stream`` is a name or int."""
     sid = SEED_STREAMS[stream] if isinstance(stream, str) else int(stream)
-    return np.random.default_rng(np.random.SeedSequence([int(config_id), sid]))
+    return np.random.default_rng(np.random.SeedSequence([int(seed_id), sid]))
 
 
-def targets_sources(config_id: int, n: int, count: int):
+def targets_sources(seed_id: int, n: int, count: int):
     """``count`` seeded (target, source) interior-vertex pairs with source != target."""
-    t = rng(config_id, "targets").integers(0, n, size=count)
-    rs = rng(config_id, "sources")
+    t = rng(seed_id, "targets").integers(0, n, size=count)
+    rs = rng(seed_id, "sources")
     s = rs.integers(0, n, size=count)
     for i in range(count):
         while s[i] == t[i]:

@@ -3,12 +3,12 @@
 from .seeds import rng
 
 
-def poisson_arrivals(config_id, domains, qps, duration):
+def poisson_arrivals(seed_id, domains, qps, duration):
     """Seeded open-loop arrivals: exponential gaps at ``qps``, uniform domain, s != t.
 
     ``domains``: list of (name, N).
     """
-    ga, gd, gs = rng(config_id, "arrivals"), rng(config_id, "domain"), rng(config_id, "sources")
+    ga, gd, gs = rng(seed_id, "arrivals"), rng(seed_id, "domain"), rng(seed_id, "sources")
     out = []
     t = 0.0
     while True:
