@@ -8,9 +8,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <string>
 #include <unordered_map>
+#include <limits>
 #include <vector>
 
 #include "dd_internal.h"
@@ -109,6 +111,7 @@ struct dd_kernel {
   std::vector<double> W_host;   // row sums
   // batched-KL operand
   DevBuf L32, Lhi, Llo, Off;
+  double omax = 0.0;   // max_x o_x (FP32 offsets as used)
   // truncated
   DevBuf start, len, col, val, val64, phi, lphi;
   DevBuf val16, rsc;   // FP16 form of the stored values and 2^-e_x per row
@@ -312,8 +315,10 @@ dd_error_bound field_bound(const dd_kernel* k, int kind, int32_t t) {
   return b;
 }
 
-// Bound of a batched-KL field from the contraction.  With
-// Lambda(x) = sum_b p_tb |l_xb| <= d(x) + |H_t| + |o_x| W_t and |o_x| <= log B:
+// Bound of a batched-KL field from the contraction.  Every l_xb = log P_xb - o_x
+// is <= 0, so Lambda(x) = sum_b p_tb |l_xb| = -sum_b p_tb l_xb
+// = d(x) - H_t + o_x W_t <= d(x) + |H_t| + max(0, max_x o_x) W_t (H_t <= 0, and
+// o_x <= 0 whenever the row max is at most 1):
 //   F32:   operand rounding u*Lambda, 64-term FP32 partial sums 33u*Lambda;
 //   F16X3: hi+lo splits of l and q (2^-22 relative each), the dropped lo*lo
 //          product (2^-22), 64-term partial sums over 12 accumulations
@@ -321,11 +326,10 @@ dd_error_bound field_bound(const dd_kernel* k, int kind, int32_t t) {
 dd_error_bound gemm_bound(const dd_kernel* k, int32_t t) {
   const double H = std::fabs(k->H_host[t]);
   const double W = k->W_host[t];
-  const double logB = std::log((double)k->B);
   const double c = k->gemm_form == DD_FORM_F32 ? 35.0 : 42.0;
   dd_error_bound b;
   b.rel = (c + 1.0) * kU;
-  b.abs = c * kU * (H + logB * W) + (k->is_f64 ? kU * (W + 2.0 * H) : 0.0);
+  b.abs = c * kU * (H + std::max(0.0, k->omax) * W) + (k->is_f64 ? kU * (W + 2.0 * H) : 0.0);
   if (k->gemm_form == DD_FORM_F16X3) b.abs += std::ldexp(1.0, -39) * (double)k->B * 88.0;
   b.abs *= 2.0;
   b.rel *= 2.0;
@@ -682,6 +686,13 @@ dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P,
                          "%d rows hold a zero entry in a non-zero column: log P is not finite "
                          "there, so the batched-KL operand cannot be built",
                          nzero));
+      // the largest row offset o_x (<= 0 for rows whose max is at most 1),
+      // used by the error bound of the contraction
+      std::vector<float> off(N);
+      if (hipMemcpy(off.data(), k->Off.p, 4 * (size_t)N, hipMemcpyDeviceToHost))
+        return bail(fail(DD_EDEVICE, "copy of the row offsets failed"));
+      k->omax = -std::numeric_limits<double>::infinity();
+      for (int32_t x = 0; x < N; ++x) k->omax = std::max(k->omax, (double)off[x]);
       k->gemm_form = o.gemm_form;
     }
   }

@@ -205,7 +205,7 @@ __device__ __forceinline__ double term64(double pb, double lpb, double q, int pa
   return e * e;
 }
 
-// FP64 distance of dense row x, one wave.  The row's entries are loaded kQ
+// FP64 sum of the terms of dense row x over columns [lo, hi), one wave.  The row's entries are loaded kQ
 // per lane at a time (indices clamped into the row, clamped slots not
 // summed): one memory round trip per 64 * kQ entries.  The target row p and
 // its logs lp are read from LDS when the block staged them there.  One
@@ -213,36 +213,38 @@ __device__ __forceinline__ double term64(double pb, double lpb, double q, int pa
 // one instance a path uses stay in the instruction cache.
 constexpr int kU = 8;
 constexpr int kQ = 24;
+// Walks on dense rows of at least kSplitB columns split each FP64 re-decision
+// row over kMaxParts waves of a kPathThreads block (below that a row is cheap,
+// and the extra waves of the walk cost more than they save).
+constexpr int kPathThreads = 512;
+constexpr int kMaxParts = 4;
+constexpr int kSplitB = 4096;
+__host__ __device__ inline bool split_rows(int is_csr, int B) { return !is_csr && B >= kSplitB; }
 
 template <int F>
 __device__ __noinline__ double exact_dense(const DenseView& dv, const double* p, const double* lp,
-                                           int x, int param) {
+                                           int x, int param, int lo, int hi) {
   const int lane = threadIdx.x & 63;
   double acc = 0.0;
   const bool f64 = dv.P64 != nullptr;
   const double* q64 = dv.P64 + (int64_t)x * dv.B;
   const float* q32 = dv.P + (int64_t)x * dv.ld;
-  for (int b0 = lane; b0 < dv.B; b0 += 64 * kQ) {
+  for (int b0 = lo + lane; b0 < hi; b0 += 64 * kQ) {
     double q[kQ];
     if (f64) {
 #pragma unroll
-      for (int u = 0; u < kQ; ++u) q[u] = q64[b0 + 64 * u < dv.B ? b0 + 64 * u : 0];
+      for (int u = 0; u < kQ; ++u) q[u] = q64[b0 + 64 * u < hi ? b0 + 64 * u : lo];
     } else {
 #pragma unroll
-      for (int u = 0; u < kQ; ++u) q[u] = (double)q32[b0 + 64 * u < dv.B ? b0 + 64 * u : 0];
+      for (int u = 0; u < kQ; ++u) q[u] = (double)q32[b0 + 64 * u < hi ? b0 + 64 * u : lo];
     }
 #pragma unroll
     for (int u = 0; u < kQ; ++u) {
       const int b = b0 + 64 * u;
-      if (b < dv.B) acc += term64<F>(p[b], F == 1 ? lp[b] : 0.0, q[u], param);
+      if (b < hi) acc += term64<F>(p[b], F == 1 ? lp[b] : 0.0, q[u], param);
     }
   }
-  acc = wsum(acc);
-  if (F == 5) {
-    const double al = (double)(param - 8) / 8.0;
-    acc *= 4.0 / (1.0 - al * al);
-  }
-  return acc;
+  return wsum(acc);
 }
 
 // FP64 distance of truncated row x (TV or KL of the truncated rows), one wave.
@@ -287,22 +289,49 @@ __device__ __noinline__ double exact_csr(const CsrView& cv, const double* p, con
   return acc + (tc[1] - E) - log(cv.phi[x]) * (tc[0] - A);
 }
 
-// FP64 distance of row x to the target, computed by one wave, from the
-// staged FP64 target row p, its logarithms lp and constants tc.  kind is the
-// library's kind value (0..3, 100 + k, 200 + j); truncated handles carry TV
-// and KL only.
+// Columns of part `part` of `parts` of a dense row: whole multiples of 64.
+__device__ __forceinline__ void part_range(int B, int part, int parts, int& lo, int& hi) {
+  const int chunk = (((B + parts - 1) / parts) + 63) & ~63;
+  lo = min(B, part * chunk);
+  hi = min(B, lo + chunk);
+}
+
+// Factor applied to the summed terms (the alpha family's 4/(1 - alpha^2)).
+__device__ __forceinline__ double distance_scale(int kind) {
+  if (kind > 200) {
+    const double al = (double)(kind - 208) / 8.0;
+    return 4.0 / (1.0 - al * al);
+  }
+  return 1.0;
+}
+
+// Part `part` of `parts` of the FP64 distance of row x to the target, computed
+// by one wave from the staged FP64 target row p, its logarithms lp and
+// constants tc: the terms of a column range of a dense row (summed over the
+// parts in order, then times distance_scale), or, on a truncated handle
+// (parts = 1), the whole truncated distance.  kind is the library's kind value
+// (0..3, 100 + k, 200 + j); truncated handles carry TV and KL only.
+__device__ __forceinline__ double exact_part(const DenseView& dv, const CsrView& cv, int is_csr,
+                                             int kind, const double* p, const double* lp,
+                                             const double* tc, int x, int part, int parts) {
+  if (is_csr) return kind == 0 ? exact_csr<0>(cv, p, lp, tc, x) : exact_csr<1>(cv, p, lp, tc, x);
+  int lo, hi;
+  part_range(dv.B, part, parts, lo, hi);
+  if (kind > 200) return exact_dense<5>(dv, p, lp, x, kind - 200, lo, hi);
+  if (kind > 100) return exact_dense<4>(dv, p, lp, x, kind - 100, lo, hi);
+  switch (kind) {
+    case 0: return exact_dense<0>(dv, p, lp, x, 0, lo, hi);
+    case 1: return exact_dense<1>(dv, p, lp, x, 0, lo, hi);
+    case 2: return exact_dense<2>(dv, p, lp, x, 0, lo, hi);
+    default: return exact_dense<3>(dv, p, lp, x, 0, lo, hi);
+  }
+}
+
+// FP64 distance of row x to the target, one wave.
 __device__ __forceinline__ double exact_distance(const DenseView& dv, const CsrView& cv,
                                                  int is_csr, int kind, const double* p,
                                                  const double* lp, const double* tc, int x) {
-  if (is_csr) return kind == 0 ? exact_csr<0>(cv, p, lp, tc, x) : exact_csr<1>(cv, p, lp, tc, x);
-  if (kind > 200) return exact_dense<5>(dv, p, lp, x, kind - 200);
-  if (kind > 100) return exact_dense<4>(dv, p, lp, x, kind - 100);
-  switch (kind) {
-    case 0: return exact_dense<0>(dv, p, lp, x, 0);
-    case 1: return exact_dense<1>(dv, p, lp, x, 0);
-    case 2: return exact_dense<2>(dv, p, lp, x, 0);
-    default: return exact_dense<3>(dv, p, lp, x, 0);
-  }
+  return exact_part(dv, cv, is_csr, kind, p, lp, tc, x, 0, 1) * distance_scale(kind);
 }
 
 __device__ __forceinline__ double uniform(double x) {
@@ -346,10 +375,13 @@ __device__ __forceinline__ float unkey(uint32_t k) {
 // (ties: lowest id) and the set of neighbours that could still be the minimum
 // as one ballot: a few dozen instructions between the loads of consecutive
 // steps.
-__global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, PathArgs a) {
-  // rows of the current and the previous FP64 re-decision (at most W + 1 <= 65)
-  __shared__ int cur_x[65], prev_x[65];
+__global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrView cv,
+                                                           PathArgs a) {
+  // rows of the current and the previous FP64 re-decision (at most W + 1 <= 65),
+  // and the parts of the rows being evaluated
+  __shared__ int cur_x[65], prev_x[65], cur_new[65];
   __shared__ double cur_d[65], prev_d[65];
+  __shared__ double part_d[65 * kMaxParts];
   int prev_n = 0;
   const int i = blockIdx.x;
   const int lane = threadIdx.x & 63;
@@ -361,6 +393,11 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
   const Bound bnd = path_bound(a, i);
   const double ea = uniform(bnd.abs), er = uniform(bnd.rel);
   const int Bt = a.is_csr ? cv.B : dv.B;
+  // a long dense row of a re-decision is split over several waves; the split
+  // depends only on B, so a row's FP64 value does not depend on which other
+  // rows are evaluated with it
+  const int parts = split_rows(a.is_csr, Bt) ? kMaxParts : 1;
+  const double dscale = distance_scale(a.kind);
   const double* p = a.trow + (int64_t)i * Bt;
   const double* lpt = a.tlog + (int64_t)i * Bt;
   if (a.tgt_in_lds) {
@@ -441,7 +478,7 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
       ++rechecks;
       const int nw = (int)(blockDim.x >> 6);
       uint64_t rest = cand | (1ull << L);
-      int pos = 0;
+      int pos = 0, task = 0;
       for (;;) {
         int x = v;
         if (pos > 0) {
@@ -449,21 +486,32 @@ __global__ __launch_bounds__(256) void paths_kernel(DenseView dv, CsrView cv, Pa
           x = __builtin_amdgcn_readlane(ul, (int)__builtin_ctzll(rest));
           rest &= rest - 1;
         }
-        if (pos % nw == wave) {
-          double dx = 0.0;
-          bool have = false;
-          for (int q = 0; q < prev_n && !have; ++q)
-            if (prev_x[q] == x) {
-              dx = prev_d[q];
-              have = true;
-            }
-          if (!have) dx = exact_distance(dv, cv, a.is_csr, a.kind, p, lpt, tc, x);
-          if (lane == 0) {
-            cur_x[pos] = x;
-            cur_d[pos] = dx;
+        double dx = 0.0;
+        bool have = false;
+        for (int q = 0; q < prev_n && !have; ++q)
+          if (prev_x[q] == x) {
+            dx = prev_d[q];
+            have = true;
           }
+        if (threadIdx.x == 0) {
+          cur_x[pos] = x;
+          cur_d[pos] = dx;
+          cur_new[pos] = have ? 0 : 1;
         }
+        if (!have)
+          for (int part = 0; part < parts; ++part, ++task)
+            if (task % nw == wave) {
+              const double pd = exact_part(dv, cv, a.is_csr, a.kind, p, lpt, tc, x, part, parts);
+              if (lane == 0) part_d[pos * kMaxParts + part] = pd;
+            }
         ++pos;
+      }
+      __syncthreads();
+      // new rows: their parts summed in order
+      if (threadIdx.x < pos && cur_new[threadIdx.x]) {
+        double dsum = 0.0;
+        for (int part = 0; part < parts; ++part) dsum += part_d[threadIdx.x * kMaxParts + part];
+        cur_d[threadIdx.x] = dsum * dscale;
       }
       __syncthreads();
       const double dxv = cur_d[0];
@@ -714,7 +762,8 @@ hipError_t launch_neighbor_values(PathArgs a, int32_t N, float* nv, hipStream_t 
 constexpr int kLdsTargetMax = 8192;
 
 template <typename K>
-static hipError_t launch_with_target(K kern, DenseView dv, CsrView cv, PathArgs a, hipStream_t s) {
+static hipError_t launch_with_target(K kern, int threads, DenseView dv, CsrView cv, PathArgs a,
+                                     hipStream_t s) {
   const int B = a.is_csr ? cv.B : dv.B;
   a.tgt_in_lds = B <= kLdsTargetMax ? 1 : 0;
   const size_t lds = a.tgt_in_lds ? 16 * (size_t)B : 0;
@@ -723,16 +772,17 @@ static hipError_t launch_with_target(K kern, DenseView dv, CsrView cv, PathArgs 
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(a.T), dim3(256), lds, s, dv, cv, a);
+  hipLaunchKernelGGL(kern, dim3(a.T), dim3(threads), lds, s, dv, cv, a);
   return hipGetLastError();
 }
 
 hipError_t launch_paths(DenseView dv, CsrView cv, PathArgs a, hipStream_t s) {
-  return launch_with_target(paths_kernel, dv, cv, a, s);
+  return launch_with_target(paths_kernel, split_rows(a.is_csr, a.is_csr ? cv.B : dv.B) ? kPathThreads : 256,
+                            dv, cv, a, s);
 }
 
 hipError_t launch_paths_on_demand(DenseView dv, CsrView cv, PathArgs a, hipStream_t s) {
-  return launch_with_target(paths_on_demand_kernel, dv, cv, a, s);
+  return launch_with_target(paths_on_demand_kernel, 256, dv, cv, a, s);
 }
 
 }  // namespace dd
