@@ -23,6 +23,8 @@
  *   the stream reaches that point.
  * - One dd_kernel may be used from several host threads and streams at once;
  *   per-call scratch memory is stream-ordered (hipMallocAsync on `stream`).
+ *   The calls that change a handle (dd_attach_mesh, dd_free_kernel) must not
+ *   overlap other calls on the same handle.
  *
  * Error bounds
  * ------------

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -91,7 +92,7 @@ struct AsyncBuf {
 struct dd_ctx {
   uint32_t magic = kCtxMagic;
   int device = 0;
-  int live_kernels = 0;
+  std::atomic<int> live_kernels{0};   // loads and frees may come from several threads
 };
 
 struct dd_kernel {
@@ -519,7 +520,7 @@ dd_status dd_create(int device, dd_ctx** out) {
 dd_status dd_destroy(dd_ctx* ctx) {
   if (!ctx_ok(ctx)) return fail(DD_ESTATE, "not a live context");
   if (ctx->live_kernels > 0)
-    return fail(DD_ESTATE, "%d kernels still loaded in this context", ctx->live_kernels);
+    return fail(DD_ESTATE, "%d kernels still loaded in this context", ctx->live_kernels.load());
   ctx->magic = kDead;
   delete ctx;
   return DD_OK;
