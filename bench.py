@@ -208,12 +208,14 @@ def run_grid1025(args):
         us = 1000.0 * a.elapsed_time(b) / reps
         byts = nnz * 6 + N * (16 if kind == "tv" else 24)
         cls, counts = kc.local_minima([t0_], f, [bd])
+        cert, und = int(counts[0, 0].item()), int(counts[0, 1].item())
+        resolved, res_ms = resolve_census(kc, [t0_], kind, cls, counts)
         res[f"a4_csr_{kind}_tau1e-5"] = {
             "avg_us": round(us, 1), "nnz": nnz, "nnz_frac": round(nnz / (N * B), 4),
             "alg_bytes": byts, "GB/s": round(gbs(byts, us), 1),
             "hbm_frac": round(gbs(byts, us) / HBM_PEAK_GBS, 4),
-            "local_minima_certain": int(counts[0, 0].item()),
-            "local_minima_undecided": int(counts[0, 1].item())}
+            "local_minima_certain": cert, "local_minima_undecided": und,
+            "local_minima_fp64": resolved[0], "fp64_census_ms": res_ms}
         log(f"csr {kind}: {us:.0f} us, minima {counts[0].tolist()}")
     res.update(csr_batch_rows(kc, ts_all, "tau1e-5"))
     kc.free()
@@ -266,6 +268,20 @@ def run_grid1025(args):
     print(json.dumps(out), flush=True)
 
 
+def resolve_census(k, targets, kind, cls, counts):
+    """FP64 re-decision of a census: (minima per field, milliseconds)."""
+    import torch
+    if counts is None:
+        counts = torch.zeros((len(targets), 2), dtype=torch.int32, device=cls.device)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    k.resolve_minima(targets, kind, cls, counts)
+    b.record()
+    torch.cuda.synchronize()
+    return [int(x) for x in counts[:, 0].cpu().tolist()], round(a.elapsed_time(b), 2)
+
+
 def csr_batch_rows(kc, ts_all, label):
     """The many-target pass over the truncated rows at T = 256 (TV and KL),
     with the local-minimum census of the 256 fields.
@@ -297,6 +313,9 @@ def csr_batch_rows(kc, ts_all, label):
         ops = 2 if kind == "tv" else 1
         cls, counts = kc.local_minima(ts, D, bounds)
         c = counts.cpu().numpy()
+        # the FP64 re-decision on the first 8 fields (it costs 1 + degree FP64 rows
+        # per undecided vertex)
+        resolved, res_ms = resolve_census(kc, ts[:8], kind, cls[:8].contiguous(), None)
         out[f"a4_csr_batch_{kind}_{label}_T{T}"] = {
             "avg_us": round(us, 1), "nnz": nnz, "nnz_frac": round(nnz / (N * B), 4),
             "entry_updates_per_s": upd, "entries_per_s": N * B * T / (us * 1e-6),
@@ -305,7 +324,8 @@ def csr_batch_rows(kc, ts_all, label):
             "GB/s": round(gbs(byts, us), 1),
             "local_minima_per_field": {"certain_mean": float(c[:, 0].mean()),
                                        "certain_max": int(c[:, 0].max()),
-                                       "undecided_mean": float(c[:, 1].mean())}}
+                                       "undecided_mean": float(c[:, 1].mean()),
+                                       "fp64_first8": resolved, "fp64_census_ms": res_ms}}
         log(f"csr batch {kind} {label}: {us:.0f} us for {T} targets")
     del D
     return out

@@ -313,6 +313,17 @@ dd_status dd_local_minima(dd_kernel* k, int32_t T, const int32_t* targets, const
                           const dd_error_bound* bounds, uint8_t* class_dev, int32_t* counts_dev,
                           void* stream);
 
+/* FP64 re-decision of a local-minimum census (Section V, "Low resolution
+ * discretizations"): every entry of class 2 (undecided) in class_dev, as
+ * dd_local_minima left it for these targets and kind, becomes 1 or 0 from the
+ * FP64 distances of the vertex and its neighbours, evaluated from the loaded
+ * matrix (1: no neighbour strictly lower, the census rule).  counts_dev
+ * (nullable, device [T][2]) is recomputed: minima, and 0 undecided.  Costs
+ * (1 + degree) FP64 row evaluations per undecided vertex.  Asynchronous on
+ * `stream`. */
+dd_status dd_resolve_minima(dd_kernel* k, int32_t T, const int32_t* targets, int32_t kind,
+                            uint8_t* class_dev, int32_t* counts_dev, void* stream);
+
 /* Plan one path: the field of `target` (dd_distance_field) followed by the
  * path from `source` (dd_trace_paths).  path_host must hold max_steps+1
  * entries.  rechecks nullable.  Synchronous with respect to `stream`. */

@@ -300,6 +300,20 @@ class Kernel:
                                           _stream_handle(stream)))
         return cls, counts
 
+    def resolve_minima(self, targets, kind, classes, counts=None, stream=None):
+        """Re-decide the undecided entries (class 2) of a census in FP64, in place;
+        counts ([T, 2] int32 device tensor, optional) recomputed."""
+        torch = _torch()
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        if not classes.is_contiguous() or classes.dtype != torch.uint8:
+            raise ValueError("classes must be a contiguous uint8 tensor")
+        L.check(self._lib.dd_resolve_minima(
+            self._h, int(len(t)), C.c_void_p(t.ctypes.data), _kind(kind),
+            C.c_void_p(classes.data_ptr()),
+            C.c_void_p(counts.data_ptr()) if counts is not None else None,
+            _stream_handle(stream)))
+        return classes, counts
+
     def plan_path(self, source, target, kind, max_steps=4000, stream=None):
         """(vertex list, status name, FP64 re-decisions) for one query; synchronous."""
         buf = (C.c_int32 * (max_steps + 1))()

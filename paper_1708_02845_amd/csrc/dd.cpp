@@ -1210,6 +1210,50 @@ dd_status dd_local_minima(dd_kernel* k, int32_t T, const int32_t* targets, const
   return DD_OK;
 }
 
+dd_status dd_resolve_minima(dd_kernel* k, int32_t T, const int32_t* targets, int32_t kind,
+                            uint8_t* class_dev, int32_t* counts_dev, void* stream) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (!k->has_adj) return fail(DD_EINVAL, "kernel was loaded without adjacency");
+  if (dd_status st = check_kind(k, kind)) return st;
+  if (T <= 0 || !targets || !class_dev)
+    return fail(DD_EINVAL, "T=%d or a required pointer is null", T);
+  for (int32_t i = 0; i < T; ++i)
+    if (targets[i] < 0 || targets[i] >= k->N)
+      return fail(DD_EINVAL, "targets[%d]=%d not in [0, %d)", i, targets[i], k->N);
+  HIP_OR(hipSetDevice(k->ctx->device));
+  hipStream_t s = as_stream(stream);
+  dd::PathArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.adj = k->adj.as<const int32_t>();
+  a.adj_w = k->adj_w;
+  a.T = T;
+  a.kind = kind;
+  a.is_csr = k->is_csr;
+  // scratch: [targets when T is large] [FP64 target rows, logs, constants]
+  const bool inl = T <= dd::kInlinePaths;
+  const size_t n_tgt = inl ? 0 : (4 * (size_t)T + 255) & ~size_t(255);
+  const size_t n_row = 16 * (size_t)T * (size_t)k->B + 32 * (size_t)T;
+  AsyncBuf ws(s);
+  HIP_OR(ws.alloc(n_tgt + n_row));
+  unsigned char* base = ws.as<unsigned char>();
+  if (inl) {
+    for (int32_t i = 0; i < T; ++i) a.small.tgt[i] = targets[i];
+  } else {
+    // pageable source: the copy is staged before hipMemcpyAsync returns
+    HIP_OR(hipMemcpyAsync(base, targets, 4 * (size_t)T, hipMemcpyHostToDevice, s));
+    a.targets = reinterpret_cast<const int32_t*>(base);
+  }
+  double* trow = reinterpret_cast<double*>(base + n_tgt);
+  double* tlog = trow + (size_t)T * (size_t)k->B;
+  double* tcon = tlog + (size_t)T * (size_t)k->B;
+  HIP_OR(dd::launch_target_rows(k->dense(), k->csr(), a, trow, tlog, tcon, s));
+  a.trow = trow;
+  a.tlog = tlog;
+  a.tconst = tcon;
+  HIP_OR(dd::launch_resolve_minima(k->dense(), k->csr(), a, k->N, class_dev, counts_dev, s));
+  return DD_OK;
+}
+
 dd_status dd_plan_path(dd_kernel* k, int32_t source, int32_t target, int32_t kind,
                        int32_t max_steps, int32_t* path_host, int32_t* len, int32_t* status,
                        int32_t* rechecks, void* stream) {

@@ -152,6 +152,10 @@ hipError_t launch_support_kl_field(DenseView v, int32_t target, double tau, int 
 // (inline or device) of PathArgs
 hipError_t launch_local_minima(PathArgs a, int32_t N, uint8_t* cls, int32_t* counts,
                                hipStream_t s);
+// FP64 re-decision of the undecided census entries (uses adj, adj_w, T,
+// targets, kind, is_csr, trow/tlog/tconst of PathArgs); counts recomputed
+hipError_t launch_resolve_minima(DenseView dv, CsrView cv, PathArgs a, int32_t N, uint8_t* cls,
+                                 int32_t* counts, hipStream_t s);
 
 // Triangle-based paths (tri.hip).
 struct TriArgs {

@@ -717,6 +717,53 @@ __global__ __launch_bounds__(256) void local_minima_kernel(PathArgs a, int32_t N
   }
 }
 
+// Re-decision of the census in FP64: every vertex of class 2 (undecided) gets
+// the FP64 distances of itself and its neighbours from the resident rows (one
+// wave, rows in turn) and becomes 1 if no neighbour is strictly lower (the
+// oracle's rule: min over neighbours >= d(v)), else 0.  A wave takes 64
+// vertices at a time and works through the undecided ones among them.
+__global__ __launch_bounds__(256) void resolve_minima_kernel(DenseView dv, CsrView cv, PathArgs a,
+                                                             int32_t N, uint8_t* cls) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t total = (int64_t)N * a.T;
+  const int Bt = a.is_csr ? cv.B : dv.B;
+  for (int64_t base = wid * 64; base < total; base += nw * 64) {
+    const int64_t idx = base + lane;
+    uint64_t m = __ballot(idx < total && cls[idx] == 2);
+    while (m) {
+      const int l = (int)__builtin_ctzll(m);
+      m &= m - 1;
+      const int64_t e = base + l;
+      const int i = __builtin_amdgcn_readfirstlane((int)(e / N));
+      const int v = __builtin_amdgcn_readfirstlane((int)(e - (int64_t)i * N));
+      const double* p = a.trow + (int64_t)i * Bt;
+      const double* lp = a.tlog + (int64_t)i * Bt;
+      const double* tc = a.tconst + (int64_t)i * 4;
+      const double d0 = exact_distance(dv, cv, a.is_csr, a.kind, p, lp, tc, v);
+      bool minimum = true;
+      for (int j = 0; j < a.adj_w && minimum; ++j) {
+        const int u = __builtin_amdgcn_readfirstlane(a.adj[(int64_t)v * a.adj_w + j]);
+        if (u < 0) break;
+        if (exact_distance(dv, cv, a.is_csr, a.kind, p, lp, tc, u) < d0) minimum = false;
+      }
+      if (lane == 0) cls[e] = minimum ? 1 : 0;
+    }
+  }
+}
+
+// counts[i] = (minima, undecided) of field i from the classes.
+__global__ __launch_bounds__(256) void count_classes_kernel(const uint8_t* cls, int32_t T,
+                                                            int32_t N, int32_t* counts) {
+  const int64_t total = (int64_t)N * T;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int c = cls[idx];
+    if (c) atomicAdd(counts + 2 * (idx / N) + (c - 1), 1);
+  }
+}
+
 // Clears the census counters with a kernel (not a memset node), so a caller
 // may capture the call in a graph.
 __global__ void zero_counts_kernel(int32_t* p, int n) {
@@ -736,6 +783,23 @@ hipError_t launch_local_minima(PathArgs a, int32_t N, uint8_t* cls, int32_t* cou
   if (grid > cap) grid = cap;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(local_minima_kernel, dim3((unsigned)grid), dim3(256), 0, s, a, N, cls,
+                     counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve_minima(DenseView dv, CsrView cv, PathArgs a, int32_t N, uint8_t* cls,
+                                 int32_t* counts, hipStream_t s) {
+  const int64_t total = (int64_t)N * a.T;
+  int64_t grid = (total + 255) / 256;
+  const int64_t cap = (int64_t)num_cus() * 8;
+  if (grid > cap) grid = cap;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(resolve_minima_kernel, dim3((unsigned)grid), dim3(256), 0, s, dv, cv, a, N,
+                     cls);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !counts) return e;
+  hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(256), 0, s, counts, 2 * a.T);
+  hipLaunchKernelGGL(count_classes_kernel, dim3((unsigned)grid), dim3(256), 0, s, cls, a.T, N,
                      counts);
   return hipGetLastError();
 }

@@ -81,3 +81,55 @@ def test_planted_minima_exact(gpu_ctx):
         assert int(counts[0, 0].item()) == len(ref) and int(counts[0, 1].item()) == 0
     finally:
         k.free()
+
+
+@pytest.mark.parametrize("kind", ["kl", "tv"])
+@pytest.mark.parametrize("T", [4, 12])
+def test_resolved_census_equals_oracle(gpu_ctx, kind, T):
+    """After the FP64 re-decision the census is the oracle's set of spurious
+    minima exactly (T = 12 takes the many-target pass)."""
+    from paper_1708_02845_amd import Kernel
+    g = grid_domain(97, 3, (0.1, 0.25), seed_id=71)
+    P = g.poisson_kernel().astype(np.float32)
+    tau = 1e-3
+    k = Kernel.load_dense(gpu_ctx, P, tau=tau, adjacency=(g.adj_ptr, g.adj_idx))
+    try:
+        ts = targets_sources(73, g.N, T)[0]
+        D, bounds = k.batch_fields(ts, kind)
+        # bounds widened 1000-fold: many undecided entries for the re-decision
+        wide = [(1000.0 * a, 1000.0 * r) for a, r in bounds]
+        cls, counts = k.local_minima(ts, D, wide)
+        und_before = counts.cpu().numpy()[:, 1].copy()
+        k.resolve_minima(ts, kind, cls, counts)
+        cls, counts = cls.cpu().numpy(), counts.cpu().numpy()
+        Pt, thr = dv.truncate(P.astype(np.float64), tau)
+        assert und_before.sum() > 0
+        for i, t in enumerate(ts):
+            ref = dv.tv_trunc_field(Pt, int(t)) if kind == "tv" else dv.kl_trunc_field(Pt, int(t), thr)
+            want = sorted(op.spurious_minima(ref, g.adj_ptr, g.adj_idx, int(t)))
+            got = np.nonzero(cls[i] == 1)[0].tolist()
+            assert got == want, (i, t)
+            assert counts[i, 0] == len(want) and counts[i, 1] == 0
+    finally:
+        k.free()
+
+
+def test_resolved_census_on_contraction_fields(gpu_ctx):
+    """Dense KL from the contraction: no spurious minima once resolved."""
+    from paper_1708_02845_amd import Kernel
+    g = grid_domain(97, 3, (0.1, 0.25), seed_id=71)
+    P = g.poisson_kernel().astype(np.float32)
+    k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx), gemm_form="f16x3")
+    try:
+        ts = targets_sources(74, g.N, 6)[0]
+        D, bounds = k.batch_fields(ts, "kl")
+        cls, counts = k.local_minima(ts, D, bounds)
+        k.resolve_minima(ts, "kl", cls, counts)
+        cls, counts = cls.cpu().numpy(), counts.cpu().numpy()
+        for i, t in enumerate(ts):
+            want = op.spurious_minima(dv.kl_field(P.astype(np.float64), int(t)), g.adj_ptr,
+                                      g.adj_idx, int(t))
+            assert np.nonzero(cls[i] == 1)[0].tolist() == sorted(want)
+            assert counts[i, 1] == 0
+    finally:
+        k.free()
