@@ -288,8 +288,8 @@ def csr_batch_rows(kc, ts_all, label):
 
     Per stored entry and target it reads 4 bytes of target weights from LDS
     (peak 128 B per clock per CU: 78.6 TB/s at 256 CUs and 2.4 GHz) and issues
-    2 (TV: min, add) or 1 (KL: FMA) VALU operations (non-packed FP32 peak
-    256 x 64 lanes x 2.4 GHz = 39.3e12 per second)."""
+    1.5 (TV in fixed point: a min, and half of a three-way add) or 1 (KL: an
+    FMA) VALU operations (peak 256 x 64 lanes x 2.4 GHz = 39.3e12 per second)."""
     import torch
     N, B, nnz = kc.N, kc.B, kc.nnz
     T = 256
@@ -310,7 +310,7 @@ def csr_batch_rows(kc, ts_all, label):
         us = 1000.0 * a.elapsed_time(b) / reps
         upd = nnz * T / (us * 1e-6)
         byts = nnz * 6 + N * 16 + T * N * 4
-        ops = 2 if kind == "tv" else 1
+        ops = 1.5 if kind == "tv" else 1
         cls, counts = kc.local_minima(ts, D, bounds)
         c = counts.cpu().numpy()
         # the FP64 re-decision on the first 8 fields (it costs 1 + degree FP64 rows

@@ -10,7 +10,11 @@
 //   KL_tau(x, t) / ln 2 = Hb_t - sum_{S_x} p~ log2 q - log2 phi_x (W_t - sum_{S_x} p~)
 //                = Hb_t - log2(phi_x) W_t - sum_{S_x} p~ g,   g = log2(q / phi_x) >= 0
 // since p~ is 0 outside S_t.  Each stored entry is read once per launch and
-// costs two VALU operations (TV) or one FMA (KL) per target.
+// costs two VALU operations (TV) or one FMA (KL) per target.  TV runs in
+// unsigned fixed point (values times 2^s, rounded to nearest) when the stored
+// row sums allow it: min commutes with the monotone rounding, the sums are
+// exact integers (no FP64 carries), and two entries' minima and the
+// accumulator combine in one v_add3_u32.
 //
 // Layout of the work: a wave owns R consecutive rows and all targets of the
 // launch (TPL targets per lane, up to 256).  The target rows are a dense
@@ -39,6 +43,11 @@ __device__ __forceinline__ float f16_value(uint16_t h, float rs) {
   return (float)__builtin_bit_cast(_Float16, h) * rs;
 }
 
+// Fixed-point value of q >= 0: q * 2^shift rounded to nearest (exact scaling).
+__device__ __forceinline__ uint32_t fixq(float q, int shift) {
+  return __float2uint_rn(ldexpf(q, shift));
+}
+
 __device__ __forceinline__ int rdlane(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
 __device__ __forceinline__ float rdlane(float v, int j) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
@@ -51,10 +60,10 @@ __global__ void clear_block_kernel(float4* __restrict__ p, int64_t n4) {
 }
 
 // One workgroup per target slot: scatter the truncated target row into column
-// `slot` of tb and reduce W_t and Hb_t in FP64 (the product p log2 p in FP32,
-// as the single-target pass does).
+// `slot` of tb (as fixed-point bits when shift > 0) and reduce W_t and Hb_t in
+// FP64 (the product p log2 p in FP32, as the single-target pass does).
 __global__ __launch_bounds__(256) void csr_targets_kernel(CsrView v, TargetList tl, int32_t Tp,
-                                                          float* __restrict__ tb,
+                                                          int shift, float* __restrict__ tb,
                                                           double* __restrict__ wt,
                                                           double* __restrict__ hbt) {
   const int slot = blockIdx.x;
@@ -66,7 +75,7 @@ __global__ __launch_bounds__(256) void csr_targets_kernel(CsrView v, TargetList 
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int b = v.col[s + i];
     const float p = v.val16 ? f16_value(v.val16[s + i], rs) : v.val[s + i];
-    tb[(int64_t)b * Tp + slot] = p;
+    tb[(int64_t)b * Tp + slot] = shift ? __uint_as_float(fixq(p, shift)) : p;
     w += (double)p;
     hb += (double)(p * hw_log2(p));
   }
@@ -110,13 +119,13 @@ __device__ __forceinline__ void fetch_window(const CsrView& v, int64_t s, int n,
 
 template <int KIND, int F16>
 __device__ __forceinline__ void take_window(int n, int base, int lane, float rphi, float rs,
-                                            int rc, float rq, int& col, float& val,
+                                            int shift, int rc, float rq, int& col, float& val,
                                             double& qsum) {
   const bool ok = base + lane < n;
   col = ok ? rc : kEnd;
   if (F16) rq = f16_value((uint16_t)__float_as_int(rq), rs);
-  if (KIND == 0) {
-    val = rq;
+  if (KIND == 0 || KIND == 2) {
+    val = KIND == 2 ? __uint_as_float(fixq(rq, shift)) : rq;
     qsum += ok ? (double)rq : 0.0;
   } else {
     val = hw_log2(rq * rphi);   // never read past the row's end
@@ -158,7 +167,8 @@ __global__ __launch_bounds__(kWaves * 64) void csr_batch_kernel(CsrView v,
                                                                const float* __restrict__ tb,
                                                                const double* __restrict__ wt,
                                                                const double* __restrict__ hbt,
-                                                               TargetList tl, int32_t T,
+                                                                               TargetList tl, int32_t T,
+                                                               int shift,
                                                                float* __restrict__ out) {
   constexpr int TP = 64 * TPL;                  // target slots of the block
   constexpr int NV4 = kKC * TP / 4 / (kWaves * 64);   // float4 per thread per chunk
@@ -176,6 +186,7 @@ __global__ __launch_bounds__(kWaves * 64) void csr_batch_kernel(CsrView v,
   double qsum[R];
   float a32[R][TPL];
   double a64[R][TPL];
+  uint32_t au[R][TPL];   // fixed-point TV sums
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t row = row0 + r;
@@ -189,13 +200,15 @@ __global__ __launch_bounds__(kWaves * 64) void csr_batch_kernel(CsrView v,
     int rc;
     float rq;
     fetch_window<F16>(v, rs[r], rn[r], 0, lane, rc, rq);
-    take_window<KIND, F16>(rn[r], 0, lane, rphi[r], rsc[r], rc, rq, col[r], val[r], qsum[r]);
+    take_window<KIND, F16>(rn[r], 0, lane, rphi[r], rsc[r], shift, rc, rq, col[r], val[r],
+                           qsum[r]);
     fetch_window<F16>(v, rs[r], rn[r], 64, lane, ncol[r], nval[r]);
     wnext[r] = 128;
 #pragma unroll
     for (int i = 0; i < TPL; ++i) {
       a32[r][i] = 0.f;
       a64[r][i] = 0.0;
+      au[r][i] = 0u;
     }
   }
 
@@ -253,21 +266,34 @@ __global__ __launch_bounds__(kWaves * 64) void csr_batch_kernel(CsrView v,
           float p0[TPL], p1[TPL];
           load_weights<KIND, TPL>(chunk, c0, lane, p0);
           load_weights<KIND, TPL>(chunk, c1, lane, p1);
-          accumulate<KIND, TPL>(p0, g0, a32[r]);
-          accumulate<KIND, TPL>(p1, g1, a32[r]);
+          if constexpr (KIND == 2) {
+            const uint32_t q0 = __float_as_uint(g0), q1 = __float_as_uint(g1);
+#pragma unroll
+            for (int i = 0; i < TPL; ++i)
+              au[r][i] += min(q0, __float_as_uint(p0[i])) + min(q1, __float_as_uint(p1[i]));
+          } else {
+            accumulate<KIND, TPL>(p0, g0, a32[r]);
+            accumulate<KIND, TPL>(p1, g1, a32[r]);
+          }
         }
         if (j < j1) {
           const int c0 = rdlane(col[r], j) - k0;
           const float g0 = rdlane(val[r], j);
           float p0[TPL];
           load_weights<KIND, TPL>(chunk, c0, lane, p0);
-          accumulate<KIND, TPL>(p0, g0, a32[r]);
+          if constexpr (KIND == 2) {
+            const uint32_t q0 = __float_as_uint(g0);
+#pragma unroll
+            for (int i = 0; i < TPL; ++i) au[r][i] += min(q0, __float_as_uint(p0[i]));
+          } else {
+            accumulate<KIND, TPL>(p0, g0, a32[r]);
+          }
         }
         j0[r] = j1;
         // the whole window consumed and more entries left: move to the next
         if (j1 == 64 && wnext[r] - 64 < rn[r]) {
-          take_window<KIND, F16>(rn[r], wnext[r] - 64, lane, rphi[r], rsc[r], ncol[r], nval[r],
-                                 col[r], val[r], qsum[r]);
+          take_window<KIND, F16>(rn[r], wnext[r] - 64, lane, rphi[r], rsc[r], shift, ncol[r],
+                                 nval[r], col[r], val[r], qsum[r]);
           j0[r] = 0;
           fetch_window<F16>(v, rs[r], rn[r], wnext[r], lane, ncol[r], nval[r]);
           wnext[r] += 64;
@@ -275,7 +301,7 @@ __global__ __launch_bounds__(kWaves * 64) void csr_batch_kernel(CsrView v,
         }
         break;
       }
-      if (done > 0) {
+      if (KIND != 2 && done > 0) {
 #pragma unroll
         for (int i = 0; i < TPL; ++i) {
           a64[r][i] += (double)a32[r][i];
@@ -305,7 +331,7 @@ __global__ __launch_bounds__(kWaves * 64) void csr_batch_kernel(CsrView v,
   for (int r = 0; r < R; ++r) {
     const int64_t row = row0 + r;
     double Q = 0.0, lphi = 0.0;
-    if (KIND == 0) {
+    if (KIND == 0 || KIND == 2) {
       Q = qsum[r];
       for (int off = 32; off > 0; off >>= 1) Q += __shfl_xor(Q, off);
     }
@@ -318,6 +344,8 @@ __global__ __launch_bounds__(kWaves * 64) void csr_batch_kernel(CsrView v,
       double d;
       if (KIND == 0)
         d = W[i] + Q - 2.0 * a64[r][i];
+      else if (KIND == 2)
+        d = W[i] + Q - 2.0 * ldexp((double)au[r][i], -shift);
       else
         d = (Hb[i] - lphi * W[i] - a64[r][i]) * 0.69314718055994530942;
       out[(int64_t)slot * v.N + row] = row == tl.t[slot] ? 0.f : (float)d;
@@ -329,16 +357,16 @@ constexpr int rows_per_wave(int TPL) { return TPL == 4 ? 4 : 8; }
 
 template <int KIND, int TPL>
 hipError_t batch_launch(CsrView v, const float* tb, const double* wt, const double* hbt,
-                        TargetList tl, int32_t T, float* out, hipStream_t s) {
+                        TargetList tl, int32_t T, int shift, float* out, hipStream_t s) {
   constexpr int R = rows_per_wave(TPL);
   const int64_t rows_per_block = (int64_t)kWaves * R;
   const int64_t grid = (v.N + rows_per_block - 1) / rows_per_block;
   if (v.val16)
     hipLaunchKernelGGL((csr_batch_kernel<KIND, TPL, R, 1>), dim3((unsigned)grid),
-                       dim3(kWaves * 64), 0, s, v, tb, wt, hbt, tl, T, out);
+                       dim3(kWaves * 64), 0, s, v, tb, wt, hbt, tl, T, shift, out);
   else
     hipLaunchKernelGGL((csr_batch_kernel<KIND, TPL, R, 0>), dim3((unsigned)grid),
-                       dim3(kWaves * 64), 0, s, v, tb, wt, hbt, tl, T, out);
+                       dim3(kWaves * 64), 0, s, v, tb, wt, hbt, tl, T, shift, out);
   return hipGetLastError();
 }
 
@@ -352,8 +380,8 @@ size_t csr_batch_workspace(CsrView v, int32_t T) {
   return (size_t)(bpad * tp) * sizeof(float) + 2 * sizeof(double) * (size_t)kMaxBatch;
 }
 
-hipError_t launch_csr_batch(CsrView v, TargetList tl, int32_t T, int kind, void* ws, float* out,
-                            hipStream_t s) {
+hipError_t launch_csr_batch(CsrView v, TargetList tl, int32_t T, int kind, int tv_shift, void* ws,
+                            float* out, hipStream_t s) {
   if (T <= 0 || T > kMaxBatch) return hipErrorInvalidValue;
   const int tpl = tpl_for(T);
   const int64_t tp = 64 * tpl;
@@ -365,18 +393,24 @@ hipError_t launch_csr_batch(CsrView v, TargetList tl, int32_t T, int kind, void*
   const int cgrid = (int)std::min<int64_t>((n4 + 255) / 256, 4096);
   hipLaunchKernelGGL(clear_block_kernel, dim3(cgrid), dim3(256), 0, s,
                      reinterpret_cast<float4*>(tb), n4);
-  hipLaunchKernelGGL(csr_targets_kernel, dim3(T), dim3(256), 0, s, v, tl, (int32_t)tp, tb, wt,
-                     hbt);
+  const int shift = kind == 0 ? tv_shift : 0;
+  hipLaunchKernelGGL(csr_targets_kernel, dim3(T), dim3(256), 0, s, v, tl, (int32_t)tp, shift, tb,
+                     wt, hbt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (kind == 0) {
-    if (tpl == 1) return batch_launch<0, 1>(v, tb, wt, hbt, tl, T, out, s);
-    if (tpl == 2) return batch_launch<0, 2>(v, tb, wt, hbt, tl, T, out, s);
-    return batch_launch<0, 4>(v, tb, wt, hbt, tl, T, out, s);
+  if (kind == 0 && shift > 0) {
+    if (tpl == 1) return batch_launch<2, 1>(v, tb, wt, hbt, tl, T, shift, out, s);
+    if (tpl == 2) return batch_launch<2, 2>(v, tb, wt, hbt, tl, T, shift, out, s);
+    return batch_launch<2, 4>(v, tb, wt, hbt, tl, T, shift, out, s);
   }
-  if (tpl == 1) return batch_launch<1, 1>(v, tb, wt, hbt, tl, T, out, s);
-  if (tpl == 2) return batch_launch<1, 2>(v, tb, wt, hbt, tl, T, out, s);
-  return batch_launch<1, 4>(v, tb, wt, hbt, tl, T, out, s);
+  if (kind == 0) {
+    if (tpl == 1) return batch_launch<0, 1>(v, tb, wt, hbt, tl, T, 0, out, s);
+    if (tpl == 2) return batch_launch<0, 2>(v, tb, wt, hbt, tl, T, 0, out, s);
+    return batch_launch<0, 4>(v, tb, wt, hbt, tl, T, 0, out, s);
+  }
+  if (tpl == 1) return batch_launch<1, 1>(v, tb, wt, hbt, tl, T, 0, out, s);
+  if (tpl == 2) return batch_launch<1, 2>(v, tb, wt, hbt, tl, T, 0, out, s);
+  return batch_launch<1, 4>(v, tb, wt, hbt, tl, T, 0, out, s);
 }
 
 }  // namespace dd

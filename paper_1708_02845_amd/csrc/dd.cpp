@@ -118,6 +118,7 @@ struct dd_kernel {
   DevBuf val16, rsc;   // FP16 form of the stored values and 2^-e_x per row
   int csr_values = DD_CSR_F32;
   double qmax = 0.0;   // max_x of the stored row sums
+  int32_t max_len = 0; // most entries stored in one row
   int64_t nnz = 0;
   std::vector<double> Ht_host, Wt_host;   // per row over the stored entries
   double lphi_absmax = 0.0;               // max_x |log2 phi_x|
@@ -337,9 +338,20 @@ dd_error_bound gemm_bound(const dd_kernel* k, int32_t t) {
   return b;
 }
 
+// Fixed-point shift of the many-target TV pass: values times 2^s with every
+// sum of stored values (row sums, at most qmax) times 2^s below 2^32, plus one
+// unit of rounding per entry; 0 keeps the FP32 path.
+int tv_shift(const dd_kernel* k) {
+  if (k->qmax <= 1.75) return 31;
+  if (k->qmax <= 3.5) return 30;
+  return 0;
+}
+
 // Bound of a truncated field from the many-target pass.  Per chunk of 32
 // columns FP32 partial sums (31u of their magnitude), then FP64.
-//   TV: d = W_t + Q_x - 2M, M = sum_{S_x} min(q, p~) <= W_t: 62u W_t.
+//   TV: d = W_t + Q_x - 2M, M = sum_{S_x} min(q, p~) <= W_t: 62u W_t in FP32;
+//       in fixed point (values times 2^s) the longest row's entry count
+//       times 2^-s (rounding only; the sums are exact).
 //   KL: d = ln2 (Hb_t - log2(phi_x) W_t - S), S = sum_{S_x} p~ g with
 //       g = hw_log2(q * fl(1/phi_x)): 2u relative in the argument (2.9u
 //       absolute in g), hardware log2 4u|g| + 4u, product u, partial sums
@@ -353,7 +365,11 @@ dd_error_bound csr_batch_bound(const dd_kernel* k, int kind, int32_t t) {
   const double ln2 = 0.69314718055994530942;
   dd_error_bound b;
   b.rel = kU;
-  if (kind == DD_TV)
+  if (kind == DD_TV && tv_shift(k) > 0)
+    // fixed point: min(fix q, fix p) = fix(min(q, p)) is within 2^-(s+1) of
+    // min(q, p), the integer sums are exact, d = W_t + Q_x - 2M
+    b.abs = std::ldexp((double)k->max_len, -tv_shift(k));
+  else if (kind == DD_TV)
     b.abs = 62.0 * kU * W;
   else
     b.abs = ln2 * 6.9 * kU * W + 36.0 * kU * (H + ln2 * k->lphi_absmax * W);
@@ -472,8 +488,10 @@ dd_status csr_row_constants(dd_kernel* k, std::vector<double>* rowmax) {
   k->Ht_host.assign(N, 0.0);
   k->Wt_host.assign(N, 0.0);
   k->qmax = 0.0;
+  k->max_len = 0;
   if (rowmax) rowmax->assign(N, 0.0);
   for (int32_t x = 0; x < N; ++x) {
+    k->max_len = std::max(k->max_len, ln[x]);
     double w = 0.0, h = 0.0, m = 0.0;
     for (int32_t i = 0; i < ln[x]; ++i) {
       const double p = v[st[x] + i];
@@ -776,6 +794,7 @@ dd_status dd_load_kernel_csr(dd_ctx* ctx, int32_t N, int32_t B, const int64_t* r
     k->Wt_host[x] = w;
     k->Ht_host[x] = h;
     k->qmax = std::max(k->qmax, w);
+    k->max_len = std::max(k->max_len, ln[x]);
     phi[x] = tau_relative ? tau * row_max[x] : tau;
   }
   auto bail = [&](dd_status s) {
@@ -869,7 +888,8 @@ dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t
       dd::TargetList tl;
       std::memset(&tl, 0, sizeof tl);
       for (int32_t i = 0; i < n; ++i) tl.t[i] = targets[g0 + i];
-      HIP_OR(dd::launch_csr_batch(k->csr(), tl, n, kind, ws.p, out_dev + (int64_t)g0 * k->N, s));
+      HIP_OR(dd::launch_csr_batch(k->csr(), tl, n, kind, tv_shift(k), ws.p,
+                                  out_dev + (int64_t)g0 * k->N, s));
     }
     if (bounds)
       for (int32_t i = 0; i < T; ++i) bounds[i] = csr_batch_bound(k, kind, targets[i]);

@@ -100,8 +100,10 @@ size_t batch_kl_workspace(GemmView gv, int32_t T);
 // (csr_batch.hip).  Up to kMaxBatch targets per launch; ws holds
 // csr_batch_workspace(v, T) bytes.
 size_t csr_batch_workspace(CsrView v, int32_t T);
-hipError_t launch_csr_batch(CsrView v, TargetList tl, int32_t T, int kind, void* ws, float* out,
-                            hipStream_t s);
+// TV runs in fixed point with values times 2^tv_shift when tv_shift > 0 (the
+// caller picks it so that row sums times 2^tv_shift stay below 2^32).
+hipError_t launch_csr_batch(CsrView v, TargetList tl, int32_t T, int kind, int tv_shift, void* ws,
+                            float* out, hipStream_t s);
 hipError_t launch_batch_kl(DenseView dv, GemmView gv, TargetList tl, int32_t T, void* ws,
                            float* out, hipStream_t s);
 
