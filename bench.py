@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"f16x3": 2500.0, "f32": 157.3}
+MFMA_PEAK_TFLOPS = {"f16x3": 2500.0, "bf16x3": 2500.0, "f32": 157.3}
 # source file of each measured kernel, for matching counter records to the code
 KERNEL_SOURCE = {"dense_tv": "stream.hip", "dense_kl": "stream.hip", "csr_tv": "stream.hip",
                  "csr_kl": "stream.hip", "gemm_kl_T1": "gemm.hip", "kl_gemm_f16x3": "gemm.hip"}
@@ -137,7 +137,7 @@ def run_grid1025(args):
     ts = ts_all[:T]
     ctx = Context(0)
     res = {}
-    for form in ("f16x3", "f32"):
+    for form in ("f16x3", "bf16x3", "f32"):
         log(f"loading with the {form} operand")
         t1 = time.perf_counter()
         k = Kernel.load_dense(ctx, P, gemm_form=form)
@@ -158,7 +158,7 @@ def run_grid1025(args):
             b.record()
             torch.cuda.synchronize()
             us = 1000.0 * a.elapsed_time(b) / reps
-            flops = 2.0 * N * B * TT * (3 if form == "f16x3" else 1)
+            flops = 2.0 * N * B * TT * (1 if form == "f32" else 3)
             byts = N * lda * 4 + TT * lda * 4 + TT * N * 4 + N * 4
             tf = flops / (us * 1e-6) / 1e12
             res[f"a5_batched_kl_{form}_T{TT}"] = {
@@ -566,9 +566,10 @@ def main():
         T = args.batch
         ts, ss = t_arr[:T], s_arr[:T]
         kf = Kernel.load_dense(ctx, P, gemm_form="f32")
+        kb = Kernel.load_dense(ctx, P, gemm_form="bf16x3")
         D = torch.empty((T, N), dtype=torch.float32, device="cuda:0")
         reps = 20
-        for form, kern in (("f16x3", kd), ("f32", kf)):
+        for form, kern in (("f16x3", kd), ("bf16x3", kb), ("f32", kf)):
             for _ in range(3):
                 kern.batch_fields(ts, "kl", out=D)
             torch.cuda.synchronize()
@@ -576,7 +577,7 @@ def main():
                 tm.run(f"gemm_{form}", lambda: kern.batch_fields(ts, "kl", out=D), True)
             torch.cuda.synchronize()
             us = tm.avg_us(f"gemm_{form}")
-            flops = 2.0 * N * B * T * (3 if form == "f16x3" else 1)
+            flops = 2.0 * N * B * T * (1 if form == "f32" else 3)
             byts = N * lda * 4 + T * lda * 4 + T * N * 4 + N * 4
             tf = flops / (us * 1e-6) / 1e12
             rows[f"a5_batched_kl_{form}_T{T}"] = {
@@ -587,6 +588,7 @@ def main():
                 "mfma_TFLOP/s": round(tf, 1),
                 "mfma_frac": round(tf / MFMA_PEAK_TFLOPS[form], 4)}
         kf.free()
+        kb.free()
         _, bounds = kd.batch_fields(ts, "kl", out=D)
         for _ in range(2):
             kd.trace_paths(ss, ts, "kl", D, bounds, args.max_steps)

@@ -78,7 +78,9 @@ typedef enum {
 typedef enum {
   DD_FORM_NONE = -1,   /* do not build a batched-KL operand */
   DD_FORM_F32 = 0,     /* FP32 log-kernel, FP32 MFMA */
-  DD_FORM_F16X3 = 1    /* FP16 hi+lo split of the log-kernel and of the targets, 3 MFMA products */
+  DD_FORM_F16X3 = 1,   /* FP16 hi+lo split of the log-kernel and of the targets, 3 MFMA products */
+  DD_FORM_BF16X3 = 2   /* BF16 hi+lo split (8 + 8 significant bits, no scaling of the targets),
+                          3 MFMA products; a looser stated bound (3 x 2^-16 relative per term) */
 } dd_form;
 
 /* Storage of the stored values of a truncated (CSR) handle, as read by the

@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(HERE, "libdd.so")
 
 DD_OK, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ESTATE = range(5)
 DD_TV, DD_KL, DD_CHI2, DD_HELLINGER = 0, 1, 2, 3
-DD_FORM_NONE, DD_FORM_F32, DD_FORM_F16X3 = -1, 0, 1
+DD_FORM_NONE, DD_FORM_F32, DD_FORM_F16X3, DD_FORM_BF16X3 = -1, 0, 1, 2
 DD_CSR_F32, DD_CSR_F16 = 0, 1
 DD_PATH_REACHED, DD_PATH_STUCK, DD_PATH_MAX_STEPS = 0, 1, 2
 

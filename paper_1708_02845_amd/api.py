@@ -14,7 +14,7 @@ from . import _lib as L
 KINDS = {"tv": L.DD_TV, "kl": L.DD_KL, "chi2": L.DD_CHI2, "hellinger": L.DD_HELLINGER}
 KINDS.update({v: v for v in list(KINDS.values())})
 FORMS = {None: L.DD_FORM_NONE, "none": L.DD_FORM_NONE, "f32": L.DD_FORM_F32,
-         "f16x3": L.DD_FORM_F16X3}
+         "f16x3": L.DD_FORM_F16X3, "bf16x3": L.DD_FORM_BF16X3}
 CSR_VALUES = {"f32": L.DD_CSR_F32, "f16": L.DD_CSR_F16}
 PATH_STATUS = {L.DD_PATH_REACHED: "reached", L.DD_PATH_STUCK: "stuck",
                L.DD_PATH_MAX_STEPS: "max_steps"}

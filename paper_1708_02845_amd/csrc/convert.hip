@@ -141,7 +141,8 @@ __global__ __launch_bounds__(256) void trunc_fill_kernel(DenseView v, const doub
 }
 
 // l_xb = log P_xb - o_x with o_x = log max_b P_xb (natural log, FP64 then
-// rounded): FP32, or an FP16 hi + lo split, written in the tiled layout
+// rounded): FP32, or an FP16 (form 1) or BF16 (form 2) hi + lo split, written
+// in the tiled layout
 // of the contraction operand (padding rows are zeroed by the caller).
 __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, int64_t lda,
                                                         float* l32, uint16_t* lhi, uint16_t* llo,
@@ -172,6 +173,11 @@ __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, i
     }
     if (form == 0) {
       l32[at] = (float)l;
+    } else if (form == 2) {
+      const __bf16 hi = (__bf16)(float)l;
+      const __bf16 lo = (__bf16)(float)(l - (double)(float)hi);
+      lhi[at] = __builtin_bit_cast(uint16_t, hi);
+      llo[at] = __builtin_bit_cast(uint16_t, lo);
     } else {
       const _Float16 hi = (_Float16)l;
       const _Float16 lo = (_Float16)(l - (double)hi);

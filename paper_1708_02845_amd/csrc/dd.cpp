@@ -210,7 +210,7 @@ size_t dense_bytes(int64_t N, int64_t B, int is_f64, const dd_load_opts& o) {
   const int64_t lda = (B + 63) & ~int64_t(63);
   size_t b = (size_t)(N * ld * 4) + (size_t)N * 8;
   if (is_f64) b += (size_t)(N * B * 8);
-  if (o.gemm_form == DD_FORM_F32 || o.gemm_form == DD_FORM_F16X3)
+  if (o.gemm_form == DD_FORM_F32 || o.gemm_form == DD_FORM_F16X3 || o.gemm_form == DD_FORM_BF16X3)
     b += (size_t)(dd::gemm_rows_padded(N) * lda * 4) + (size_t)N * 4;
   return b;
 }
@@ -328,11 +328,21 @@ dd_error_bound field_bound(const dd_kernel* k, int kind, int32_t t) {
 dd_error_bound gemm_bound(const dd_kernel* k, int32_t t) {
   const double H = std::fabs(k->H_host[t]);
   const double W = k->W_host[t];
+  // BF16X3: hi+lo of l and of q each within 2^-16 relative, the dropped
+  // lo*lo product 2^-16: 3 x 2^-16 relative per term on top of the
+  // accumulation (F16X3's terms are 2^-22 and inside c).
   const double c = k->gemm_form == DD_FORM_F32 ? 35.0 : 42.0;
+  const double split = k->gemm_form == DD_FORM_BF16X3 ? 3.0 * std::ldexp(1.0, -16) : 0.0;
   dd_error_bound b;
-  b.rel = (c + 1.0) * kU;
-  b.abs = c * kU * (H + std::max(0.0, k->omax) * W) + (k->is_f64 ? kU * (W + 2.0 * H) : 0.0);
+  b.rel = (c + 1.0) * kU + split;
+  b.abs = (c * kU + split) * (H + std::max(0.0, k->omax) * W) +
+          (k->is_f64 ? kU * (W + 2.0 * H) : 0.0);
   if (k->gemm_form == DD_FORM_F16X3) b.abs += std::ldexp(1.0, -39) * (double)k->B * 88.0;
+  // BF16 subnormal floors: a lo part below 2^-126 (if flushed) loses under
+  // 2^-126 times the other operand (|l| <= 104 + max(0, o_max), q <= W_t) per
+  // entry
+  if (k->gemm_form == DD_FORM_BF16X3)
+    b.abs += std::ldexp(1.0, -125) * (double)k->B * (104.0 + std::max(0.0, k->omax) + W);
   b.abs *= 2.0;
   b.rel *= 2.0;
   return b;
@@ -560,7 +570,8 @@ dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P,
   if (N <= 0 || B <= 0) return fail(DD_EINVAL, "N=%d B=%d must be positive", N, B);
   if (B > kMaxB) return fail(DD_EINVAL, "B=%d exceeds the supported %d columns", B, kMaxB);
   const dd_load_opts o = opts ? *opts : default_opts();
-  if (o.gemm_form != DD_FORM_NONE && o.gemm_form != DD_FORM_F32 && o.gemm_form != DD_FORM_F16X3)
+  if (o.gemm_form != DD_FORM_NONE && o.gemm_form != DD_FORM_F32 && o.gemm_form != DD_FORM_F16X3 &&
+      o.gemm_form != DD_FORM_BF16X3)
     return fail(DD_EINVAL, "unknown gemm_form %d", o.gemm_form);
   if (!(o.tau >= 0.0) || !std::isfinite(o.tau) || o.tau > 1.0)
     return fail(DD_EINVAL, "tau must be in [0, 1]");
@@ -686,7 +697,7 @@ dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P,
         e = k->L32.alloc(4 * elems);
         if (!e) e = hipMemset(k->L32.p, 0, 4 * elems);
       }
-      if (!e && o.gemm_form == DD_FORM_F16X3) {
+      if (!e && o.gemm_form != DD_FORM_F32) {
         e = k->Lhi.alloc(2 * elems);
         if (!e) e = k->Llo.alloc(2 * elems);
         if (!e) e = hipMemset(k->Lhi.p, 0, 2 * elems);

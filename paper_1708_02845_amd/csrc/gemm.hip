@@ -23,6 +23,8 @@
 //   F16X3  l = l_hi + l_lo and p*s_t = q_hi + q_lo in FP16 (s_t a power of two
 //          putting max q at 2^13..2^14), three products l_hi q_hi + l_hi q_lo
 //          + l_lo q_hi on v_mfma_f32_32x32x16_f16, divided by s_t at the end.
+//   BF16X3 the same split in BF16 (no scale: BF16 has the FP32 range) on
+//          v_mfma_f32_32x32x16_bf16; 8 + 8 significant bits per operand.
 //
 // Both forms carry the FP32 accumulators into FP64 after every K-chunk of 64,
 // so the FP32 accumulation error is that of 64-term partial sums; H_t, W_t and
@@ -42,6 +44,7 @@
 namespace dd {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bhalf8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 // Register arrays use native vector types: arrays of HIP's struct vector
 // types are not promoted to registers and end up in scratch memory.
@@ -55,7 +58,7 @@ static_assert(GROWS == kGemmRows, "a workgroup owns one row tile of the operand"
 
 struct BatchOperand {
   float* b32;        // [Tpad][lda] FP32 targets (F32)
-  uint16_t* bhi;     // [Tpad][lda] FP16 bits (F16X3)
+  uint16_t* bhi;     // [Tpad][lda] FP16 / BF16 bits (F16X3 / BF16X3)
   uint16_t* blo;
   double* H;         // [Tpad]
   double* W;         // [Tpad]
@@ -156,6 +159,11 @@ __global__ __launch_bounds__(256) void batch_target_prep(DenseView dv, GemmView 
       p = dv.P64 ? (float)dv.P64[(int64_t)t * dv.B + k] : dv.P[(int64_t)t * dv.ld + k];
     if (gv.form == 0) {
       o.b32[(int64_t)j * gv.lda + k] = p;
+    } else if (gv.form == 2) {
+      const __bf16 qh = (__bf16)p;
+      const __bf16 ql = (__bf16)(p - (float)qh);
+      o.bhi[(int64_t)j * gv.lda + k] = __builtin_bit_cast(uint16_t, qh);
+      o.blo[(int64_t)j * gv.lda + k] = __builtin_bit_cast(uint16_t, ql);
     } else {
       const float q = p * s;                    // exact: s is a power of two
       const _Float16 qh = (_Float16)q;
@@ -202,9 +210,29 @@ __device__ __forceinline__ void write_fields(const GemmView& gv, const BatchOper
   }
 }
 
-template <int NT>
-__global__ __launch_bounds__(256, 2) void kl_gemm_f16x3(GemmView gv, BatchOperand o, int32_t T,
-                                                     int32_t groups, float* __restrict__ out) {
+// The three products of one K step of 16 (FP16 or BF16 operands).
+template <bool BF>
+__device__ __forceinline__ floatx16 split3(u32x4 ah, u32x4 al, u32x4 bh, u32x4 bl, floatx16 c) {
+  if constexpr (BF) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bhalf8, ah),
+                                                __builtin_bit_cast(bhalf8, bh), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bhalf8, ah),
+                                                __builtin_bit_cast(bhalf8, bl), c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bhalf8, al),
+                                                   __builtin_bit_cast(bhalf8, bh), c, 0, 0, 0);
+  } else {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, ah),
+                                               __builtin_bit_cast(half8, bh), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, ah),
+                                               __builtin_bit_cast(half8, bl), c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, al),
+                                                  __builtin_bit_cast(half8, bh), c, 0, 0, 0);
+  }
+}
+
+template <int NT, bool BF>
+__device__ __forceinline__ void gemm_split_body(GemmView gv, BatchOperand o, int32_t T,
+                                                int32_t groups, float* __restrict__ out) {
   int rb, grp;
   block_tile(groups, rb, grp);
   if ((int64_t)rb * GROWS >= gv.N) return;   // padding of the grid to whole XCD rounds
@@ -310,15 +338,11 @@ __global__ __launch_bounds__(256, 2) void kl_gemm_f16x3(GemmView gv, BatchOperan
     if (c < nchunks) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const half8 a_h = __builtin_bit_cast(half8, sh[j]);
-        const half8 a_l = __builtin_bit_cast(half8, sl[j]);
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-          const half8 b_h = *reinterpret_cast<const half8*>(&sbh[n * 32 + r][h * 32 + j * 8]);
-          const half8 b_l = *reinterpret_cast<const half8*>(&sbl[n * 32 + r][h * 32 + j * 8]);
-          acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_h, b_h, acc[n], 0, 0, 0);
-          acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_h, b_l, acc[n], 0, 0, 0);
-          acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_l, b_h, acc[n], 0, 0, 0);
+          const u32x4 b_h = *reinterpret_cast<const u32x4*>(&sbh[n * 32 + r][h * 32 + j * 8]);
+          const u32x4 b_l = *reinterpret_cast<const u32x4*>(&sbl[n * 32 + r][h * 32 + j * 8]);
+          acc[n] = split3<BF>(sh[j], sl[j], b_h, b_l, acc[n]);
         }
         // keep the B fragments of one K step live at a time (register budget)
         __builtin_amdgcn_sched_barrier(0);
@@ -343,6 +367,18 @@ __global__ __launch_bounds__(256, 2) void kl_gemm_f16x3(GemmView gv, BatchOperan
   }
   __syncthreads();   // every wave is done with the staged target tiles
   write_fields<NT>(gv, o, T, tbase, row0, lane, accd, reinterpret_cast<float*>(lds), out);
+}
+
+template <int NT>
+__global__ __launch_bounds__(256, 2) void kl_gemm_f16x3(GemmView gv, BatchOperand o, int32_t T,
+                                                     int32_t groups, float* __restrict__ out) {
+  gemm_split_body<NT, false>(gv, o, T, groups, out);
+}
+
+template <int NT>
+__global__ __launch_bounds__(256, 2) void kl_gemm_bf16x3(GemmView gv, BatchOperand o, int32_t T,
+                                                      int32_t groups, float* __restrict__ out) {
+  gemm_split_body<NT, true>(gv, o, T, groups, out);
 }
 
 template <int NT>
@@ -449,6 +485,11 @@ hipError_t launch_batch_kl(DenseView dv, GemmView gv, TargetList tl, int32_t T, 
       hipLaunchKernelGGL(kl_gemm_f32<1>, grid, dim3(256), 0, s, gv, o, T, groups, out);
     else
       hipLaunchKernelGGL(kl_gemm_f32<2>, grid, dim3(256), 0, s, gv, o, T, groups, out);
+  } else if (gv.form == 2) {
+    if (Tpad == 32)
+      hipLaunchKernelGGL(kl_gemm_bf16x3<1>, grid, dim3(256), 0, s, gv, o, T, groups, out);
+    else
+      hipLaunchKernelGGL(kl_gemm_bf16x3<2>, grid, dim3(256), 0, s, gv, o, T, groups, out);
   } else {
     if (Tpad == 32)
       hipLaunchKernelGGL(kl_gemm_f16x3<1>, grid, dim3(256), 0, s, gv, o, T, groups, out);

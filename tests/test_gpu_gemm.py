@@ -11,8 +11,10 @@ from workloads.seeds import targets_sources
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-5
-FORMS = ["f32", "f16x3"]
+FORMS = ["f32", "f16x3", "bf16x3"]
+# normwise tolerance per form: BF16 carries 8 + 8 significant bits per operand
+# (about 2^-17 relative per product), FP16 11 + 11 with a scaled B operand
+TOL = {"f32": 1e-5, "f16x3": 1e-5, "bf16x3": 1e-4}
 
 
 @pytest.fixture(scope="module")
@@ -43,7 +45,7 @@ def test_batched_kl_matches_oracle(grid, gemm_kernel, T):
     picks = {0, T // 2, T - 1} | {i for g0 in range(64, T, 64) for i in (g0 - 1, g0)}
     for i in sorted(picks):
         ref = dv.kl_field(P64, int(ts[i]))
-        assert normwise(D[i], ref) <= TOL, (form, T, i)
+        assert normwise(D[i], ref) <= TOL[form], (form, T, i)
         assert within_bound(D[i], ref, bounds[i]), (form, T, i)
 
 
@@ -91,7 +93,7 @@ def test_unit_disk_fp64_input(gpu_ctx, form):
         D = D.cpu().numpy()
         for i in (0, 7, 15):
             ref = dv.kl_field(inst.P, int(ts[i]))
-            assert normwise(D[i], ref) <= TOL
+            assert normwise(D[i], ref) <= TOL[form]
             assert within_bound(D[i], ref, bounds[i])
     finally:
         k.free()
@@ -122,7 +124,7 @@ def test_grid257_batch_of_256(gpu_ctx, form):
         P64 = P.astype(np.float64)
         for i in (0, 63, 64, 191, 255):
             ref = dv.kl_field(P64, int(ts[i]))
-            assert normwise(D[i], ref) <= TOL
+            assert normwise(D[i], ref) <= TOL[form]
             assert within_bound(D[i], ref, bounds[i])
     finally:
         k.free()
