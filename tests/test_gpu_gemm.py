@@ -128,3 +128,31 @@ def test_grid257_batch_of_256(gpu_ctx, form):
             assert within_bound(D[i], ref, bounds[i])
     finally:
         k.free()
+
+
+@pytest.mark.parametrize("form", ["f16x3", "bf16x3"])
+def test_ragged_rows_every_target(gpu_ctx, form):
+    """An odd number of 128-row operand tiles with a ragged last tile, batches
+    of 65, 128 and 200 targets (ragged and whole target groups): every target
+    against the oracle, and fields equal to those computed alone."""
+    from paper_1708_02845_amd import Kernel
+    g = grid_domain(61, 2, (0.1, 0.3), seed_id=51)
+    P = g.poisson_kernel().astype(np.float32)
+    k = Kernel.load_dense(gpu_ctx, P, gemm_form=form)
+    try:
+        assert (-(-k.N // 128)) % 2 == 1 and k.N % 128 != 0
+        P64 = P.astype(np.float64)
+        for T in (65, 128, 200):
+            ts = targets_sources(60 + T, g.N, T)[0]
+            ts[-1] = g.N - 1
+            D, bounds = k.batch_fields(ts, "kl")
+            D = D.cpu().numpy()
+            for i in range(T):
+                ref = dv.kl_field(P64, int(ts[i]))
+                assert normwise(D[i], ref) <= TOL[form], (T, i)
+                assert within_bound(D[i], ref, bounds[i]), (T, i)
+            for i in (0, 64, T - 1):
+                alone = k.batch_fields([int(ts[i])], "kl")[0].cpu().numpy()[0]
+                assert np.array_equal(alone, D[i]), (T, i)
+    finally:
+        k.free()
