@@ -251,6 +251,8 @@ def run_grid1025(args):
                            adjacency=(g.adj_ptr, g.adj_idx))
     res.update(csr_batch_rows(kc, ts_all, f"abs{tau_abs:g}"))
     kc.free()
+    torch.cuda.empty_cache()
+    res["a0_grid_poisson_kernel"] = grid_poisson_row(ctx, g, P, build_s)
     ctx.close()
     main_row = res["a5_batched_kl_f16x3_T64"]
     out = {"metric": METRIC, "value": main_row["entries_per_s"], "unit": "entries/s",
@@ -266,6 +268,42 @@ def run_grid1025(args):
                         "traffic": measured_traffic("grid1025_T64", "kl_gemm_f16x3")},
            "rows": res}
     print(json.dumps(out), flush=True)
+
+
+def grid_poisson_row(ctx, g, P_host, build_s, batch=1024):
+    """The whole P_IB of a grid domain solved on the device (FP64 multigrid-
+    preconditioned CG, FP32 output), timed against the host build of the same
+    matrix, and compared with it on sampled rows."""
+    import torch
+    out = torch.empty((g.N, g.K), dtype=torch.float32, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = ctx.grid_poisson_kernel(g.node_type(), out=out, tol=1e-12, batch=batch)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    # algorithmic bytes of one iteration over a batch: 14 passes over the fine
+    # level (product 2, update 6, restriction 1, prolongation and smoothing 2,
+    # direction 3), 4 over each coarser level
+    G, levels = g.G, []
+    Gl = G
+    for _ in range(st["levels"]):
+        levels.append(Gl)
+        Gl = Gl // 2 + 1
+    per_iter = 8 * batch * (14 * G * G + sum(4 * x * x for x in levels[1:]))
+    byts = st["total_iterations"] * per_iter + 4 * g.N * g.K
+    rows = np.random.default_rng(5).choice(g.N, size=64, replace=False)
+    diff = float(np.abs(out[torch.as_tensor(rows, device="cuda:0")].cpu().numpy() -
+                        np.asarray(P_host[rows, :g.K], dtype=np.float32)).max())
+    del out
+    torch.cuda.empty_cache()
+    gbs_ = byts / secs / 1e9
+    log(f"grid Poisson kernel on the device: {secs:.2f} s, {st}, max |diff| {diff:.2e}")
+    return {"seconds": round(secs, 3), "host_build_s": round(build_s, 1),
+            "speedup_vs_host": round(build_s / secs, 2), "iterations_max": st["iterations"],
+            "iterations_total": st["total_iterations"], "batches": st["batches"],
+            "levels": st["levels"], "max_rel_residual": st["max_rel_residual"],
+            "alg_bytes": byts, "GB/s": round(gbs_, 1), "hbm_frac": round(gbs_ / HBM_PEAK_GBS, 4),
+            "max_abs_diff_vs_host_64_rows": diff}
 
 
 def resolve_census(k, targets, kind, cls, counts):

@@ -49,7 +49,9 @@ typedef enum {
   DD_EINVAL = 1,   /* bad argument or bad input data; nothing written */
   DD_ENOMEM = 2,   /* the HBM footprint does not fit in free device memory */
   DD_EDEVICE = 3,  /* a HIP runtime call failed */
-  DD_ESTATE = 4    /* freed, foreign or mismatched handle */
+  DD_ESTATE = 4,   /* freed, foreign or mismatched handle */
+  DD_ENOCONV = 5   /* an iterative solve stopped at its iteration cap above its
+                      tolerance; outputs hold the last iterate */
 } dd_status;
 
 typedef enum {
@@ -332,6 +334,49 @@ dd_status dd_resolve_minima(dd_kernel* k, int32_t T, const int32_t* targets, int
 dd_status dd_plan_path(dd_kernel* k, int32_t source, int32_t target, int32_t kind,
                        int32_t max_steps, int32_t* path_host, int32_t* len,
                        int32_t* status, int32_t* rechecks, void* stream);
+
+/* Statistics of dd_grid_poisson_kernel. */
+typedef struct {
+  int32_t iterations;        /* CG iterations of the slowest column batch */
+  int32_t batches;           /* column batches solved */
+  int32_t levels;            /* multigrid levels */
+  int32_t total_iterations;  /* CG iterations summed over the batches */
+  double max_rel_residual;   /* max over columns of ||r|| / ||b|| at exit */
+} dd_grid_solve_stats;
+
+/* Poisson kernel P_IB of a grid domain computed on the device (the
+ * preprocessing of Section IV, eqs. 32-33): column b is the discrete harmonic
+ * function on the interior vertices with boundary values the indicator of
+ * boundary vertex b.  On the right-triangle grid the cotangent Laplacian is
+ * the five-point stencil, so each column solves
+ *   4 u_v - sum_{interior n ~ v} u_n = #{boundary n ~ v : n = b}.
+ *   G          vertices per grid side, 3 <= G <= 46340.
+ *   node_type  host [G*G] uint8, vertex (i, j) at index j*G + i: 0 = not in
+ *              the domain, 1 = interior, 2 = boundary.  Interior vertices
+ *              may not lie on the grid's edge, and each of their four axis
+ *              neighbours must be interior or boundary.  Rows of P are the
+ *              interior vertices and columns the boundary vertices, each in
+ *              ascending index order (N and K their counts).
+ *   col_begin, ncols  the columns [col_begin, col_begin + ncols) of P_IB to
+ *              compute (0 <= col_begin, 1 <= ncols, col_begin + ncols <= K).
+ *   P32        nullable device [N][ld32] FP32 (ld32 >= ncols): column
+ *              col_begin + c of P_IB is written at position c of each row.
+ *   P64        nullable device [N][ld64] FP64, likewise; at least one of the two.
+ *              Entries are max(u, 0); other columns of the rows are untouched.
+ *   tol        relative residual ||b - A u|| / ||b|| each column must reach.
+ *   max_iter   conjugate-gradient iteration cap per column batch (>= 1).
+ *   batch      columns solved together (a multiple of 64), or 0 to choose from
+ *              free device memory.
+ *   stats      nullable host output.
+ * Conjugate gradients with a geometric multigrid preconditioner in FP64; the
+ * library allocates its workspace (about 5 x 8 x G^2 x batch bytes) for the
+ * call and frees it on return.  DD_ENOCONV if a column is above tol at the
+ * cap (the outputs then hold the last iterate), DD_ENOMEM if the workspace
+ * for 64 columns does not fit.  Synchronous on `stream`. */
+dd_status dd_grid_poisson_kernel(dd_ctx* ctx, int32_t G, const uint8_t* node_type,
+                                 int32_t col_begin, int32_t ncols, float* P32, int64_t ld32,
+                                 double* P64, int64_t ld64, double tol, int32_t max_iter,
+                                 int32_t batch, dd_grid_solve_stats* stats, void* stream);
 
 /* Release a handle and its device memory (waits for the device first). */
 dd_status dd_free_kernel(dd_kernel* k);

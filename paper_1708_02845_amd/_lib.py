@@ -6,13 +6,14 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdd.so")
 
-DD_OK, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ESTATE = range(5)
+DD_OK, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ESTATE, DD_ENOCONV = range(6)
 DD_TV, DD_KL, DD_CHI2, DD_HELLINGER = 0, 1, 2, 3
 DD_FORM_NONE, DD_FORM_F32, DD_FORM_F16X3, DD_FORM_BF16X3 = -1, 0, 1, 2
 DD_CSR_F32, DD_CSR_F16 = 0, 1
 DD_PATH_REACHED, DD_PATH_STUCK, DD_PATH_MAX_STEPS = 0, 1, 2
 
-STATUS_NAMES = {0: "DD_OK", 1: "DD_EINVAL", 2: "DD_ENOMEM", 3: "DD_EDEVICE", 4: "DD_ESTATE"}
+STATUS_NAMES = {0: "DD_OK", 1: "DD_EINVAL", 2: "DD_ENOMEM", 3: "DD_EDEVICE", 4: "DD_ESTATE",
+                5: "DD_ENOCONV"}
 
 
 class DDError(RuntimeError):
@@ -32,6 +33,11 @@ class dd_load_opts(C.Structure):
 
 class dd_error_bound(C.Structure):
     _fields_ = [("abs", C.c_double), ("rel", C.c_double)]
+
+
+class dd_grid_solve_stats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("batches", C.c_int32), ("levels", C.c_int32),
+                ("total_iterations", C.c_int32), ("max_rel_residual", C.c_double)]
 
 
 class dd_kernel_info(C.Structure):
@@ -78,6 +84,10 @@ EXPORTS = {
     "dd_trace_paths_triangles": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dd_grid_poisson_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
+                                         C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                         C.c_double, C.c_int32, C.c_int32,
+                                         C.POINTER(dd_grid_solve_stats), C.c_void_p]),
     "dd_free_kernel": (C.c_int, [C.c_void_p]),
     "dd_last_error": (C.c_char_p, []),
 }

@@ -85,6 +85,41 @@ class Context:
             L.check(self._lib.dd_destroy(self._h))
             self._h = None
 
+    def grid_poisson_kernel(self, node_type, cols=None, tol=1e-12, max_iter=1000, batch=0,
+                            dtype="f32", out=None, stream=None):
+        """Poisson kernel P_IB of a grid domain, computed on the device.
+
+        node_type: [G, G] or [G*G] uint8 (0 outside, 1 interior, 2 boundary;
+        vertex (i, j) at j*G + i).  cols: (begin, count) of the boundary
+        columns to compute (all by default).  dtype "f32" or "f64".  out:
+        optional device tensor [N, >= count] of that dtype.  Returns
+        (P tensor [N, count] view, stats dict)."""
+        torch = _torch()
+        nt = np.ascontiguousarray(np.asarray(node_type, dtype=np.uint8).reshape(-1))
+        G = int(round(len(nt) ** 0.5))
+        if G * G != len(nt):
+            raise ValueError("node_type is not a square grid")
+        N = int((nt == 1).sum())
+        K = int((nt == 2).sum())
+        begin, count = (0, K) if cols is None else (int(cols[0]), int(cols[1]))
+        tdt = {"f32": torch.float32, "f64": torch.float64}[dtype]
+        if out is None:
+            out = torch.empty((N, max(count, 1)), dtype=tdt, device=f"cuda:{self.device}")
+        if out.dtype != tdt or out.dim() != 2 or out.shape[0] != N or out.stride(1) != 1:
+            raise ValueError("out must be a row-major [N, >= count] tensor of the dtype")
+        st = L.dd_grid_solve_stats()
+        ptr = C.c_void_p(out.data_ptr())
+        ld = out.stride(0)
+        L.check(self._lib.dd_grid_poisson_kernel(
+            self._h, G, nt.ctypes.data_as(C.c_void_p), begin, count,
+            ptr if dtype == "f32" else None, ld if dtype == "f32" else 0,
+            ptr if dtype == "f64" else None, ld if dtype == "f64" else 0,
+            float(tol), int(max_iter), int(batch), C.byref(st), _stream_handle(stream)))
+        stats = {"iterations": st.iterations, "batches": st.batches, "levels": st.levels,
+                 "total_iterations": st.total_iterations,
+                 "max_rel_residual": st.max_rel_residual}
+        return out[:, :count], stats
+
 
 class Kernel:
     """A resident Poisson-kernel matrix (dense or truncated) on the device."""

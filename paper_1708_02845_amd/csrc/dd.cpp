@@ -1317,6 +1317,69 @@ dd_status dd_plan_path(dd_kernel* k, int32_t source, int32_t target, int32_t kin
   return DD_OK;
 }
 
+dd_status dd_grid_poisson_kernel(dd_ctx* ctx, int32_t G, const uint8_t* node_type,
+                                 int32_t col_begin, int32_t ncols, float* P32, int64_t ld32,
+                                 double* P64, int64_t ld64, double tol, int32_t max_iter,
+                                 int32_t batch, dd_grid_solve_stats* stats, void* stream) {
+  if (!ctx_ok(ctx)) return fail(DD_ESTATE, "not a live context");
+  if (G < 3 || G > 46340) return fail(DD_EINVAL, "G=%d outside [3, 46340]", G);
+  if (!node_type) return fail(DD_EINVAL, "node_type is null");
+  if (!P32 && !P64) return fail(DD_EINVAL, "no output (P32 and P64 both null)");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(DD_EINVAL, "tol must be positive");
+  if (max_iter < 1) return fail(DD_EINVAL, "max_iter must be >= 1");
+  if (batch < 0 || batch % 64 != 0) return fail(DD_EINVAL, "batch %d is not a multiple of 64", batch);
+  int64_t n_int = 0, n_bnd = 0;
+  for (int64_t j = 0; j < G; ++j)
+    for (int64_t i = 0; i < G; ++i) {
+      const uint8_t t = node_type[j * G + i];
+      if (t > 2) return fail(DD_EINVAL, "node_type %d at (%lld, %lld)", t, (long long)i, (long long)j);
+      if (t == 2) ++n_bnd;
+      if (t != 1) continue;
+      ++n_int;
+      if (i == 0 || j == 0 || i == G - 1 || j == G - 1)
+        return fail(DD_EINVAL, "interior vertex (%lld, %lld) on the grid edge", (long long)i,
+                    (long long)j);
+      const int64_t g = j * G + i;
+      if (!node_type[g - 1] || !node_type[g + 1] || !node_type[g - G] || !node_type[g + G])
+        return fail(DD_EINVAL, "interior vertex (%lld, %lld) has a neighbour outside the domain",
+                    (long long)i, (long long)j);
+    }
+  if (n_int == 0 || n_bnd == 0) return fail(DD_EINVAL, "no interior or no boundary vertex");
+  if (col_begin < 0 || ncols < 1 || (int64_t)col_begin + ncols > n_bnd)
+    return fail(DD_EINVAL, "columns [%d, %d + %d) outside the %lld boundary vertices", col_begin,
+                col_begin, ncols, (long long)n_bnd);
+  if (P32 && ld32 < ncols) return fail(DD_EINVAL, "ld32=%lld < ncols=%d", (long long)ld32, ncols);
+  if (P64 && ld64 < ncols) return fail(DD_EINVAL, "ld64=%lld < ncols=%d", (long long)ld64, ncols);
+  HIP_OR(hipSetDevice(ctx->device));
+  size_t free_b = 0, total_b = 0;
+  HIP_OR(hipMemGetInfo(&free_b, &total_b));
+  int32_t C = batch;
+  if (C == 0) {
+    // the widest batch up to 1024 columns whose workspace takes at most
+    // 90% of free memory
+    C = std::min<int32_t>(1024, (ncols + 63) / 64 * 64);
+    while (C > 64 && dd::grid_poisson_workspace(G, C) > free_b / 10 * 9) C -= 64;
+  }
+  if (dd::grid_poisson_workspace(G, C) > free_b)
+    return fail(DD_ENOMEM, "a batch of %d columns needs %zu bytes, %zu free", C,
+                dd::grid_poisson_workspace(G, C), free_b);
+  dd::GridSolveStats st{};
+  const hipError_t e = dd::grid_poisson(G, node_type, col_begin, ncols, C, tol, max_iter, P32,
+                                        ld32, P64, ld64, &st, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(DD_EDEVICE, "grid Poisson solve: %s", hipGetErrorString(e));
+  if (stats) {
+    stats->iterations = st.iterations;
+    stats->batches = st.batches;
+    stats->levels = st.levels;
+    stats->total_iterations = st.total_iterations;
+    stats->max_rel_residual = st.max_rel_residual;
+  }
+  if (!st.converged)
+    return fail(DD_ENOCONV, "relative residual %.3e above tol %.3e after %d iterations",
+                st.max_rel_residual, tol, st.iterations);
+  return DD_OK;
+}
+
 dd_status dd_free_kernel(dd_kernel* k) {
   if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
   // work in flight may still read the handle's memory: wait for it, then free

@@ -96,6 +96,20 @@ struct TargetList {
 };
 size_t batch_kl_workspace(GemmView gv, int32_t T);
 
+// ---- Poisson kernel of a grid domain (poisson.hip) ----
+struct GridSolveStats {
+  int32_t iterations, batches, levels, total_iterations;
+  int32_t converged;   // every column reached rr <= tol^2 bb
+  double max_rel_residual;
+};
+int32_t grid_levels(int32_t G);
+size_t grid_poisson_workspace(int32_t G, int32_t C);
+// Columns [col_begin, col_begin + ncols) of P_IB, C columns per batch (a
+// multiple of 64); node_type as in dd_grid_poisson_kernel, already validated.
+hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, int32_t ncols,
+                        int32_t C, double tol, int32_t max_iter, float* P32, int64_t ld32,
+                        double* P64, int64_t ld64, GridSolveStats* st, hipStream_t s);
+
 // Truncated fields of many targets in one pass over the stored rows
 // (csr_batch.hip).  Up to kMaxBatch targets per launch; ws holds
 // csr_batch_workspace(v, T) bytes.

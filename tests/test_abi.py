@@ -47,6 +47,8 @@ def test_null_handles_are_rejected_without_touching_the_device(lib):
     assert lib.dd_distance_field(None, 0, 0, None, C.byref(b), None) == L.DD_ESTATE
     assert b"not a live kernel" in lib.dd_last_error()
     assert lib.dd_free_kernel(None) == L.DD_ESTATE
+    assert lib.dd_grid_poisson_kernel(None, 9, None, 0, 1, None, 0, None, 0, 1e-12, 10, 0, None,
+                                      None) == L.DD_ESTATE
     assert lib.dd_destroy(None) == L.DD_ESTATE
     n = C.c_int32()
     assert lib.dd_plan_path(None, 0, 1, 0, 10, None, C.byref(n), C.byref(n), None, None) \
@@ -86,7 +88,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = {"dd_load_opts": L.dd_load_opts, "dd_error_bound": L.dd_error_bound,
-               "dd_kernel_info": L.dd_kernel_info, "dd_adjacency": L.dd_adjacency}
+               "dd_kernel_info": L.dd_kernel_info, "dd_adjacency": L.dd_adjacency,
+               "dd_grid_solve_stats": L.dd_grid_solve_stats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dd.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')

@@ -142,3 +142,27 @@ def test_grid_outer_corners_are_the_only_zero_columns(small_grid):
     zero = np.nonzero(P.max(axis=0) == 0)[0]
     G = g.G
     assert set(g.boundary[zero].tolist()) == {0, G - 1, G * (G - 1), G * G - 1}
+
+
+def test_poisson_kernel_of_square_matches_sine_series():
+    # Closed form of the discrete problem on the plain (G x G) square: with
+    # M = G - 1 and boundary vertex (m, 0) on the bottom edge, separation of
+    # variables in the five-point equations gives
+    #   u(i, j) = sum_k c_k sin(k pi i / M) sinh(mu_k (M - j)) / sinh(mu_k M),
+    #   cosh mu_k = 2 - cos(k pi / M),  c_k = (2 / M) sin(k pi m / M),
+    # the discrete sine series of the boundary indicator.  Pins the oracle's
+    # stencil, boundary coupling and solve against an independent formula.
+    G = 17
+    M = G - 1
+    g = grid_domain(G, 0, seed_id=0)
+    P = poisson.poisson_kernel(fem.cotan_laplacian(g.xy(), g.triangles), g.interior, g.boundary)
+    col = {int(b): c for c, b in enumerate(g.boundary)}
+    ii = g.interior % G
+    jj = g.interior // G
+    k = np.arange(1, M)
+    mu = np.arccosh(2.0 - np.cos(k * np.pi / M))
+    for m in (1, 5, 8, 15):
+        ck = (2.0 / M) * np.sin(k * np.pi * m / M)
+        u = (ck[None, :] * np.sin(np.outer(ii, k) * np.pi / M) *
+             np.sinh(np.outer(M - jj, mu)) / np.sinh(mu * M)[None, :]).sum(axis=1)
+        assert np.abs(P[:, col[m]] - u).max() < 1e-13, m

@@ -66,6 +66,13 @@ class GridDomain:
         f = loc[self.triangles]
         return f[(f >= 0).all(axis=1)], self.xy()[self.interior]
 
+    def node_type(self):
+        """uint8 [G*G]: 0 removed (inside an obstacle), 1 interior, 2 boundary."""
+        t = np.zeros(self.G * self.G, dtype=np.uint8)
+        t[self.interior] = 1
+        t[self.boundary] = 2
+        return t
+
     def poisson_kernel(self, dtype=np.float64, workers=None, progress=None):
         if self._P is None or self._P.dtype != dtype:
             self._P = harmonic_measure_5pt(self, dtype=dtype, workers=workers, progress=progress)
