@@ -206,7 +206,9 @@ __global__ __launch_bounds__(256) void pk_direction(double* __restrict__ p,
 
 // Restriction of the pre-smoothed residual: with e = W r (one damped Jacobi
 // sweep from zero) the residual is t = r - A e; rc[I] = sum of the bilinear
-// weights times t over the 3 x 3 fine vertices around 2I.
+// weights times t over the 3 x 3 fine vertices around 2I.  A wave walks
+// consecutive coarse vertices of a row, so the fine column 2I + 1 of one is
+// the column 2I' - 1 of the next: its three t values are carried over.
 __global__ __launch_bounds__(256) void pk_down(const double* __restrict__ r, const uint8_t* act,
                                                int32_t G, double* __restrict__ rc,
                                                const uint8_t* actc, int32_t Gc, int64_t C,
@@ -218,26 +220,35 @@ __global__ __launch_bounds__(256) void pk_down(const double* __restrict__ r, con
   const int64_t c = grp * 64 + (threadIdx.x & 63);
   const int64_t g0 = rb * kRowsPerBlock + (threadIdx.x >> 6) * kRowsPerWave;
   const int64_t up = (int64_t)G * C;
-  for (int k = 0; k < kRowsPerWave; ++k) {
+  auto t_at = [&](int64_t n) -> double {
+    if (!act[n]) return 0.0;
+    const int64_t o = n * C + c;
+    const double rn = r[o];
+    return rn - kW * (4.0 * rn - ((r[o - C] + r[o + C]) + (r[o - up] + r[o + up])));
+  };
+  double l0 = 0.0, l1 = 0.0, l2 = 0.0;   // t at column 2I - 1, rows 2J - 1, 2J, 2J + 1
+  bool carried = false;                  // l* hold the previous vertex's column 2I + 1
+  int64_t I = g0 % Gc, J = g0 / Gc;      // coordinates of gc, carried along
+  for (int k = 0; k < kRowsPerWave; ++k, I = I + 1 == Gc ? 0 : I + 1, J += I == 0) {
     const int64_t gc = g0 + k;
     if (gc >= nodes) break;
     double v = 0.0;
     if (actc[gc]) {
-      const int64_t I = gc % Gc, J = gc / Gc;
       const int64_t g = 2 * J * G + 2 * I;
-#pragma unroll
-      for (int dj = -1; dj <= 1; ++dj)
-#pragma unroll
-        for (int di = -1; di <= 1; ++di) {
-          const int64_t n = g + dj * (int64_t)G + di;
-          if (!act[n]) continue;
-          const int64_t o = n * C + c;
-          const double rn = r[o];
-          const double t =
-              rn - kW * (4.0 * rn - ((r[o - C] + r[o + C]) + (r[o - up] + r[o + up])));
-          const double w = (di == 0 ? 1.0 : 0.5) * (dj == 0 ? 1.0 : 0.5);
-          v += w * t;
-        }
+      if (!carried) {
+        l0 = t_at(g - 1 - G);
+        l1 = t_at(g - 1);
+        l2 = t_at(g - 1 + G);
+      }
+      const double m0 = t_at(g - G), m1 = t_at(g), m2 = t_at(g + G);
+      const double r0 = t_at(g + 1 - G), r1 = t_at(g + 1), r2 = t_at(g + 1 + G);
+      v = (m1 + 0.5 * ((m0 + m2) + (l1 + r1))) + 0.25 * ((l0 + l2) + (r0 + r2));
+      l0 = r0;
+      l1 = r1;
+      l2 = r2;
+      carried = true;
+    } else {
+      carried = false;
     }
     rc[gc * C + c] = v;
   }
@@ -245,7 +256,7 @@ __global__ __launch_bounds__(256) void pk_down(const double* __restrict__ r, con
 
 // Bilinear prolongation of the coarse correction ec at fine vertex (i, j).
 __device__ __forceinline__ double prolong(const double* __restrict__ ec, int32_t Gc, int64_t C,
-                                          int64_t c, int64_t i, int64_t j) {
+                                          int64_t c, int32_t i, int32_t j) {
   const int64_t i0 = i >> 1, j0 = j >> 1;
   const int64_t a = (j0 * Gc + i0) * C + c;
   const bool oi = i & 1, oj = j & 1;
@@ -270,23 +281,41 @@ __global__ __launch_bounds__(256) void pk_up(const double* __restrict__ r, const
   if (!block_of(nodes, groups, rb, grp)) return;
   const int64_t c = grp * 64 + (threadIdx.x & 63);
   const int64_t g0 = rb * kRowsPerBlock + (threadIdx.x >> 6) * kRowsPerWave;
-  auto e_at = [&](int64_t n) -> double {
+  // e at vertex n = (i, j); coordinates are carried along, not divided out
+  auto e_at = [&](int64_t n, int32_t i, int32_t j) -> double {
     if (!act[n]) return 0.0;
-    return kW * r[n * C + c] + prolong(ec, Gc, C, c, n % G, n / G);
+    return kW * r[n * C + c] + prolong(ec, Gc, C, c, i, j);
   };
+  // a window of e along the wave's vertices: e(g - 1), e(g), e(g + 1) (the
+  // vertices g +- 1 of an unknown g are its left and right neighbours)
   double acc = 0.0;
+  double e_m = 0.0, e_c = 0.0;
+  int32_t gi = 0, gj = 0;   // coordinates of g
+  if (g0 < nodes) {
+    gi = (int32_t)(g0 % G);
+    gj = (int32_t)(g0 / G);
+    // g0 - 1 is never an unknown when g0 starts a grid row (an edge vertex)
+    e_m = gi > 0 ? e_at(g0 - 1, gi - 1, gj) : 0.0;
+    e_c = e_at(g0, gi, gj);
+  }
   for (int k = 0; k < kRowsPerWave; ++k) {
     const int64_t g = g0 + k;
     if (g >= nodes) break;
+    const bool wrap = gi + 1 == G;
+    const int32_t ni = wrap ? 0 : gi + 1, nj = wrap ? gj + 1 : gj;
+    const double e_p = g + 1 < nodes ? e_at(g + 1, ni, nj) : 0.0;
     double v = 0.0;
     if (act[g]) {
       const double rg = r[g * C + c];
-      const double eg = e_at(g);
-      const double s = (e_at(g - 1) + e_at(g + 1)) + (e_at(g - G) + e_at(g + G));
-      v = eg + kW * (rg - (4.0 * eg - s));
+      const double s = (e_m + e_p) + (e_at(g - G, gi, gj - 1) + e_at(g + G, gi, gj + 1));
+      v = e_c + kW * (rg - (4.0 * e_c - s));
       acc += rg * v;
     }
     out[g * C + c] = v;
+    e_m = e_c;
+    e_c = e_p;
+    gi = ni;
+    gj = nj;
   }
   if (part) block_partial(acc, part, rb, C, c);
 }
