@@ -220,11 +220,18 @@ __global__ __launch_bounds__(256) void pk_down(const double* __restrict__ r, con
   const int64_t c = grp * 64 + (threadIdx.x & 63);
   const int64_t g0 = rb * kRowsPerBlock + (threadIdx.x >> 6) * kRowsPerWave;
   const int64_t up = (int64_t)G * C;
+  // t at a fine vertex n around an unknown centre.  n may lie on the grid's
+  // edge (then it is not an unknown), where a neighbour can be past the
+  // grid: a vertex that is not an unknown reads itself in place of its
+  // neighbours, so every load is in the grid and none needs a branch (the
+  // vertex type only selects)
   auto t_at = [&](int64_t n) -> double {
-    if (!act[n]) return 0.0;
+    const bool a = act[n];
     const int64_t o = n * C + c;
+    const int64_t dh = a ? C : 0, dv = a ? up : 0;
     const double rn = r[o];
-    return rn - kW * (4.0 * rn - ((r[o - C] + r[o + C]) + (r[o - up] + r[o + up])));
+    const double t = rn - kW * (4.0 * rn - ((r[o - dh] + r[o + dh]) + (r[o - dv] + r[o + dv])));
+    return a ? t : 0.0;
   };
   double l0 = 0.0, l1 = 0.0, l2 = 0.0;   // t at column 2I - 1, rows 2J - 1, 2J, 2J + 1
   bool carried = false;                  // l* hold the previous vertex's column 2I + 1
@@ -281,10 +288,13 @@ __global__ __launch_bounds__(256) void pk_up(const double* __restrict__ r, const
   if (!block_of(nodes, groups, rb, grp)) return;
   const int64_t c = grp * 64 + (threadIdx.x & 63);
   const int64_t g0 = rb * kRowsPerBlock + (threadIdx.x >> 6) * kRowsPerWave;
-  // e at vertex n = (i, j); coordinates are carried along, not divided out
+  // e at vertex n = (i, j); coordinates are carried along, not divided out.
+  // The loads need no guard: r[n] is in the grid, and the prolongation of
+  // any fine vertex reads coarse vertices (i+1)/2 <= Gc - 1, (j+1)/2 <= Gc - 1
+  // (the vertex type only selects)
   auto e_at = [&](int64_t n, int32_t i, int32_t j) -> double {
-    if (!act[n]) return 0.0;
-    return kW * r[n * C + c] + prolong(ec, Gc, C, c, i, j);
+    const double e = kW * r[n * C + c] + prolong(ec, Gc, C, c, i, j);
+    return act[n] ? e : 0.0;
   };
   // a window of e along the wave's vertices: e(g - 1), e(g), e(g + 1) (the
   // vertices g +- 1 of an unknown g are its left and right neighbours)
