@@ -244,6 +244,34 @@ def run_grid1025(args):
     res.update(csr_batch_rows(kc, ts_all, "tau1e-5_f16"))
     kc.free()
     torch.cuda.empty_cache()
+    # the same truncation with the floored log-kernel operand: KL_tau of 256
+    # targets as one f16x3 contraction
+    log(f"loading the tau={tau:g} truncation with the floored contraction operand")
+    kg = Kernel.load_dense(ctx, P, tau=tau, gemm_form="f16x3")
+    lda = (kg.B + 63) // 64 * 64
+    D = torch.empty((len(ts_all), kg.N), dtype=torch.float32, device="cuda:0")
+    kg.batch_fields(ts_all, "kl", out=D)
+    torch.cuda.synchronize()
+    reps = 5
+    a.record()
+    for _ in range(reps):
+        kg.batch_fields(ts_all, "kl", out=D)
+    b.record()
+    torch.cuda.synchronize()
+    us = 1000.0 * a.elapsed_time(b) / reps
+    TT = len(ts_all)
+    flops = 2.0 * kg.N * kg.B * TT * 3
+    byts = kg.N * lda * 4 + TT * lda * 4 + TT * kg.N * 4 + kg.N * 4
+    tf = flops / (us * 1e-6) / 1e12
+    res[f"a4_trunc_kl_contraction_f16x3_tau{tau:g}_T{TT}"] = {
+        "avg_us": round(us, 1), "entries_per_s": kg.N * kg.B * TT / (us * 1e-6),
+        "alg_bytes": byts, "GB/s": round(gbs(byts, us), 1),
+        "hbm_frac": round(gbs(byts, us) / HBM_PEAK_GBS, 4), "mfma_TFLOP/s": round(tf, 1),
+        "mfma_frac": round(tf / MFMA_PEAK_TFLOPS["f16x3"], 4)}
+    log(f"floored KL contraction: {us:.0f} us for {TT} targets")
+    del D
+    kg.free()
+    torch.cuda.empty_cache()
     # second truncation point: an absolute threshold that keeps about 5% of the entries
     tau_abs = 4e-4
     log(f"loading the absolute tau={tau_abs:g} truncation")

@@ -116,7 +116,8 @@ typedef struct {
 } dd_adjacency;
 
 typedef struct {
-  int32_t gemm_form;     /* dd_form built for dd_batch_distance_fields with DD_KL */
+  int32_t gemm_form;     /* dd_form built for dd_batch_distance_fields with DD_KL; with
+                            tau > 0 the floored operand (dense loads, FP32 values only) */
   double tau;            /* > 0: keep only the truncation of P (CSR form); 0: dense */
   int32_t tau_relative;  /* 1: keep P_xb >= tau * max_b P_xb; 0: keep P_xb >= tau */
   int32_t validate;      /* 1: reject rows that are not probability vectors */
@@ -213,6 +214,12 @@ dd_status dd_distance_field(dd_kernel* k, int32_t target, int32_t kind, float* o
  *     KL_tau(x,t) = H_t - log(phi_x) W_t - sum_{b in S_x} P~_tb log(P~_xb / phi_x)
  * (Q_x = sum_{b in S_x} P~_xb; the truncated fields of dd_load_kernel_csr
  * rearranged); a target's field is then bit-identical in every such batch.
+ * DD_KL on a truncated handle loaded dense with a gemm_form instead takes the
+ * contraction over the floored kernel, for any T:
+ *     KL_tau(x,t) = H~_t - o_x W~_t - sum_b P~_tb l~_xb,
+ *     l~_xb = log max(P_xb, phi_x) - o_x
+ * (P^_xb = max(P_xb, phi_x) is the stored value or the floor; H~_t and W~_t
+ * are sums over the truncated target row).
  * Otherwise one streaming pass per target.  bounds: nullable host [T].
  * Asynchronous on `stream`. */
 dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t T,

@@ -146,7 +146,8 @@ __global__ __launch_bounds__(256) void trunc_fill_kernel(DenseView v, const doub
 // of the contraction operand (padding rows are zeroed by the caller).
 __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, int64_t lda,
                                                         float* l32, uint16_t* lhi, uint16_t* llo,
-                                                        float* offset, int32_t* zeros) {
+                                                        float* offset, int32_t* zeros,
+                                                        const double* floor) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= v.N) return;
@@ -160,12 +161,13 @@ __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, i
   const int64_t R = gemm_row_tiles(v.N);
   const int64_t tile_base = (row / kGemmRows) * kGemmRows * kGemmK;
   const int xr = (int)(row % kGemmRows);
+  const double fl = floor ? floor[row] : 0.0;   // > 0 when given
   for (int64_t b = lane; b < lda; b += 64) {
     const int64_t at = tile_base + (b / kGemmK) * R * kGemmRows * kGemmK +
                        gemm_tile_offset(form == 0, xr, (int)(b % kGemmK));
     double l = 0.0;
     if (b < v.B) {
-      const double p = master_at(v, row, (int)b);
+      const double p = fmax(master_at(v, row, (int)b), fl);
       if (p > 0.0)
         l = log(p) - of;
       else
@@ -256,9 +258,41 @@ hipError_t launch_csr_f16(const int64_t* start, const int32_t* len, const float*
 }
 
 hipError_t launch_log_forms(DenseView v, int form, int64_t lda, float* l32, uint16_t* lhi,
-                            uint16_t* llo, float* offset, int32_t* zeros, hipStream_t s) {
+                            uint16_t* llo, float* offset, int32_t* zeros, const double* floor,
+                            hipStream_t s) {
   hipLaunchKernelGGL(log_forms_kernel, dim3(rows_grid(v.N)), dim3(256), 0, s, v, form, lda, l32,
-                     lhi, llo, offset, zeros);
+                     lhi, llo, offset, zeros, floor);
+  return hipGetLastError();
+}
+
+// Row j of the dense target block: the truncated row of target tl.t[j] (its
+// stored values, zero elsewhere) in FP32 [Tpad][ld] and, from the FP64
+// values when the handle has them, FP64 [Tpad][B]; rows past T are zero.
+__global__ __launch_bounds__(256) void csr_rows_dense_kernel(CsrView v, TargetList tl, int32_t T,
+                                                             int64_t ld, float* out32,
+                                                             double* out64) {
+  const int j = blockIdx.x;
+  float* o32 = out32 + (int64_t)j * ld;
+  double* o64 = out64 ? out64 + (int64_t)j * v.B : nullptr;
+  for (int64_t b = threadIdx.x; b < ld; b += blockDim.x) {
+    o32[b] = 0.f;
+    if (o64 && b < v.B) o64[b] = 0.0;
+  }
+  __syncthreads();
+  if (j >= T) return;
+  const int t = tl.t[j];
+  const int64_t st = v.start[t];
+  for (int i = threadIdx.x; i < v.len[t]; i += blockDim.x) {
+    const int b = v.col[st + i];
+    o32[b] = v.val[st + i];
+    if (o64) o64[b] = v.val64[st + i];
+  }
+}
+
+hipError_t launch_csr_rows_dense(CsrView v, TargetList tl, int32_t T, int32_t Tpad, int64_t ld,
+                                 float* out32, double* out64, hipStream_t s) {
+  hipLaunchKernelGGL(csr_rows_dense_kernel, dim3(Tpad), dim3(256), 0, s, v, tl, T, ld, out32,
+                     out64);
   return hipGetLastError();
 }
 

@@ -113,6 +113,7 @@ struct dd_kernel {
   // batched-KL operand
   DevBuf L32, Lhi, Llo, Off;
   double omax = 0.0;   // max_x o_x (FP32 offsets as used)
+  double lfloor = 0.0; // truncated handles: max_x (o_x - log phi_x) >= |l_xb| of the floored operand
   // truncated
   DevBuf start, len, col, val, val64, phi, lphi;
   DevBuf val16, rsc;   // FP16 form of the stored values and 2^-e_x per row
@@ -326,6 +327,22 @@ dd_error_bound field_bound(const dd_kernel* k, int kind, int32_t t) {
 //          product (2^-22), 64-term partial sums over 12 accumulations
 //          (30u), FP16 subnormal floors (2^-25 per entry, scaled by 1/s_t).
 dd_error_bound gemm_bound(const dd_kernel* k, int32_t t) {
+  if (k->is_csr) {
+    // floored operand: every |l_xb| <= lfloor, and the truncated target row
+    // sums to at most W_t, so the weight of the products is at most
+    // W_t lfloor; the FP32 rounding of FP64 target values adds u per term
+    const double c = k->gemm_form == DD_FORM_F32 ? 35.0 : 42.0;
+    const double split = k->gemm_form == DD_FORM_BF16X3 ? 3.0 * std::ldexp(1.0, -16) : 0.0;
+    const double W = k->W_host[t];
+    dd_error_bound b;
+    b.rel = 2.0 * ((c + 1.0) * kU + split);
+    b.abs = 2.0 * (c * kU + split + (k->val64.p ? kU : 0.0)) * W * k->lfloor;
+    if (k->gemm_form == DD_FORM_F16X3)
+      b.abs += 2.0 * std::ldexp(1.0, -39) * (double)k->B * std::max(88.0, k->lfloor);
+    if (k->gemm_form == DD_FORM_BF16X3)
+      b.abs += 2.0 * std::ldexp(1.0, -125) * (double)k->B * (104.0 + k->lfloor + W);
+    return b;
+  }
   const double H = std::fabs(k->H_host[t]);
   const double W = k->W_host[t];
   // BF16X3: hi+lo of l and of q each within 2^-16 relative, the dropped
@@ -527,6 +544,59 @@ hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 }  // namespace
 
+// The batched-KL operand l_xb = log P_xb - o_x in the tiled layout of form
+// `form`, from the dense rows still held by k; with `floor` (device [N]),
+// l_xb = log max(P_xb, phi_x) - o_x, the floored kernel of a truncated handle.
+dd_status build_gemm_operand(dd_kernel* k, int form, const double* floor) {
+  const int32_t N = k->N;
+  k->lda = ((int64_t)k->B + 63) & ~int64_t(63);
+  DevBuf zeros;
+  hipError_t e = zeros.alloc(4);
+  if (!e) e = hipMemset(zeros.p, 0, 4);
+  if (!e) e = k->Off.alloc(4 * (size_t)N);
+  const size_t elems = (size_t)dd::gemm_rows_padded(N) * (size_t)k->lda;
+  if (!e && form == DD_FORM_F32) {
+    e = k->L32.alloc(4 * elems);
+    if (!e) e = hipMemset(k->L32.p, 0, 4 * elems);
+  }
+  if (!e && form != DD_FORM_F32) {
+    e = k->Lhi.alloc(2 * elems);
+    if (!e) e = k->Llo.alloc(2 * elems);
+    if (!e) e = hipMemset(k->Lhi.p, 0, 2 * elems);
+    if (!e) e = hipMemset(k->Llo.p, 0, 2 * elems);
+  }
+  if (!e) e = dd::launch_log_forms(k->dense(), form, k->lda, k->L32.as<float>(),
+                                   k->Lhi.as<uint16_t>(), k->Llo.as<uint16_t>(),
+                                   k->Off.as<float>(), zeros.as<int32_t>(), floor, nullptr);
+  if (!e) e = hipDeviceSynchronize();
+  if (e) return fail(DD_EDEVICE, "log-kernel operand: %s", hipGetErrorString(e));
+  int32_t nzero = 0;
+  if (hipMemcpy(&nzero, zeros.p, 4, hipMemcpyDeviceToHost))
+    return fail(DD_EDEVICE, "copy of the zero count failed");
+  if (nzero > 0)
+    return fail(DD_EINVAL,
+                "%d rows hold a zero entry in a non-zero column: log P is not finite "
+                "there, so the batched-KL operand cannot be built",
+                nzero);
+  // the largest row offset o_x (<= 0 for rows whose max is at most 1),
+  // used by the error bound of the contraction
+  std::vector<float> off(N);
+  if (hipMemcpy(off.data(), k->Off.p, 4 * (size_t)N, hipMemcpyDeviceToHost))
+    return fail(DD_EDEVICE, "copy of the row offsets failed");
+  k->omax = -std::numeric_limits<double>::infinity();
+  for (int32_t x = 0; x < N; ++x) k->omax = std::max(k->omax, (double)off[x]);
+  if (floor) {
+    std::vector<double> phi(N);
+    if (hipMemcpy(phi.data(), floor, 8 * (size_t)N, hipMemcpyDeviceToHost))
+      return fail(DD_EDEVICE, "copy of the floors failed");
+    k->lfloor = 0.0;
+    for (int32_t x = 0; x < N; ++x)
+      k->lfloor = std::max(k->lfloor, (double)off[x] - std::log(phi[x]));
+  }
+  k->gemm_form = form;
+  return DD_OK;
+}
+
 extern "C" {
 
 const char* dd_last_error(void) { return g_err.c_str(); }
@@ -575,8 +645,8 @@ dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P,
     return fail(DD_EINVAL, "unknown gemm_form %d", o.gemm_form);
   if (!(o.tau >= 0.0) || !std::isfinite(o.tau) || o.tau > 1.0)
     return fail(DD_EINVAL, "tau must be in [0, 1]");
-  if (o.tau > 0.0 && o.gemm_form != DD_FORM_NONE)
-    return fail(DD_EINVAL, "a truncated load has no batched-KL operand");
+  if (o.tau > 0.0 && o.gemm_form != DD_FORM_NONE && o.csr_values != DD_CSR_F32)
+    return fail(DD_EINVAL, "the floored batched-KL operand needs FP32 stored values");
   if (o.csr_values != DD_CSR_F32 && o.csr_values != DD_CSR_F16)
     return fail(DD_EINVAL, "unknown csr_values %d", o.csr_values);
   if (dd_status s = check_adjacency(N, adj)) return s;
@@ -677,6 +747,9 @@ dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P,
       if (e) return bail(fail(DD_EDEVICE, "floor copy: %s", hipGetErrorString(e)));
       if (dd_status s = build_csr_f16(k, smax, phi)) return bail(s);
     }
+    if (o.gemm_form != DD_FORM_NONE)
+      if (dd_status s = build_gemm_operand(k, o.gemm_form, k->phi.as<const double>()))
+        return bail(s);
     k->P32.release();
     k->P64.release();
   } else {
@@ -686,45 +759,8 @@ dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P,
     k->H_host.assign(N, 0.0);
     if (!e) e = hipMemcpy(k->H_host.data(), k->H.p, 8 * (size_t)N, hipMemcpyDeviceToHost);
     if (e) return bail(fail(DD_EDEVICE, "row entropy: %s", hipGetErrorString(e)));
-    if (o.gemm_form != DD_FORM_NONE) {
-      k->lda = ((int64_t)k->B + 63) & ~int64_t(63);
-      DevBuf zeros;
-      e = zeros.alloc(4);
-      if (!e) e = hipMemset(zeros.p, 0, 4);
-      if (!e) e = k->Off.alloc(4 * (size_t)N);
-      const size_t elems = (size_t)dd::gemm_rows_padded(N) * (size_t)k->lda;
-      if (!e && o.gemm_form == DD_FORM_F32) {
-        e = k->L32.alloc(4 * elems);
-        if (!e) e = hipMemset(k->L32.p, 0, 4 * elems);
-      }
-      if (!e && o.gemm_form != DD_FORM_F32) {
-        e = k->Lhi.alloc(2 * elems);
-        if (!e) e = k->Llo.alloc(2 * elems);
-        if (!e) e = hipMemset(k->Lhi.p, 0, 2 * elems);
-        if (!e) e = hipMemset(k->Llo.p, 0, 2 * elems);
-      }
-      if (!e) e = dd::launch_log_forms(k->dense(), o.gemm_form, k->lda, k->L32.as<float>(),
-                                       k->Lhi.as<uint16_t>(), k->Llo.as<uint16_t>(),
-                                       k->Off.as<float>(), zeros.as<int32_t>(), nullptr);
-      if (!e) e = hipDeviceSynchronize();
-      if (e) return bail(fail(DD_EDEVICE, "log-kernel operand: %s", hipGetErrorString(e)));
-      int32_t nzero = 0;
-      if (hipMemcpy(&nzero, zeros.p, 4, hipMemcpyDeviceToHost))
-        return bail(fail(DD_EDEVICE, "copy of the zero count failed"));
-      if (nzero > 0)
-        return bail(fail(DD_EINVAL,
-                         "%d rows hold a zero entry in a non-zero column: log P is not finite "
-                         "there, so the batched-KL operand cannot be built",
-                         nzero));
-      // the largest row offset o_x (<= 0 for rows whose max is at most 1),
-      // used by the error bound of the contraction
-      std::vector<float> off(N);
-      if (hipMemcpy(off.data(), k->Off.p, 4 * (size_t)N, hipMemcpyDeviceToHost))
-        return bail(fail(DD_EDEVICE, "copy of the row offsets failed"));
-      k->omax = -std::numeric_limits<double>::infinity();
-      for (int32_t x = 0; x < N; ++x) k->omax = std::max(k->omax, (double)off[x]);
-      k->gemm_form = o.gemm_form;
-    }
+    if (o.gemm_form != DD_FORM_NONE)
+      if (dd_status s = build_gemm_operand(k, o.gemm_form, nullptr)) return bail(s);
   }
   if (dd_status s = upload_adjacency(k, adj)) return bail(s);
   return finish_handle(k, ctx, out);
@@ -742,7 +778,7 @@ dd_status dd_load_kernel_csr(dd_ctx* ctx, int32_t N, int32_t B, const int64_t* r
   if (!(tau > 0.0) || !(tau <= 1.0)) return fail(DD_EINVAL, "tau must be in (0, 1]");
   const dd_load_opts o = opts ? *opts : default_opts();
   if (o.gemm_form != DD_FORM_NONE)
-    return fail(DD_EINVAL, "a truncated load has no batched-KL operand");
+    return fail(DD_EINVAL, "a CSR load has no dense rows to build the batched-KL operand from");
   if (o.csr_values != DD_CSR_F32 && o.csr_values != DD_CSR_F16)
     return fail(DD_EINVAL, "unknown csr_values %d", o.csr_values);
   if (dd_status s = check_adjacency(N, adj)) return s;
@@ -872,19 +908,38 @@ dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t
       return fail(DD_EINVAL, "targets[%d]=%d not in [0, %d)", i, targets[i], k->N);
   HIP_OR(hipSetDevice(k->ctx->device));
   hipStream_t s = as_stream(stream);
-  if (kind == DD_KL && !k->is_csr && k->gemm_form != DD_FORM_NONE) {
+  if (kind == DD_KL && k->gemm_form != DD_FORM_NONE) {
     dd::GemmView gv{k->L32.as<const float>(), k->Lhi.as<const uint16_t>(),
                     k->Llo.as<const uint16_t>(), k->Off.as<const float>(),
                     k->lda, k->N, k->B, k->gemm_form};
     // up to 256 targets per launch; each launch reads the log-kernel about once
-    AsyncBuf ws(s);
-    HIP_OR(ws.alloc(dd::batch_kl_workspace(gv, std::min<int32_t>(T, dd::kMaxBatch))));
+    const int32_t tmax = std::min<int32_t>(T, dd::kMaxBatch);
+    AsyncBuf ws(s), rows(s);
+    HIP_OR(ws.alloc(dd::batch_kl_workspace(gv, tmax)));
+    // a truncated handle: the truncated target rows are expanded to dense
+    // rows first (FP32 [Tpad][lda], and FP64 [Tpad][B] from FP64 values)
+    const int32_t tpad = dd::batch_padded_targets(tmax);
+    const bool f64 = k->is_csr && k->val64.p;
+    const size_t r32 = 4 * (size_t)tpad * (size_t)k->lda;
+    if (k->is_csr) HIP_OR(rows.alloc(r32 + (f64 ? 8 * (size_t)tpad * (size_t)k->B : 0)));
     for (int32_t g0 = 0; g0 < T; g0 += dd::kMaxBatch) {
       const int32_t n = std::min<int32_t>(dd::kMaxBatch, T - g0);
       dd::TargetList tl;
       std::memset(&tl, 0, sizeof tl);
       for (int32_t i = 0; i < n; ++i) tl.t[i] = targets[g0 + i];
-      HIP_OR(dd::launch_batch_kl(k->dense(), gv, tl, n, ws.p, out_dev + (int64_t)g0 * k->N, s));
+      if (!k->is_csr) {
+        HIP_OR(dd::launch_batch_kl(k->dense(), gv, tl, n, ws.p, out_dev + (int64_t)g0 * k->N, s));
+        continue;
+      }
+      float* d32 = rows.as<float>();
+      double* d64 = f64 ? reinterpret_cast<double*>(rows.as<unsigned char>() + r32) : nullptr;
+      HIP_OR(dd::launch_csr_rows_dense(k->csr(), tl, n, dd::batch_padded_targets(n), k->lda, d32,
+                                       d64, s));
+      dd::TargetList id;
+      std::memset(&id, 0, sizeof id);
+      for (int32_t i = 0; i < n; ++i) id.t[i] = i;
+      const dd::DenseView dv{d32, d64, k->lda, dd::batch_padded_targets(n), k->B};
+      HIP_OR(dd::launch_batch_kl(dv, gv, id, n, ws.p, out_dev + (int64_t)g0 * k->N, s));
     }
     if (bounds)
       for (int32_t i = 0; i < T; ++i) bounds[i] = gemm_bound(k, targets[i]);

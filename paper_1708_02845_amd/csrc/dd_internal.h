@@ -52,8 +52,10 @@ hipError_t launch_trunc_fill(DenseView v, const double* thr, const int64_t* star
 // FP16 copy of the stored values, row x scaled by 2^e_x (rscale[x] = 2^-e_x).
 hipError_t launch_csr_f16(const int64_t* start, const int32_t* len, const float* val,
                           const float* rscale, int32_t N, uint16_t* val16, hipStream_t s);
+// floor: nullable per-row floor phi_x; with it l = log max(P_xb, phi_x) - o_x.
 hipError_t launch_log_forms(DenseView v, int form, int64_t lda, float* l32, uint16_t* lhi,
-                            uint16_t* llo, float* offset, int32_t* zeros, hipStream_t s);
+                            uint16_t* llo, float* offset, int32_t* zeros, const double* floor,
+                            hipStream_t s);
 
 // ---- streaming fields (stream.hip) ----
 hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out, hipStream_t s);
@@ -95,6 +97,10 @@ struct TargetList {
   int32_t t[kMaxBatch];
 };
 size_t batch_kl_workspace(GemmView gv, int32_t T);
+int32_t batch_padded_targets(int32_t T);   // target slots of one contraction launch
+// Dense rows of the truncated target rows (see convert.hip), Tpad blocks.
+hipError_t launch_csr_rows_dense(CsrView v, TargetList tl, int32_t T, int32_t Tpad, int64_t ld,
+                                 float* out32, double* out64, hipStream_t s);
 
 // ---- Poisson kernel of a grid domain (poisson.hip) ----
 struct GridSolveStats {
