@@ -266,8 +266,9 @@ hipError_t launch_log_forms(DenseView v, int form, int64_t lda, float* l32, uint
 }
 
 // Row j of the dense target block: the truncated row of target tl.t[j] (its
-// stored values, zero elsewhere) in FP32 [Tpad][ld] and, from the FP64
-// values when the handle has them, FP64 [Tpad][B]; rows past T are zero.
+// stored values, zero elsewhere) in FP32 [rows][ld] and, from the FP64
+// values when the handle has them, FP64 [rows][B]; rows past T are zero.
+// The contraction's target preparation reads rows j < T only.
 __global__ __launch_bounds__(256) void csr_rows_dense_kernel(CsrView v, TargetList tl, int32_t T,
                                                              int64_t ld, float* out32,
                                                              double* out64) {

@@ -917,8 +917,9 @@ dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t
     AsyncBuf ws(s), rows(s);
     HIP_OR(ws.alloc(dd::batch_kl_workspace(gv, tmax)));
     // a truncated handle: the truncated target rows are expanded to dense
-    // rows first (FP32 [Tpad][lda], and FP64 [Tpad][B] from FP64 values)
-    const int32_t tpad = dd::batch_padded_targets(tmax);
+    // rows first (FP32 [rows][lda], and FP64 [rows][B] from FP64 values);
+    // the target preparation reads the first n rows of a group of n
+    const int32_t tpad = (tmax + 63) / 64 * 64;
     const bool f64 = k->is_csr && k->val64.p;
     const size_t r32 = 4 * (size_t)tpad * (size_t)k->lda;
     if (k->is_csr) HIP_OR(rows.alloc(r32 + (f64 ? 8 * (size_t)tpad * (size_t)k->B : 0)));
@@ -933,12 +934,12 @@ dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t
       }
       float* d32 = rows.as<float>();
       double* d64 = f64 ? reinterpret_cast<double*>(rows.as<unsigned char>() + r32) : nullptr;
-      HIP_OR(dd::launch_csr_rows_dense(k->csr(), tl, n, dd::batch_padded_targets(n), k->lda, d32,
-                                       d64, s));
+      const int32_t rows_n = (n + 63) / 64 * 64;   // <= tpad
+      HIP_OR(dd::launch_csr_rows_dense(k->csr(), tl, n, rows_n, k->lda, d32, d64, s));
       dd::TargetList id;
       std::memset(&id, 0, sizeof id);
       for (int32_t i = 0; i < n; ++i) id.t[i] = i;
-      const dd::DenseView dv{d32, d64, k->lda, dd::batch_padded_targets(n), k->B};
+      const dd::DenseView dv{d32, d64, k->lda, rows_n, k->B};
       HIP_OR(dd::launch_batch_kl(dv, gv, id, n, ws.p, out_dev + (int64_t)g0 * k->N, s));
     }
     if (bounds)

@@ -97,8 +97,7 @@ struct TargetList {
   int32_t t[kMaxBatch];
 };
 size_t batch_kl_workspace(GemmView gv, int32_t T);
-int32_t batch_padded_targets(int32_t T);   // target slots of one contraction launch
-// Dense rows of the truncated target rows (see convert.hip), Tpad blocks.
+// Dense rows of the truncated target rows (see convert.hip), one block per row.
 hipError_t launch_csr_rows_dense(CsrView v, TargetList tl, int32_t T, int32_t Tpad, int64_t ld,
                                  float* out32, double* out64, hipStream_t s);
 

@@ -90,8 +90,6 @@ constexpr int kXcds = 8;   // MI355X: 8 XCDs, work-groups dispatched round robin
 
 static int padded_targets(int32_t T) { return T <= 32 ? 32 : (T + 63) / 64 * 64; }
 
-int32_t batch_padded_targets(int32_t T) { return padded_targets(T); }
-
 // Row block and target group of this workgroup (see the header comment).
 __device__ __forceinline__ void block_tile(int groups, int& rb, int& g) {
   const int b = (int)blockIdx.x;
