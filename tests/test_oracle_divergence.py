@@ -286,3 +286,21 @@ def test_disk_power_and_alpha_closed_forms(c1, k):
     for a in (-0.5, 0.25, 0.75):
         ref = odisk.alpha_closed(c1.z, c1.z[t], a)
         assert np.abs(dv.alpha_field(c1.P, t, a) - ref).max() < 2e-5
+
+
+@pytest.mark.parametrize("tau,relative", [(1e-3, True), (1e-6, True), (2e-4, False)])
+def test_truncated_kl_is_a_floored_contraction(grid_P, tau, relative):
+    # An entry is stored when P_xb >= phi_x, and a dropped one stands at phi_x, so
+    # the value KL_tau takes for row x is max(P_xb, phi_x) and
+    #   KL_tau(x, t) = sum_b p~_b log p~_b - sum_b p~_b log max(P_xb, phi_x):
+    # one matrix product over the floored log-kernel (the form the library's
+    # contraction takes on truncated handles).
+    P = np.asarray(grid_P, dtype=np.float64)
+    Pt, thr = dv.truncate(P, tau, relative)
+    L = np.log(np.maximum(P, thr[:, None]))
+    for t in (0, 17, P.shape[0] - 1):
+        p = Pt[t]
+        H = float((p[p > 0] * np.log(p[p > 0])).sum())
+        alt = H - L @ p
+        ref = dv.kl_trunc_field(Pt, t, thr)
+        assert np.abs(alt - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), t
