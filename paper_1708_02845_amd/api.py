@@ -144,7 +144,10 @@ class Kernel:
                    validate=True, csr_values="f32"):
         """Load an N x B matrix given as a numpy array or a torch tensor (any device).
         With tau > 0 the handle keeps the truncation, its values read as FP32 or,
-        with csr_values="f16", as FP16 scaled per row."""
+        with csr_values="f16", as FP16 scaled per row.  gemm_form ("f32", "f16x3",
+        "bf16x3") builds the batched-KL contraction operand; with tau > 0 it is
+        the floored log-kernel, and KL_tau of many targets runs as one
+        contraction (FP32 values only)."""
         torch = _torch()
         keep = []
         if isinstance(P, np.ndarray):
@@ -228,7 +231,9 @@ class Kernel:
         return out, bound_tuple(b)
 
     def batch_fields(self, targets, kind, out=None, stream=None):
-        """(fields [T, N], list of bounds) for T targets."""
+        """(fields [T, N], list of (abs, rel) bounds) for T targets: KL through the
+        contraction when the handle has an operand, the pass over the stored rows
+        on a truncated handle from 8 targets, else one streaming pass each."""
         t = np.ascontiguousarray(targets, dtype=np.int32)
         T = len(t)
         out = self._out((T, self.N), out)
