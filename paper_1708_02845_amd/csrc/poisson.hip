@@ -36,8 +36,11 @@
 //   (a device flag), so its result does not depend on the other columns of
 //   its batch either: the batch runs until all its columns have stopped.
 // * Work-groups take row ranges that are contiguous per XCD (work-groups go
-//   to the 8 XCDs round robin), so a vertex's neighbours one grid row up and
-//   down are read from the same L2.
+//   to the 8 XCDs round robin), so the ranges an XCD runs together are
+//   adjacent and a vertex's neighbours one grid row up and down were fetched
+//   shortly before by the same XCD.  Part of them are fetched again (from the
+//   memory-side cache): the stencil kernels are bound by load latency, and a
+//   column-walking variant that removed those fetches ran slower.
 #include <math.h>
 
 #include <vector>
