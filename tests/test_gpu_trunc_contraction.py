@@ -120,3 +120,22 @@ def test_rejections(gpu_ctx, grid):
     g, P = grid
     with pytest.raises(DDError, match="FP32 stored values"):
         Kernel.load_dense(gpu_ctx, P, tau=1e-3, gemm_form="f16x3", csr_values="f16")
+
+
+@pytest.mark.parametrize("T", [1, 33])
+def test_small_and_ragged_batches(gpu_ctx, grid, T):
+    """One target (32 padded target slots) and 33 targets (a ragged group of 64)
+    through the floored contraction, every target against the oracle."""
+    from paper_1708_02845_amd import Kernel
+    g, P = grid
+    k = Kernel.load_dense(gpu_ctx, P, tau=1e-4, gemm_form="f16x3")
+    try:
+        ts = targets_sources(95 + T, g.N, T)[0]
+        d, bounds = k.batch_fields(ts, "kl")
+        d = d.cpu().numpy()
+        for i in range(T):
+            ref = oracle_trunc_kl(P, 1e-4, True, int(ts[i]))
+            assert normwise(d[i], ref) <= 1e-5, i
+            assert within_bound(d[i], ref, bounds[i]), i
+    finally:
+        k.free()
