@@ -309,15 +309,15 @@ def grid_poisson_row(ctx, g, P_host, build_s, batch=1024):
     _, st = ctx.grid_poisson_kernel(g.node_type(), out=out, tol=1e-12, batch=batch)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    # algorithmic bytes of one iteration over a batch: 14 passes over the fine
-    # level (product 2, update 6, restriction 1, prolongation and smoothing 2,
-    # direction 3), 4 over each coarser level
+    # algorithmic bytes of one iteration over a batch: 13 passes over the fine
+    # level (product 2, residual update 3, restriction 1, prolongation and
+    # smoothing 2, direction with the solution update 5), 4 over each coarser level
     G, levels = g.G, []
     Gl = G
     for _ in range(st["levels"]):
         levels.append(Gl)
         Gl = Gl // 2 + 1
-    per_iter = 8 * batch * (14 * G * G + sum(4 * x * x for x in levels[1:]))
+    per_iter = 8 * batch * (13 * G * G + sum(4 * x * x for x in levels[1:]))
     byts = st["total_iterations"] * per_iter + 4 * g.N * g.K
     rows = np.random.default_rng(5).choice(g.N, size=64, replace=False)
     diff = float(np.abs(out[torch.as_tensor(rows, device="cuda:0")].cpu().numpy() -

@@ -155,20 +155,21 @@ __global__ __launch_bounds__(256) void pk_matvec(const double* __restrict__ p,
   block_partial(acc, part, rb, C, c);
 }
 
-// alpha = rz / pq per column (0 once the column has stopped);
-// x += alpha p, r -= alpha q; partials of r.r.
-__global__ __launch_bounds__(256) void pk_update(double* __restrict__ x, double* __restrict__ r,
-                                                 const double* __restrict__ p,
+// alpha = rz / pq per column (0 once the column has stopped), kept in
+// alpha_out for the step x += alpha p, which the next direction update makes
+// while it reads p anyway; r -= alpha q; partials of r.r.
+__global__ __launch_bounds__(256) void pk_update(double* __restrict__ r,
                                                  const double* __restrict__ q, const double* rz,
                                                  const double* pq, const double* done,
-                                                 const uint8_t* act, int32_t G, int64_t C,
-                                                 int groups, double* part) {
+                                                 double* alpha_out, const uint8_t* act, int32_t G,
+                                                 int64_t C, int groups, double* part) {
   const int64_t nodes = (int64_t)G * G;
   int64_t rb;
   int grp;
   if (!block_of(nodes, groups, rb, grp)) return;
   const int64_t c = grp * 64 + (threadIdx.x & 63);
   const double a = done[c] == 0.0 && pq[c] > 0.0 ? rz[c] / pq[c] : 0.0;
+  if (rb == 0 && threadIdx.x < 64) alpha_out[c] = a;   // one writer per column
   const int64_t g0 = rb * kRowsPerBlock + (threadIdx.x >> 6) * kRowsPerWave;
   double acc = 0.0;
 #pragma unroll 4
@@ -177,7 +178,6 @@ __global__ __launch_bounds__(256) void pk_update(double* __restrict__ x, double*
     if (g >= nodes) break;
     if (!act[g]) continue;
     const int64_t o = g * C + c;
-    x[o] += a * p[o];
     const double rn = r[o] - a * q[o];
     r[o] = rn;
     acc += rn * rn;
@@ -185,9 +185,11 @@ __global__ __launch_bounds__(256) void pk_update(double* __restrict__ x, double*
   block_partial(acc, part, rb, C, c);
 }
 
-// p = z (first) or z + beta p, beta = rz_new / rz_old per column.
+// p = z (first) or z + beta p, beta = rz_new / rz_old per column; before p
+// is replaced, the previous step's x += alpha p.
 __global__ __launch_bounds__(256) void pk_direction(double* __restrict__ p,
                                                     const double* __restrict__ z,
+                                                    double* __restrict__ x, const double* alpha,
                                                     const double* rz_new, const double* rz_old,
                                                     int first, const uint8_t* act, int32_t G,
                                                     int64_t C, int groups) {
@@ -197,13 +199,43 @@ __global__ __launch_bounds__(256) void pk_direction(double* __restrict__ p,
   if (!block_of(nodes, groups, rb, grp)) return;
   const int64_t c = grp * 64 + (threadIdx.x & 63);
   const double beta = first ? 0.0 : (rz_old[c] > 0.0 ? rz_new[c] / rz_old[c] : 0.0);
+  const double a = first ? 0.0 : alpha[c];
   const int64_t g0 = rb * kRowsPerBlock + (threadIdx.x >> 6) * kRowsPerWave;
 #pragma unroll 4
   for (int k = 0; k < kRowsPerWave; ++k) {
     const int64_t g = g0 + k;
     if (g >= nodes) break;
     const int64_t o = g * C + c;
-    p[o] = act[g] ? (first ? z[o] : z[o] + beta * p[o]) : 0.0;
+    if (!act[g]) {
+      p[o] = 0.0;
+      continue;
+    }
+    if (first) {
+      p[o] = z[o];
+    } else {
+      const double po = p[o];
+      x[o] += a * po;
+      p[o] = z[o] + beta * po;
+    }
+  }
+}
+
+// The last step x += alpha p (at exit, with no direction update after it).
+__global__ __launch_bounds__(256) void pk_axpy(double* __restrict__ x,
+                                               const double* __restrict__ p, const double* alpha,
+                                               const uint8_t* act, int32_t G, int64_t C,
+                                               int groups) {
+  const int64_t nodes = (int64_t)G * G;
+  int64_t rb;
+  int grp;
+  if (!block_of(nodes, groups, rb, grp)) return;
+  const int64_t c = grp * 64 + (threadIdx.x & 63);
+  const double a = alpha[c];
+  const int64_t g0 = rb * kRowsPerBlock + (threadIdx.x >> 6) * kRowsPerWave;
+  for (int k = 0; k < kRowsPerWave; ++k) {
+    const int64_t g = g0 + k;
+    if (g >= nodes) break;
+    if (act[g]) x[g * C + c] += a * p[g * C + c];
   }
 }
 
@@ -456,7 +488,7 @@ size_t grid_poisson_workspace(int32_t G, int32_t C) {
     bytes += (size_t)arrays * nodes * C * 8 + (size_t)nodes;
     Gl = Gl / 2 + 1;
   }
-  bytes += (size_t)row_blocks((int64_t)G * G) * C * 8 + 6 * (size_t)C * 8;
+  bytes += (size_t)row_blocks((int64_t)G * G) * C * 8 + 7 * (size_t)C * 8;
   bytes += (size_t)G * G * 4 + (size_t)C * 4;
   return bytes;
 }
@@ -508,7 +540,7 @@ hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, 
   if (L > 1) PK_OR(tco.alloc((size_t)Gs[L - 1] * Gs[L - 1] * C * 8));
   const int64_t nrb0 = row_blocks(nodes);
   PK_OR(part.alloc((size_t)nrb0 * C * 8));
-  PK_OR(sc.alloc(6 * (size_t)C * 8));
+  PK_OR(sc.alloc(7 * (size_t)C * 8));
   PK_OR(dil.alloc((size_t)nodes * 4));
   PK_OR(dbnd.alloc((size_t)C * 4));
   PK_OR(hipMemcpyAsync(dil.p, iloc.data(), (size_t)nodes * 4, hipMemcpyHostToDevice, s));
@@ -518,6 +550,7 @@ hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, 
   double* rr = rz + 3 * C;
   double* bb = rz + 4 * C;
   double* done = rz + 5 * C;
+  double* alpha = rz + 6 * C;
   const double tol2 = tol * tol;
 
   auto fill = [&](void* a, size_t n) {
@@ -603,7 +636,7 @@ hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, 
     PK_OR(hipMemcpyAsync(h_bb.data(), bb, (size_t)C * 8, hipMemcpyDeviceToHost, s));
     precondition(rz);
     hipLaunchKernelGGL(pk_direction, dim3(g0), dim3(256), 0, s, p.as<double>(), z.as<double>(),
-                       rz, rz, 1, a0, G, (int64_t)C, groups);
+                       x.as<double>(), alpha, rz, rz, 1, a0, G, (int64_t)C, groups);
     PK_OR(hipGetLastError());
     int32_t it = 0;
     double res = 0.0;
@@ -613,8 +646,8 @@ hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, 
       hipLaunchKernelGGL(pk_matvec, dim3(g0), dim3(256), 0, s, p.as<double>(), q.as<double>(), a0,
                          G, (int64_t)C, groups, part.as<double>());
       dot_final(nrb0, pq);
-      hipLaunchKernelGGL(pk_update, dim3(g0), dim3(256), 0, s, x.as<double>(), dr[0].as<double>(),
-                         p.as<double>(), q.as<double>(), rz, pq, done, a0, G, (int64_t)C, groups,
+      hipLaunchKernelGGL(pk_update, dim3(g0), dim3(256), 0, s, dr[0].as<double>(),
+                         q.as<double>(), rz, pq, done, alpha, a0, G, (int64_t)C, groups,
                          part.as<double>());
       dot_final(nrb0, rr);
       hipLaunchKernelGGL(pk_converged, dim3((C + 255) / 256), dim3(256), 0, s, rr, bb, tol2, done,
@@ -633,12 +666,14 @@ hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, 
       }
       precondition(rzn);
       hipLaunchKernelGGL(pk_direction, dim3(g0), dim3(256), 0, s, p.as<double>(), z.as<double>(),
-                         rzn, rz, 0, a0, G, (int64_t)C, groups);
+                         x.as<double>(), alpha, rzn, rz, 0, a0, G, (int64_t)C, groups);
       PK_OR(hipGetLastError());
       double* t = rz;
       rz = rzn;
       rzn = t;
     }
+    hipLaunchKernelGGL(pk_axpy, dim3(g0), dim3(256), 0, s, x.as<double>(), p.as<double>(), alpha,
+                       a0, G, (int64_t)C, groups);
     hipLaunchKernelGGL(pk_write, dim3(g0), dim3(256), 0, s, x.as<double>(), a0, dil.as<int32_t>(),
                        G, (int64_t)C, groups, nb, P32 ? P32 + c0 : nullptr, ld32,
                        P64 ? P64 + c0 : nullptr, ld64);
