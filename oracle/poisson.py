@@ -41,15 +41,27 @@ def poisson_kernel(L, interior, boundary, chunk=256):
     return P
 
 
+class RowSolver:
+    """Rows of P_IB by row solves, with one sparse LU of L_II for many calls;
+    requires the symmetric L^c.  Row x is (L_II^{-1} e_x)^T (-L_IB)."""
+
+    def __init__(self, Lc, interior, boundary):
+        LII, LIB = block_split(Lc, interior, boundary)
+        self.m = LII.shape[0]
+        self.lu = spla.splu(LII.tocsc())
+        self.LIBt = sp.csr_matrix(LIB).T.tocsr()
+
+    def rows(self, rows):
+        rows = np.asarray(rows, dtype=np.int64)
+        E = np.zeros((self.m, len(rows)))
+        E[rows, np.arange(len(rows))] = 1.0
+        Y = self.lu.solve(E)                          # columns of L_II^{-1}
+        return -(self.LIBt @ Y).T                     # y^T L_IB with sign of eq. (33)
+
+
 def poisson_kernel_rows(Lc, interior, boundary, rows):
     """Selected rows of P_IB by row solves; requires the symmetric L^c."""
-    LII, LIB = block_split(Lc, interior, boundary)
-    lu = spla.splu(LII.tocsc())
-    rows = np.asarray(rows, dtype=np.int64)
-    E = np.zeros((LII.shape[0], len(rows)))
-    E[rows, np.arange(len(rows))] = 1.0
-    Y = lu.solve(E)                                   # columns of L_II^{-1}
-    return -(sp.csr_matrix(LIB).T @ Y).T              # y^T L_IB with sign of eq. (33)
+    return RowSolver(Lc, interior, boundary).rows(rows)
 
 
 def poisson_kernel_dense(L, interior, boundary):

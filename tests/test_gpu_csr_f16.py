@@ -138,3 +138,32 @@ def test_f16_rejections(gpu_ctx, grid):
         Kernel.load_dense(gpu_ctx, P, tau=1e-9, csr_values="f16")
     with pytest.raises(KeyError):
         Kernel.load_dense(gpu_ctx, P, tau=1e-3, csr_values="bf16")
+
+
+@pytest.mark.parametrize("T", [200, 257])
+@pytest.mark.parametrize("kind", ["tv", "kl"])
+def test_f16_many_target_pass_every_target(gpu_ctx, grid, T, kind):
+    """FP16 values with more than 128 targets: the four-lists-per-lane instance
+    of the many-target pass (257 = one full group of 256 and a ragged one of 1).
+    Every target of the batch is checked against the oracle's truncated field
+    of the FP32 input within its stated bound."""
+    from paper_1708_02845_amd import Kernel
+    g, P = grid
+    tau = 1e-5
+    k = Kernel.load_dense(gpu_ctx, P, tau=tau, csr_values="f16")
+    try:
+        ts = targets_sources(53, g.N, T)[0].astype(np.int32)
+        batch, bounds = k.batch_fields(ts, kind)
+        batch = batch.cpu().numpy()
+        Pt, thr = dv.truncate(np.asarray(P, dtype=np.float64), tau, True)
+        for i, t in enumerate(ts):
+            t = int(t)
+            ref = dv.tv_trunc_field(Pt, t) if kind == "tv" else dv.kl_trunc_field(Pt, t, thr)
+            assert batch[i, t] == 0.0, (i, t)
+            assert within_bound(batch[i], ref, bounds[i]), (i, t)
+            assert normwise(batch[i], ref) <= 2.0 ** -10, (i, t)
+        # a target's field does not depend on the batch it is computed in
+        single = k.batch_fields(ts[:8], kind)[0].cpu().numpy()
+        assert np.array_equal(single, batch[:8])
+    finally:
+        k.free()

@@ -211,21 +211,40 @@ def _solve_chunk(args):
     return hi - lo
 
 
-def harmonic_measure_5pt(dom, dtype=np.float64, workers=None, chunk=128, progress=None):
+def gpu_initialised():
+    """True when this process may hold a GPU context: torch's device runtime is
+    initialised, or the HIP library has been loaded.  Forking such a process
+    is unsafe."""
+    import sys
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_initialized():
+        return True
+    lib = sys.modules.get("paper_1708_02845_amd._lib")
+    return bool(lib is not None and getattr(lib, "_lib", None) is not None)
+
+
+def harmonic_measure_5pt(dom, dtype=np.float64, workers=None, chunk=128, progress=None,
+                         out_path=None):
     """Dense [N, K] matrix: row v = harmonic measure of interior vertex v.
 
     With several workers the columns are solved in forked processes into a
-    shared memory-mapped file, which is returned mapped (no final copy).
-    ``progress(done_columns, K)`` is called as chunks finish.
+    shared memory-mapped file, which is returned mapped (no final copy); a
+    process that already holds a GPU context does not fork and solves in
+    process instead.  ``out_path``: write the matrix to this raw file (row-major,
+    kept after return) and return it mapped.  ``progress(done_columns, K)`` is
+    called as chunks finish.
     """
     A, R = _five_point_system(dom)
     n, k = dom.N, dom.K
     if workers is None:
         workers = min(16, os.cpu_count() or 1)
+    if workers > 1 and gpu_initialised():
+        workers = 1
     work = [(lo, min(k, lo + chunk)) for lo in range(0, k, chunk)]
     if workers <= 1 or len(work) <= 1 or n * k < 2_000_000:
         lu = spla.splu(A)
-        P = np.empty((n, k), dtype=dtype)
+        P = (np.empty((n, k), dtype=dtype) if out_path is None else
+             np.memmap(out_path, dtype=dtype, mode="w+", shape=(n, k)))
         for lo, hi in work:
             X = lu.solve(R[:, lo:hi].toarray())
             np.maximum(X, 0.0, out=X)
@@ -235,9 +254,13 @@ def harmonic_measure_5pt(dom, dtype=np.float64, workers=None, chunk=128, progres
         return P
     import multiprocessing as mp
     import tempfile
-    d = "/dev/shm" if os.path.isdir("/dev/shm") else None
-    fd, name = tempfile.mkstemp(prefix="hm5pt_", dir=d)
-    os.close(fd)
+    if out_path is None:
+        d = "/dev/shm" if os.path.isdir("/dev/shm") else None
+        fd, name = tempfile.mkstemp(prefix="hm5pt_", dir=d)
+        os.close(fd)
+    else:
+        name = out_path
+    assert not gpu_initialised()
     try:
         out = np.memmap(name, dtype=dtype, mode="w+", shape=(n, k))
         del out
@@ -251,5 +274,6 @@ def harmonic_measure_5pt(dom, dtype=np.float64, workers=None, chunk=128, progres
         P = np.memmap(name, dtype=dtype, mode="r+", shape=(n, k))
     finally:
         _WORK.clear()
-        os.unlink(name)      # the mapping stays valid until P is released
+        if out_path is None:
+            os.unlink(name)      # the mapping stays valid until P is released
     return P
