@@ -226,6 +226,31 @@ dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t
                                    int32_t kind, float* out_dev, dd_error_bound* bounds,
                                    void* stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * Same arguments, fields and bounds as dd_batch_distance_fields (the same
+ * kernels run, so the fields are bit-identical), but the call's device
+ * scratch -- the target operands of the contraction, the target block of the
+ * many-target pass, the expanded truncated target rows -- is taken from a
+ * fixed buffer of DD_NOALLOC_SCRATCH_BYTES that the library holds on each GPU
+ * it runs on until the process ends, and the call allocates and frees nothing.
+ * The caller still passes targets, outputs and bounds.
+ *   DD_EINVAL   the call would need more scratch than the buffer holds (the
+ *               need grows with min(T, 256) and the kept columns; the FP64 rows
+ *               of a truncated handle loaded from FP64 values with a gemm_form
+ *               are the largest part); nothing has been enqueued.
+ * Every call on a GPU, from any context or thread, shares that GPU's buffer,
+ * which keeps the last call's contents: calls that overlap on one GPU race
+ * and give wrong fields, so a call may start only after the stream of the
+ * previous call has reached its end.  No contents need clearing between calls
+ * (each call writes, with kernels, every byte it reads; no memset is
+ * enqueued).  Asynchronous on `stream`. */
+#define DD_NOALLOC_SCRATCH_BYTES ((size_t)48 << 20)
+dd_status dd_batch_distance_fields_noalloc(dd_kernel* k, const int32_t* targets, int32_t T,
+                                           int32_t kind, float* out_dev, dd_error_bound* bounds,
+                                           void* stream);
+
 /* Trace T steepest-descent paths on precomputed fields (Section IV, edge-based
  * variant): from v = source[i], move to the neighbour with the smallest field
  * value (ties: lowest id) while it is strictly below the current value.

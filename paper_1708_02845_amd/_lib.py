@@ -11,6 +11,7 @@ DD_TV, DD_KL, DD_CHI2, DD_HELLINGER = 0, 1, 2, 3
 DD_FORM_NONE, DD_FORM_F32, DD_FORM_F16X3, DD_FORM_BF16X3 = -1, 0, 1, 2
 DD_CSR_F32, DD_CSR_F16 = 0, 1
 DD_PATH_REACHED, DD_PATH_STUCK, DD_PATH_MAX_STEPS = 0, 1, 2
+DD_NOALLOC_SCRATCH_BYTES = 48 << 20
 
 STATUS_NAMES = {0: "DD_OK", 1: "DD_EINVAL", 2: "DD_ENOMEM", 3: "DD_EDEVICE", 4: "DD_ESTATE",
                 5: "DD_ENOCONV"}
@@ -88,6 +89,9 @@ EXPORTS = {
                                          C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                          C.c_double, C.c_int32, C.c_int32,
                                          C.POINTER(dd_grid_solve_stats), C.c_void_p]),
+    "dd_batch_distance_fields_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                                   C.c_void_p, C.POINTER(dd_error_bound),
+                                                   C.c_void_p]),
     "dd_free_kernel": (C.c_int, [C.c_void_p]),
     "dd_last_error": (C.c_char_p, []),
 }

@@ -234,13 +234,21 @@ class Kernel:
         """(fields [T, N], list of (abs, rel) bounds) for T targets: KL through the
         contraction when the handle has an operand, the pass over the stored rows
         on a truncated handle from 8 targets, else one streaming pass each."""
+        return self._batch(self._lib.dd_batch_distance_fields, targets, kind, out, stream)
+
+    def batch_fields_noalloc(self, targets, kind, out=None, stream=None):
+        """batch_fields with the library's fixed per-GPU scratch instead of
+        per-call device allocations (pass ``out`` to allocate nothing at all).
+        Calls on one GPU must not overlap."""
+        return self._batch(self._lib.dd_batch_distance_fields_noalloc, targets, kind, out, stream)
+
+    def _batch(self, fn, targets, kind, out, stream):
         t = np.ascontiguousarray(targets, dtype=np.int32)
         T = len(t)
         out = self._out((T, self.N), out)
         bounds = (L.dd_error_bound * max(T, 1))()
-        L.check(self._lib.dd_batch_distance_fields(self._h, C.c_void_p(t.ctypes.data), int(T),
-                                                   _kind(kind), C.c_void_p(out.data_ptr()),
-                                                   bounds, _stream_handle(stream)))
+        L.check(fn(self._h, C.c_void_p(t.ctypes.data), int(T), _kind(kind),
+                   C.c_void_p(out.data_ptr()), bounds, _stream_handle(stream)))
         return out, [bound_tuple(bounds[i]) for i in range(T)]
 
     # ---- paths ----

@@ -87,12 +87,46 @@ struct AsyncBuf {
   }
 };
 
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Device scratch of one batch call: stream-ordered allocations freed on the
+// same stream when the object goes out of scope, or, with a fixed buffer,
+// consecutive 256-byte-aligned slices of it (the caller has checked the total
+// against the buffer's size first).
+class CallScratch {
+ public:
+  CallScratch(hipStream_t s, unsigned char* fixed) : s_(s), fixed_(fixed) {}
+  ~CallScratch() {
+    for (void* p : owned_) (void)hipFreeAsync(p, s_);
+  }
+  CallScratch(const CallScratch&) = delete;
+  CallScratch& operator=(const CallScratch&) = delete;
+  hipError_t get(size_t n, void** p) {
+    if (fixed_) {
+      if (used_ + align256(n) > dd::kFixedScratchBytes) return hipErrorOutOfMemory;
+      *p = fixed_ + used_;
+      used_ += align256(n);
+      return hipSuccess;
+    }
+    const hipError_t e = hipMallocAsync(p, n ? n : 1, s_);
+    if (e == hipSuccess) owned_.push_back(*p);
+    return e;
+  }
+
+ private:
+  hipStream_t s_;
+  unsigned char* fixed_;
+  size_t used_ = 0;
+  std::vector<void*> owned_;
+};
+
 }  // namespace
 
 struct dd_ctx {
   uint32_t magic = kCtxMagic;
   int device = 0;
   std::atomic<int> live_kernels{0};   // loads and frees may come from several threads
+  void* scratch = nullptr;            // this device's fixed scratch (dd::fixed_scratch)
 };
 
 struct dd_kernel {
@@ -608,9 +642,12 @@ dd_status dd_create(int device, dd_ctx** out) {
   if (device < 0 || device >= n) return fail(DD_EINVAL, "device %d of %d", device, n);
   HIP_OR(hipSetDevice(device));
   HIP_OR(dd::init_log_table());
+  void* fixed = nullptr;
+  HIP_OR(dd::fixed_scratch(device, &fixed));
   dd_ctx* c = new (std::nothrow) dd_ctx;
   if (!c) return fail(DD_ENOMEM, "host allocation failed");
   c->device = device;
+  c->scratch = fixed;
   *out = c;
   return DD_OK;
 }
@@ -898,49 +935,77 @@ dd_status dd_distance_field(dd_kernel* k, int32_t target, int32_t kind, float* o
   return DD_OK;
 }
 
-dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t T, int32_t kind,
-                                   float* out_dev, dd_error_bound* bounds, void* stream) {
+namespace {
+
+// Device scratch a batch call takes, in the order it takes it.
+size_t batch_scratch_bytes(const dd_kernel* k, int32_t T, int32_t kind) {
+  const int32_t tmax = std::min<int32_t>(T, dd::kMaxBatch);
+  if (kind == DD_KL && k->gemm_form != DD_FORM_NONE) {
+    dd::GemmView gv{nullptr, nullptr, nullptr, nullptr, k->lda, k->N, k->B, k->gemm_form};
+    size_t n = align256(dd::batch_kl_workspace(gv, tmax));
+    if (k->is_csr) {
+      const size_t tpad = (size_t)((tmax + 63) / 64 * 64);
+      n += align256(4 * tpad * (size_t)k->lda + (k->val64.p ? 8 * tpad * (size_t)k->B : 0));
+    }
+    return n;
+  }
+  if (k->is_csr && T >= kCsrBatchMin) return align256(dd::csr_batch_workspace(k->csr(), tmax));
+  return 0;
+}
+
+dd_status batch_fields(dd_kernel* k, const int32_t* targets, int32_t T, int32_t kind,
+                       float* out_dev, dd_error_bound* bounds, void* stream, bool fixed) {
   if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
   if (dd_status st = check_kind(k, kind)) return st;
   if (T <= 0 || !targets || !out_dev) return fail(DD_EINVAL, "T=%d, targets or out_dev null", T);
   for (int32_t i = 0; i < T; ++i)
     if (targets[i] < 0 || targets[i] >= k->N)
       return fail(DD_EINVAL, "targets[%d]=%d not in [0, %d)", i, targets[i], k->N);
+  if (fixed) {
+    const size_t need = batch_scratch_bytes(k, T, kind);
+    if (need > dd::kFixedScratchBytes)
+      return fail(DD_EINVAL, "this call needs %zu bytes of scratch; the fixed buffer holds %zu",
+                  need, dd::kFixedScratchBytes);
+    if (!k->ctx->scratch) return fail(DD_ESTATE, "context has no fixed scratch");
+  }
   HIP_OR(hipSetDevice(k->ctx->device));
   hipStream_t s = as_stream(stream);
+  CallScratch scr(s, fixed ? static_cast<unsigned char*>(k->ctx->scratch) : nullptr);
   if (kind == DD_KL && k->gemm_form != DD_FORM_NONE) {
     dd::GemmView gv{k->L32.as<const float>(), k->Lhi.as<const uint16_t>(),
                     k->Llo.as<const uint16_t>(), k->Off.as<const float>(),
                     k->lda, k->N, k->B, k->gemm_form};
     // up to 256 targets per launch; each launch reads the log-kernel about once
     const int32_t tmax = std::min<int32_t>(T, dd::kMaxBatch);
-    AsyncBuf ws(s), rows(s);
-    HIP_OR(ws.alloc(dd::batch_kl_workspace(gv, tmax)));
+    void* ws = nullptr;
+    HIP_OR(scr.get(dd::batch_kl_workspace(gv, tmax), &ws));
     // a truncated handle: the truncated target rows are expanded to dense
     // rows first (FP32 [rows][lda], and FP64 [rows][B] from FP64 values);
     // the target preparation reads the first n rows of a group of n
     const int32_t tpad = (tmax + 63) / 64 * 64;
     const bool f64 = k->is_csr && k->val64.p;
     const size_t r32 = 4 * (size_t)tpad * (size_t)k->lda;
-    if (k->is_csr) HIP_OR(rows.alloc(r32 + (f64 ? 8 * (size_t)tpad * (size_t)k->B : 0)));
+    void* rows = nullptr;
+    if (k->is_csr) HIP_OR(scr.get(r32 + (f64 ? 8 * (size_t)tpad * (size_t)k->B : 0), &rows));
     for (int32_t g0 = 0; g0 < T; g0 += dd::kMaxBatch) {
       const int32_t n = std::min<int32_t>(dd::kMaxBatch, T - g0);
       dd::TargetList tl;
       std::memset(&tl, 0, sizeof tl);
       for (int32_t i = 0; i < n; ++i) tl.t[i] = targets[g0 + i];
       if (!k->is_csr) {
-        HIP_OR(dd::launch_batch_kl(k->dense(), gv, tl, n, ws.p, out_dev + (int64_t)g0 * k->N, s));
+        HIP_OR(dd::launch_batch_kl(k->dense(), gv, tl, n, ws, out_dev + (int64_t)g0 * k->N, s));
         continue;
       }
-      float* d32 = rows.as<float>();
-      double* d64 = f64 ? reinterpret_cast<double*>(rows.as<unsigned char>() + r32) : nullptr;
+      float* d32 = static_cast<float*>(rows);
+      double* d64 = f64 ? reinterpret_cast<double*>(static_cast<unsigned char*>(rows) + r32)
+                        : nullptr;
       const int32_t rows_n = (n + 63) / 64 * 64;   // <= tpad
       HIP_OR(dd::launch_csr_rows_dense(k->csr(), tl, n, rows_n, k->lda, d32, d64, s));
       dd::TargetList id;
       std::memset(&id, 0, sizeof id);
       for (int32_t i = 0; i < n; ++i) id.t[i] = i;
       const dd::DenseView dv{d32, d64, k->lda, rows_n, k->B};
-      HIP_OR(dd::launch_batch_kl(dv, gv, id, n, ws.p, out_dev + (int64_t)g0 * k->N, s));
+      HIP_OR(dd::launch_batch_kl(dv, gv, id, n, ws, out_dev + (int64_t)g0 * k->N, s));
     }
     if (bounds)
       for (int32_t i = 0; i < T; ++i) bounds[i] = gemm_bound(k, targets[i]);
@@ -948,14 +1013,14 @@ dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t
   }
   if (k->is_csr && T >= kCsrBatchMin) {
     // one pass over the stored rows per group of up to 256 targets
-    AsyncBuf ws(s);
-    HIP_OR(ws.alloc(dd::csr_batch_workspace(k->csr(), std::min<int32_t>(T, dd::kMaxBatch))));
+    void* ws = nullptr;
+    HIP_OR(scr.get(dd::csr_batch_workspace(k->csr(), std::min<int32_t>(T, dd::kMaxBatch)), &ws));
     for (int32_t g0 = 0; g0 < T; g0 += dd::kMaxBatch) {
       const int32_t n = std::min<int32_t>(dd::kMaxBatch, T - g0);
       dd::TargetList tl;
       std::memset(&tl, 0, sizeof tl);
       for (int32_t i = 0; i < n; ++i) tl.t[i] = targets[g0 + i];
-      HIP_OR(dd::launch_csr_batch(k->csr(), tl, n, kind, tv_shift(k), ws.p,
+      HIP_OR(dd::launch_csr_batch(k->csr(), tl, n, kind, tv_shift(k), ws,
                                   out_dev + (int64_t)g0 * k->N, s));
     }
     if (bounds)
@@ -971,6 +1036,21 @@ dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t
     if (bounds) bounds[i] = field_bound(k, kind, targets[i]);
   }
   return DD_OK;
+}
+
+}  // namespace
+
+dd_status dd_batch_distance_fields(dd_kernel* k, const int32_t* targets, int32_t T, int32_t kind,
+                                   float* out_dev, dd_error_bound* bounds, void* stream) {
+  return batch_fields(k, targets, T, kind, out_dev, bounds, stream, false);
+}
+
+dd_status dd_batch_distance_fields_noalloc(dd_kernel* k, const int32_t* targets, int32_t T,
+                                           int32_t kind, float* out_dev, dd_error_bound* bounds,
+                                           void* stream) {
+  static_assert(DD_NOALLOC_SCRATCH_BYTES == dd::kFixedScratchBytes,
+                "the header states the fixed scratch size");
+  return batch_fields(k, targets, T, kind, out_dev, bounds, stream, true);
 }
 
 dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const int32_t* targets,

@@ -201,6 +201,12 @@ hipError_t launch_triangle_paths(TriArgs a, hipStream_t s);
 // Device table of the FP64 log used by the path kernels; once per device.
 hipError_t init_log_table();
 
+// Fixed per-GPU scratch of the allocation-free batch entry point
+// (scratch.hip): its size, and its device address on `device` (which must be
+// current), looked up once per device.
+constexpr size_t kFixedScratchBytes = size_t(48) << 20;
+hipError_t fixed_scratch(int device, void** out);
+
 int num_cus();
 
 }  // namespace dd
