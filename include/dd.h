@@ -81,8 +81,11 @@ typedef enum {
   DD_FORM_NONE = -1,   /* do not build a batched-KL operand */
   DD_FORM_F32 = 0,     /* FP32 log-kernel, FP32 MFMA */
   DD_FORM_F16X3 = 1,   /* FP16 hi+lo split of the log-kernel and of the targets, 3 MFMA products */
-  DD_FORM_BF16X3 = 2   /* BF16 hi+lo split (8 + 8 significant bits, no scaling of the targets),
+  DD_FORM_BF16X3 = 2,  /* BF16 hi+lo split (8 + 8 significant bits, no scaling of the targets),
                           3 MFMA products; a looser stated bound (3 x 2^-16 relative per term) */
+  DD_FORM_F16 = 3      /* the FP16 hi parts alone (11 significant bits each), one MFMA product:
+                          2 bytes per operand entry, half the bytes of F16X3; stated bound
+                          2^-10 + 2^-22 relative per term on top of the accumulation */
 } dd_form;
 
 /* Storage of the stored values of a truncated (CSR) handle, as read by the
@@ -190,6 +193,18 @@ dd_status dd_load_kernel_csr(dd_ctx* ctx, int32_t N, int32_t B, const int64_t* r
 
 /* Sizes and device memory held by a handle. */
 dd_status dd_kernel_get_info(const dd_kernel* k, dd_kernel_info* info);
+
+/* Device memory resident in a handle (the hbm_bytes of dd_kernel_get_info):
+ * admission control of further loads against free memory. */
+dd_status dd_kernel_footprint(const dd_kernel* k, size_t* hbm_bytes);
+
+/* Device scratch that one call on this handle allocates while it runs, on top
+ * of the resident bytes and of the caller's output buffers: fields_bytes for
+ * dd_batch_distance_fields with T targets of `kind`, paths_bytes for
+ * dd_trace_paths with T paths (0 without adjacency).  Either output nullable.
+ * Admission of a launch against free device memory. */
+dd_status dd_call_scratch_bytes(const dd_kernel* k, int32_t T, int32_t kind, size_t* fields_bytes,
+                                size_t* paths_bytes);
 
 /* Device bytes a dense load of an N x B matrix with these options would
  * need (admission control before loading). */
@@ -334,6 +349,28 @@ dd_status dd_trace_paths_triangles(dd_kernel* k, int32_t T, const int32_t* sourc
                                    int32_t max_steps, double* points_dev, int32_t* where_dev,
                                    int32_t* len_dev, int32_t* status_dev, void* stream);
 
+/* dd_trace_paths_triangles on FP64 fields (from dd_exact_distance_fields):
+ * every decision of the tracer -- the incident triangle, the exit edge, the
+ * slide along an edge, the corner snap -- is then taken on FP64 values, so
+ * the path is the one the exact field gives up to the rounding of its FP64
+ * sums.  fields_dev: device [T][N] FP64.  Other arguments as for
+ * dd_trace_paths_triangles.  Asynchronous on `stream`. */
+dd_status dd_trace_paths_triangles_f64(dd_kernel* k, int32_t T, const int32_t* sources,
+                                       const int32_t* targets, const double* fields_dev,
+                                       int32_t max_steps, double* points_dev, int32_t* where_dev,
+                                       int32_t* len_dev, int32_t* status_dev, void* stream);
+
+/* FP64 distance fields of T targets (eqs. 34-35, or the truncated forms on a
+ * CSR handle, or the other kinds on a dense handle) into out_dev[T][N]
+ * (device FP64): every term and sum in FP64 from the rows as loaded, the
+ * evaluation the FP64 re-decisions of the path entry points use (one FP64
+ * logarithm per entry for KL, so much slower than the FP32 fields); d(t, t)
+ * is 0.  For decisions that need the exact field, such as
+ * dd_trace_paths_triangles_f64.  targets: host [T], T <= 65535.
+ * Asynchronous on `stream`. */
+dd_status dd_exact_distance_fields(dd_kernel* k, const int32_t* targets, int32_t T, int32_t kind,
+                                   double* out_dev, void* stream);
+
 /* Spurious local minima of T fields (Section V, "Low resolution
  * discretizations"): a vertex v other than the target is a local minimum when
  * no neighbour u has d(u) < d(v).  Each vertex is classified against the
@@ -408,6 +445,27 @@ typedef struct {
 dd_status dd_grid_poisson_kernel(dd_ctx* ctx, int32_t G, const uint8_t* node_type,
                                  int32_t col_begin, int32_t ncols, float* P32, int64_t ld32,
                                  double* P64, int64_t ld64, double tol, int32_t max_iter,
+                                 int32_t batch, dd_grid_solve_stats* stats, void* stream);
+
+/* The discrete Dirichlet Green's function of a grid domain, the comparison
+ * distance D of the paper (Section IV, "The Dirichlet Green's function",
+ * eqs. 19-22): for each pole p = poles[c], the column
+ *     D_Ip = (-L_II)^{-1} e_p,
+ * harmonic at every interior vertex but p, zero on the boundary, positive and
+ * largest at p; paths descend -D towards p.  The operator, grid description,
+ * solver, tol, max_iter, batch and stats are those of dd_grid_poisson_kernel
+ * (on the right-triangle grid -L_II is the five-point stencil, so column c
+ * solves 4 u_v - sum_{interior n ~ v} u_n = [v = p]).
+ *   poles      host [T] interior-vertex ids in [0, N) (interior vertices in
+ *              ascending grid index, as the rows of P_IB)
+ *   D32        nullable device [T][ld32] FP32 (ld32 >= N): row c is D_Ip over
+ *              the interior vertices
+ *   D64        nullable device [T][ld64] FP64, likewise; at least one of the two
+ * DD_EINVAL for a pole outside [0, N) or a bad grid; DD_ENOCONV if a column is
+ * above tol at the cap.  Synchronous on `stream`. */
+dd_status dd_grid_green_function(dd_ctx* ctx, int32_t G, const uint8_t* node_type,
+                                 const int32_t* poles, int32_t T, float* D32, int64_t ld32,
+                                 double* D64, int64_t ld64, double tol, int32_t max_iter,
                                  int32_t batch, dd_grid_solve_stats* stats, void* stream);
 
 /* Release a handle and its device memory (waits for the device first). */

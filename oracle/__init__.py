@@ -19,12 +19,15 @@ Contents (each function cites the passage it follows):
                  count (Section IV "Gradient-descent path generation", Section V
                  "Low resolution discretizations").
 * ``disk``       unit-disk closed forms (Appendix eqs. A1, A6, A8, A10).
+* ``green``      discrete Dirichlet Green's function D_Ip = (-L_II)^{-1} e_p
+                 and the harmonic potential of eq. (23) (Section IV, eqs.
+                 19-23): the comparison distance D.
 
 Precision: FP64 throughout.  Inputs handed to the library in FP32 are upcast
 to FP64 before the oracle sees them, so oracle and library read the same
 numbers.
 """
 
-from . import fem, poisson, divergence, path, disk
+from . import fem, poisson, divergence, path, disk, green
 
-__all__ = ["fem", "poisson", "divergence", "path", "disk"]
+__all__ = ["fem", "poisson", "divergence", "path", "disk", "green"]

@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(HERE, "libdd.so")
 
 DD_OK, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ESTATE, DD_ENOCONV = range(6)
 DD_TV, DD_KL, DD_CHI2, DD_HELLINGER = 0, 1, 2, 3
-DD_FORM_NONE, DD_FORM_F32, DD_FORM_F16X3, DD_FORM_BF16X3 = -1, 0, 1, 2
+DD_FORM_NONE, DD_FORM_F32, DD_FORM_F16X3, DD_FORM_BF16X3, DD_FORM_F16 = -1, 0, 1, 2, 3
 DD_CSR_F32, DD_CSR_F16 = 0, 1
 DD_PATH_REACHED, DD_PATH_STUCK, DD_PATH_MAX_STEPS = 0, 1, 2
 DD_NOALLOC_SCRATCH_BYTES = 48 << 20
@@ -92,6 +92,18 @@ EXPORTS = {
     "dd_batch_distance_fields_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                                    C.c_void_p, C.POINTER(dd_error_bound),
                                                    C.c_void_p]),
+    "dd_kernel_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "dd_call_scratch_bytes": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
+                                        C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "dd_grid_green_function": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                         C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                         C.c_double, C.c_int32, C.c_int32,
+                                         C.POINTER(dd_grid_solve_stats), C.c_void_p]),
+    "dd_trace_paths_triangles_f64": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                               C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                               C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dd_exact_distance_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                           C.c_void_p, C.c_void_p]),
     "dd_free_kernel": (C.c_int, [C.c_void_p]),
     "dd_last_error": (C.c_char_p, []),
 }

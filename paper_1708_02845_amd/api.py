@@ -14,7 +14,7 @@ from . import _lib as L
 KINDS = {"tv": L.DD_TV, "kl": L.DD_KL, "chi2": L.DD_CHI2, "hellinger": L.DD_HELLINGER}
 KINDS.update({v: v for v in list(KINDS.values())})
 FORMS = {None: L.DD_FORM_NONE, "none": L.DD_FORM_NONE, "f32": L.DD_FORM_F32,
-         "f16x3": L.DD_FORM_F16X3, "bf16x3": L.DD_FORM_BF16X3}
+         "f16x3": L.DD_FORM_F16X3, "bf16x3": L.DD_FORM_BF16X3, "f16": L.DD_FORM_F16}
 CSR_VALUES = {"f32": L.DD_CSR_F32, "f16": L.DD_CSR_F16}
 PATH_STATUS = {L.DD_PATH_REACHED: "reached", L.DD_PATH_STUCK: "stuck",
                L.DD_PATH_MAX_STEPS: "max_steps"}
@@ -121,6 +121,39 @@ class Context:
         return out[:, :count], stats
 
 
+    def grid_green_function(self, node_type, poles, tol=1e-12, max_iter=1000, batch=0,
+                            dtype="f32", out=None, stream=None):
+        """Dirichlet Green's functions D_Ip = (-L_II)^{-1} e_p of a grid domain for
+        the interior vertices p in ``poles``, computed on the device.  Returns
+        (D tensor [T, N] of the dtype, one field per pole, stats dict)."""
+        torch = _torch()
+        nt = np.ascontiguousarray(np.asarray(node_type, dtype=np.uint8).reshape(-1))
+        G = int(round(len(nt) ** 0.5))
+        if G * G != len(nt):
+            raise ValueError("node_type is not a square grid")
+        N = int((nt == 1).sum())
+        pl = np.ascontiguousarray(poles, dtype=np.int32)
+        T = len(pl)
+        tdt = {"f32": torch.float32, "f64": torch.float64}[dtype]
+        if out is None:
+            out = torch.empty((T, N), dtype=tdt, device=f"cuda:{self.device}")
+        if out.dtype != tdt or out.dim() != 2 or out.shape[0] != T or out.shape[1] < N \
+                or out.stride(1) != 1:
+            raise ValueError("out must be a row-major [T, >= N] tensor of the dtype")
+        st = L.dd_grid_solve_stats()
+        ptr = C.c_void_p(out.data_ptr())
+        ld = out.stride(0)
+        L.check(self._lib.dd_grid_green_function(
+            self._h, G, nt.ctypes.data_as(C.c_void_p), C.c_void_p(pl.ctypes.data), T,
+            ptr if dtype == "f32" else None, ld if dtype == "f32" else 0,
+            ptr if dtype == "f64" else None, ld if dtype == "f64" else 0,
+            float(tol), int(max_iter), int(batch), C.byref(st), _stream_handle(stream)))
+        stats = {"iterations": st.iterations, "batches": st.batches, "levels": st.levels,
+                 "total_iterations": st.total_iterations,
+                 "max_rel_residual": st.max_rel_residual}
+        return out[:, :N], stats
+
+
 class Kernel:
     """A resident Poisson-kernel matrix (dense or truncated) on the device."""
 
@@ -145,7 +178,7 @@ class Kernel:
         """Load an N x B matrix given as a numpy array or a torch tensor (any device).
         With tau > 0 the handle keeps the truncation, its values read as FP32 or,
         with csr_values="f16", as FP16 scaled per row.  gemm_form ("f32", "f16x3",
-        "bf16x3") builds the batched-KL contraction operand; with tau > 0 it is
+        "bf16x3", "f16") builds the batched-KL contraction operand; with tau > 0 it is
         the floored log-kernel, and KL_tau of many targets runs as one
         contraction (FP32 values only)."""
         torch = _torch()
@@ -201,6 +234,20 @@ class Kernel:
         out = C.c_size_t()
         L.check(lib.dd_dense_footprint(int(N), int(B), int(bool(f64)), C.byref(opts), C.byref(out)))
         return out.value
+
+    def footprint(self):
+        """Device bytes resident in the handle."""
+        out = C.c_size_t()
+        L.check(self._lib.dd_kernel_footprint(self._h, C.byref(out)))
+        return out.value
+
+    def call_scratch(self, T, kind="kl"):
+        """(batch_fields scratch bytes, trace_paths scratch bytes) of calls with T
+        targets / paths: device memory a launch allocates beyond its outputs."""
+        fb, pb = C.c_size_t(), C.c_size_t()
+        L.check(self._lib.dd_call_scratch_bytes(self._h, int(T), _kind(kind), C.byref(fb),
+                                                C.byref(pb)))
+        return fb.value, pb.value
 
     def free(self):
         if self._h:
@@ -310,20 +357,37 @@ class Kernel:
         L.check(self._lib.dd_attach_mesh(self._h, int(f.shape[0]), C.c_void_p(f.ctypes.data),
                                          C.c_void_p(c.ctypes.data)))
 
+    def exact_fields(self, targets, kind, out=None, stream=None):
+        """FP64 fields [T, N] of T targets, every term and sum in FP64."""
+        torch = _torch()
+        t = np.ascontiguousarray(targets, dtype=np.int32)
+        T = len(t)
+        if out is None:
+            out = torch.empty((T, self.N), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() < T * self.N:
+            raise ValueError("out must be a contiguous float64 tensor of T x N")
+        L.check(self._lib.dd_exact_distance_fields(self._h, C.c_void_p(t.ctypes.data), int(T),
+                                                   _kind(kind), C.c_void_p(out.data_ptr()),
+                                                   _stream_handle(stream)))
+        return out
+
     def trace_paths_triangles(self, sources, targets, fields, max_steps, stream=None):
         """Device tensors (points [T, max_steps+1, 2] f64, where [T, max_steps+1, 2] i32,
-        len [T], status [T]) of triangle-based paths on the given fields."""
+        len [T], status [T]) of triangle-based paths on the given fields (FP32, or
+        FP64 fields from exact_fields)."""
         torch = _torch()
         s = np.ascontiguousarray(sources, dtype=np.int32)
         t = np.ascontiguousarray(targets, dtype=np.int32)
         T = len(s)
         dev = f"cuda:{self.ctx.device}"
-        if not fields.is_contiguous() or fields.dtype != torch.float32:
-            raise ValueError("fields must be contiguous float32")
+        if not fields.is_contiguous() or fields.dtype not in (torch.float32, torch.float64):
+            raise ValueError("fields must be contiguous float32 or float64")
+        fn = (self._lib.dd_trace_paths_triangles if fields.dtype == torch.float32
+              else self._lib.dd_trace_paths_triangles_f64)
         pts = torch.empty((T, max_steps + 1, 2), dtype=torch.float64, device=dev)
         wh = torch.empty((T, max_steps + 1, 2), dtype=torch.int32, device=dev)
         info = torch.empty((2, T), dtype=torch.int32, device=dev)
-        L.check(self._lib.dd_trace_paths_triangles(
+        L.check(fn(
             self._h, int(T), C.c_void_p(s.ctypes.data), C.c_void_p(t.ctypes.data),
             C.c_void_p(fields.data_ptr()), int(max_steps), C.c_void_p(pts.data_ptr()),
             C.c_void_p(wh.data_ptr()), C.c_void_p(info[0].data_ptr()),

@@ -141,7 +141,8 @@ __global__ __launch_bounds__(256) void trunc_fill_kernel(DenseView v, const doub
 }
 
 // l_xb = log P_xb - o_x with o_x = log max_b P_xb (natural log, FP64 then
-// rounded): FP32, or an FP16 (form 1) or BF16 (form 2) hi + lo split, written
+// rounded): FP32, an FP16 (form 1) or BF16 (form 2) hi + lo split, or the FP16
+// hi part alone (form 3), written
 // in the tiled layout
 // of the contraction operand (padding rows are zeroed by the caller).
 __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, int64_t lda,
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(256) void log_forms_kernel(DenseView v, int form, i
       const _Float16 hi = (_Float16)l;
       const _Float16 lo = (_Float16)(l - (double)hi);
       lhi[at] = __builtin_bit_cast(uint16_t, hi);
-      llo[at] = __builtin_bit_cast(uint16_t, lo);
+      if (form == 1) llo[at] = __builtin_bit_cast(uint16_t, lo);
     }
   }
   if (__ballot(nz) != 0ull && lane == 0) atomicAdd(zeros, 1);

@@ -247,6 +247,7 @@ size_t dense_bytes(int64_t N, int64_t B, int is_f64, const dd_load_opts& o) {
   if (is_f64) b += (size_t)(N * B * 8);
   if (o.gemm_form == DD_FORM_F32 || o.gemm_form == DD_FORM_F16X3 || o.gemm_form == DD_FORM_BF16X3)
     b += (size_t)(dd::gemm_rows_padded(N) * lda * 4) + (size_t)N * 4;
+  if (o.gemm_form == DD_FORM_F16) b += (size_t)(dd::gemm_rows_padded(N) * lda * 2) + (size_t)N * 4;
   return b;
 }
 
@@ -366,13 +367,18 @@ dd_error_bound gemm_bound(const dd_kernel* k, int32_t t) {
     // sums to at most W_t, so the weight of the products is at most
     // W_t lfloor; the FP32 rounding of FP64 target values adds u per term
     const double c = k->gemm_form == DD_FORM_F32 ? 35.0 : 42.0;
-    const double split = k->gemm_form == DD_FORM_BF16X3 ? 3.0 * std::ldexp(1.0, -16) : 0.0;
+    const double split = k->gemm_form == DD_FORM_BF16X3 ? 3.0 * std::ldexp(1.0, -16)
+                         : k->gemm_form == DD_FORM_F16 ? std::ldexp(1.0, -10) + std::ldexp(1.0, -22)
+                                                        : 0.0;
     const double W = k->W_host[t];
     dd_error_bound b;
     b.rel = 2.0 * ((c + 1.0) * kU + split);
     b.abs = 2.0 * (c * kU + split + (k->val64.p ? kU : 0.0)) * W * k->lfloor;
     if (k->gemm_form == DD_FORM_F16X3)
       b.abs += 2.0 * std::ldexp(1.0, -39) * (double)k->B * std::max(88.0, k->lfloor);
+    if (k->gemm_form == DD_FORM_F16)
+      b.abs += 2.0 * (std::ldexp(1.0, -25) * W +
+                      std::ldexp(1.0, -38) * (double)k->B * std::max(88.0, k->lfloor));
     if (k->gemm_form == DD_FORM_BF16X3)
       b.abs += 2.0 * std::ldexp(1.0, -125) * (double)k->B * (104.0 + k->lfloor + W);
     return b;
@@ -381,14 +387,21 @@ dd_error_bound gemm_bound(const dd_kernel* k, int32_t t) {
   const double W = k->W_host[t];
   // BF16X3: hi+lo of l and of q each within 2^-16 relative, the dropped
   // lo*lo product 2^-16: 3 x 2^-16 relative per term on top of the
-  // accumulation (F16X3's terms are 2^-22 and inside c).
+  // accumulation (F16X3's terms are 2^-22 and inside c).  F16: l and q*s_t
+  // each rounded once to FP16, 2^-11 relative each, 2^-10 + 2^-22 per term.
   const double c = k->gemm_form == DD_FORM_F32 ? 35.0 : 42.0;
-  const double split = k->gemm_form == DD_FORM_BF16X3 ? 3.0 * std::ldexp(1.0, -16) : 0.0;
+  const double split = k->gemm_form == DD_FORM_BF16X3 ? 3.0 * std::ldexp(1.0, -16)
+                       : k->gemm_form == DD_FORM_F16  ? std::ldexp(1.0, -10) + std::ldexp(1.0, -22)
+                                                      : 0.0;
   dd_error_bound b;
   b.rel = (c + 1.0) * kU + split;
   b.abs = (c * kU + split) * (H + std::max(0.0, k->omax) * W) +
           (k->is_f64 ? kU * (W + 2.0 * H) : 0.0);
   if (k->gemm_form == DD_FORM_F16X3) b.abs += std::ldexp(1.0, -39) * (double)k->B * 88.0;
+  // F16: an l below the FP16 normal range is within 2^-25 (times q <= W_t in
+  // sum), a q s_t below it within 2^-25 / s_t <= 2^-38 (times |l| <= 88 per entry)
+  if (k->gemm_form == DD_FORM_F16)
+    b.abs += std::ldexp(1.0, -25) * W + std::ldexp(1.0, -38) * (double)k->B * 88.0;
   // BF16 subnormal floors: a lo part below 2^-126 (if flushed) loses under
   // 2^-126 times the other operand (|l| <= 104 + max(0, o_max), q <= W_t) per
   // entry
@@ -595,8 +608,10 @@ dd_status build_gemm_operand(dd_kernel* k, int form, const double* floor) {
   }
   if (!e && form != DD_FORM_F32) {
     e = k->Lhi.alloc(2 * elems);
-    if (!e) e = k->Llo.alloc(2 * elems);
     if (!e) e = hipMemset(k->Lhi.p, 0, 2 * elems);
+  }
+  if (!e && (form == DD_FORM_F16X3 || form == DD_FORM_BF16X3)) {
+    e = k->Llo.alloc(2 * elems);
     if (!e) e = hipMemset(k->Llo.p, 0, 2 * elems);
   }
   if (!e) e = dd::launch_log_forms(k->dense(), form, k->lda, k->L32.as<float>(),
@@ -678,7 +693,7 @@ dd_status dd_load_kernel_dense(dd_ctx* ctx, int32_t N, int32_t B, const void* P,
   if (B > kMaxB) return fail(DD_EINVAL, "B=%d exceeds the supported %d columns", B, kMaxB);
   const dd_load_opts o = opts ? *opts : default_opts();
   if (o.gemm_form != DD_FORM_NONE && o.gemm_form != DD_FORM_F32 && o.gemm_form != DD_FORM_F16X3 &&
-      o.gemm_form != DD_FORM_BF16X3)
+      o.gemm_form != DD_FORM_BF16X3 && o.gemm_form != DD_FORM_F16)
     return fail(DD_EINVAL, "unknown gemm_form %d", o.gemm_form);
   if (!(o.tau >= 0.0) || !std::isfinite(o.tau) || o.tau > 1.0)
     return fail(DD_EINVAL, "tau must be in [0, 1]");
@@ -1053,6 +1068,43 @@ dd_status dd_batch_distance_fields_noalloc(dd_kernel* k, const int32_t* targets,
   return batch_fields(k, targets, T, kind, out_dev, bounds, stream, true);
 }
 
+namespace {
+
+// Scratch of dd_trace_paths: [sources, targets, bounds when T is large]
+// [FP64 target rows, their logs, constants].
+struct PathScratch {
+  bool inl;
+  size_t n_small, o_row, total;
+};
+
+PathScratch path_scratch(const dd_kernel* k, int32_t T) {
+  PathScratch l;
+  l.inl = T <= dd::kInlinePaths;
+  l.n_small = l.inl ? 0 : ((8 * (size_t)T + 15) & ~size_t(15)) + sizeof(dd::Bound) * T;
+  l.o_row = align256(l.n_small);
+  l.total = l.o_row + 16 * (size_t)T * (size_t)k->B + 32 * (size_t)T;
+  return l;
+}
+
+}  // namespace
+
+dd_status dd_kernel_footprint(const dd_kernel* k, size_t* hbm_bytes) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (!hbm_bytes) return fail(DD_EINVAL, "hbm_bytes is null");
+  *hbm_bytes = k->footprint();
+  return DD_OK;
+}
+
+dd_status dd_call_scratch_bytes(const dd_kernel* k, int32_t T, int32_t kind, size_t* fields_bytes,
+                                size_t* paths_bytes) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (T <= 0) return fail(DD_EINVAL, "T=%d", T);
+  if (dd_status st = check_kind(k, kind)) return st;
+  if (fields_bytes) *fields_bytes = batch_scratch_bytes(k, T, kind);
+  if (paths_bytes) *paths_bytes = k->has_adj ? path_scratch(k, T).total : 0;
+  return DD_OK;
+}
+
 dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const int32_t* targets,
                          int32_t kind, const float* fields_dev, const dd_error_bound* bounds,
                          int32_t max_steps, int32_t* path_dev, int32_t* len_dev,
@@ -1086,16 +1138,11 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
   a.max_steps = max_steps;
   a.kind = kind;
   a.is_csr = k->is_csr;
-  // scratch: [sources, targets, bounds when T is large] [csr target rows] [neighbour values]
-  const bool inl = T <= dd::kInlinePaths;
-  const size_t o_small = 0;
-  const size_t n_small = inl ? 0 : ((8 * (size_t)T + 15) & ~size_t(15)) + sizeof(dd::Bound) * T;
-  const size_t o_row = (o_small + n_small + 255) & ~size_t(255);
-  const size_t n_row = 16 * (size_t)T * (size_t)k->B + 32 * (size_t)T;
-  const size_t o_nv = (o_row + n_row + 255) & ~size_t(255);
-  const size_t n_nv = 4 * (size_t)T * (size_t)k->N * (size_t)k->adj_w;
+  const PathScratch lay = path_scratch(k, T);
+  const bool inl = lay.inl;
+  const size_t n_small = lay.n_small, o_row = lay.o_row;
   AsyncBuf ws(s);
-  HIP_OR(ws.alloc(o_nv + n_nv));
+  HIP_OR(ws.alloc(lay.total));
   unsigned char* base = ws.as<unsigned char>();
   std::vector<unsigned char> host;
   if (inl) {
@@ -1129,9 +1176,6 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
     a.tlog = tlog;
     a.tconst = tcon;
   }
-  float* nv = reinterpret_cast<float*>(base + o_nv);
-  HIP_OR(dd::launch_neighbor_values(a, k->N, nv, s));
-  a.nv = nv;
   HIP_OR(dd::launch_paths(k->dense(), k->csr(), a, s));
   return DD_OK;
 }
@@ -1285,15 +1329,19 @@ dd_status dd_attach_mesh(dd_kernel* k, int32_t n_faces, const int32_t* faces, co
   return DD_OK;
 }
 
-dd_status dd_trace_paths_triangles(dd_kernel* k, int32_t T, const int32_t* sources,
-                                   const int32_t* targets, const float* fields_dev,
-                                   int32_t max_steps, double* points_dev, int32_t* where_dev,
-                                   int32_t* len_dev, int32_t* status_dev, void* stream) {
+}  // extern "C"
+
+namespace {
+
+dd_status triangle_paths(dd_kernel* k, int32_t T, const int32_t* sources, const int32_t* targets,
+                         const float* fields_dev, const double* fields64_dev, int32_t max_steps,
+                         double* points_dev, int32_t* where_dev, int32_t* len_dev,
+                         int32_t* status_dev, void* stream) {
   if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
   if (!k->has_mesh) return fail(DD_EINVAL, "no mesh attached (dd_attach_mesh)");
   if (!k->has_adj) return fail(DD_EINVAL, "kernel was loaded without adjacency");
-  if (T <= 0 || !sources || !targets || !fields_dev || !points_dev || !where_dev || !len_dev ||
-      !status_dev)
+  if (T <= 0 || !sources || !targets || (!fields_dev && !fields64_dev) || !points_dev ||
+      !where_dev || !len_dev || !status_dev)
     return fail(DD_EINVAL, "T=%d or a required pointer is null", T);
   if (max_steps < 0) return fail(DD_EINVAL, "max_steps=%d", max_steps);
   for (int32_t i = 0; i < T; ++i)
@@ -1318,6 +1366,7 @@ dd_status dd_trace_paths_triangles(dd_kernel* k, int32_t T, const int32_t* sourc
   a.adj = k->adj.as<const int32_t>();
   a.adj_w = k->adj_w;
   a.fields = fields_dev;
+  a.fields64 = fields64_dev;
   a.sources = ws.as<const int32_t>();
   a.targets = ws.as<const int32_t>() + T;
   a.points = points_dev;
@@ -1328,6 +1377,69 @@ dd_status dd_trace_paths_triangles(dd_kernel* k, int32_t T, const int32_t* sourc
   a.N = k->N;
   a.max_steps = max_steps;
   HIP_OR(dd::launch_triangle_paths(a, s));
+  return DD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dd_status dd_trace_paths_triangles(dd_kernel* k, int32_t T, const int32_t* sources,
+                                   const int32_t* targets, const float* fields_dev,
+                                   int32_t max_steps, double* points_dev, int32_t* where_dev,
+                                   int32_t* len_dev, int32_t* status_dev, void* stream) {
+  if (!fields_dev) return fail(DD_EINVAL, "fields_dev is null");
+  return triangle_paths(k, T, sources, targets, fields_dev, nullptr, max_steps, points_dev,
+                        where_dev, len_dev, status_dev, stream);
+}
+
+dd_status dd_trace_paths_triangles_f64(dd_kernel* k, int32_t T, const int32_t* sources,
+                                       const int32_t* targets, const double* fields_dev,
+                                       int32_t max_steps, double* points_dev, int32_t* where_dev,
+                                       int32_t* len_dev, int32_t* status_dev, void* stream) {
+  if (!fields_dev) return fail(DD_EINVAL, "fields_dev is null");
+  return triangle_paths(k, T, sources, targets, nullptr, fields_dev, max_steps, points_dev,
+                        where_dev, len_dev, status_dev, stream);
+}
+
+dd_status dd_exact_distance_fields(dd_kernel* k, const int32_t* targets, int32_t T, int32_t kind,
+                                   double* out_dev, void* stream) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (dd_status st = check_kind(k, kind)) return st;
+  if (T <= 0 || !targets || !out_dev) return fail(DD_EINVAL, "T=%d, targets or out_dev null", T);
+  if (T > 65535) return fail(DD_EINVAL, "T=%d above 65535 targets per call", T);
+  for (int32_t i = 0; i < T; ++i)
+    if (targets[i] < 0 || targets[i] >= k->N)
+      return fail(DD_EINVAL, "targets[%d]=%d not in [0, %d)", i, targets[i], k->N);
+  HIP_OR(hipSetDevice(k->ctx->device));
+  hipStream_t s = as_stream(stream);
+  dd::PathArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.T = T;
+  a.kind = kind;
+  a.is_csr = k->is_csr;
+  // scratch: [targets when T is large] [FP64 target rows, logs, constants]
+  const bool inl = T <= dd::kInlinePaths;
+  const size_t n_small = inl ? 0 : 4 * (size_t)T;
+  const size_t o_row = align256(n_small);
+  AsyncBuf ws(s);
+  HIP_OR(ws.alloc(o_row + 16 * (size_t)T * (size_t)k->B + 32 * (size_t)T));
+  unsigned char* base = ws.as<unsigned char>();
+  if (inl) {
+    for (int32_t i = 0; i < T; ++i) a.small.tgt[i] = targets[i];
+  } else {
+    // pageable source: the copy is staged before hipMemcpyAsync returns
+    HIP_OR(hipMemcpyAsync(base, targets, n_small, hipMemcpyHostToDevice, s));
+    a.targets = reinterpret_cast<const int32_t*>(base);
+  }
+  double* trow = reinterpret_cast<double*>(base + o_row);
+  double* tlog = trow + (size_t)T * (size_t)k->B;
+  double* tcon = tlog + (size_t)T * (size_t)k->B;
+  HIP_OR(dd::launch_target_rows(k->dense(), k->csr(), a, trow, tlog, tcon, s));
+  a.trow = trow;
+  a.tlog = tlog;
+  a.tconst = tcon;
+  HIP_OR(dd::launch_exact_fields(k->dense(), k->csr(), a, k->N, out_dev, s));
   return DD_OK;
 }
 
@@ -1453,18 +1565,23 @@ dd_status dd_plan_path(dd_kernel* k, int32_t source, int32_t target, int32_t kin
   return DD_OK;
 }
 
-dd_status dd_grid_poisson_kernel(dd_ctx* ctx, int32_t G, const uint8_t* node_type,
-                                 int32_t col_begin, int32_t ncols, float* P32, int64_t ld32,
-                                 double* P64, int64_t ld64, double tol, int32_t max_iter,
-                                 int32_t batch, dd_grid_solve_stats* stats, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Checks shared by the grid solves; counts the interior and boundary vertices.
+dd_status check_grid(const dd_ctx* ctx, int32_t G, const uint8_t* node_type, const void* o32,
+                     const void* o64, double tol, int32_t max_iter, int32_t batch,
+                     int64_t& n_int, int64_t& n_bnd) {
   if (!ctx_ok(ctx)) return fail(DD_ESTATE, "not a live context");
   if (G < 3 || G > 46340) return fail(DD_EINVAL, "G=%d outside [3, 46340]", G);
   if (!node_type) return fail(DD_EINVAL, "node_type is null");
-  if (!P32 && !P64) return fail(DD_EINVAL, "no output (P32 and P64 both null)");
+  if (!o32 && !o64) return fail(DD_EINVAL, "no output (both outputs null)");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(DD_EINVAL, "tol must be positive");
   if (max_iter < 1) return fail(DD_EINVAL, "max_iter must be >= 1");
   if (batch < 0 || batch % 64 != 0) return fail(DD_EINVAL, "batch %d is not a multiple of 64", batch);
-  int64_t n_int = 0, n_bnd = 0;
+  n_int = 0;
+  n_bnd = 0;
   for (int64_t j = 0; j < G; ++j)
     for (int64_t i = 0; i < G; ++i) {
       const uint8_t t = node_type[j * G + i];
@@ -1481,28 +1598,28 @@ dd_status dd_grid_poisson_kernel(dd_ctx* ctx, int32_t G, const uint8_t* node_typ
                     (long long)i, (long long)j);
     }
   if (n_int == 0 || n_bnd == 0) return fail(DD_EINVAL, "no interior or no boundary vertex");
-  if (col_begin < 0 || ncols < 1 || (int64_t)col_begin + ncols > n_bnd)
-    return fail(DD_EINVAL, "columns [%d, %d + %d) outside the %lld boundary vertices", col_begin,
-                col_begin, ncols, (long long)n_bnd);
-  if (P32 && ld32 < ncols) return fail(DD_EINVAL, "ld32=%lld < ncols=%d", (long long)ld32, ncols);
-  if (P64 && ld64 < ncols) return fail(DD_EINVAL, "ld64=%lld < ncols=%d", (long long)ld64, ncols);
-  HIP_OR(hipSetDevice(ctx->device));
+  return DD_OK;
+}
+
+// Columns per batch: the requested width, or the widest up to 1024 whose
+// workspace takes at most 90% of free memory.
+dd_status grid_batch(int32_t G, int32_t ncols, int32_t batch, int32_t& C) {
   size_t free_b = 0, total_b = 0;
   HIP_OR(hipMemGetInfo(&free_b, &total_b));
-  int32_t C = batch;
+  C = batch;
   if (C == 0) {
-    // the widest batch up to 1024 columns whose workspace takes at most
-    // 90% of free memory
     C = std::min<int32_t>(1024, (ncols + 63) / 64 * 64);
     while (C > 64 && dd::grid_poisson_workspace(G, C) > free_b / 10 * 9) C -= 64;
   }
   if (dd::grid_poisson_workspace(G, C) > free_b)
     return fail(DD_ENOMEM, "a batch of %d columns needs %zu bytes, %zu free", C,
                 dd::grid_poisson_workspace(G, C), free_b);
-  dd::GridSolveStats st{};
-  const hipError_t e = dd::grid_poisson(G, node_type, col_begin, ncols, C, tol, max_iter, P32,
-                                        ld32, P64, ld64, &st, static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return fail(DD_EDEVICE, "grid Poisson solve: %s", hipGetErrorString(e));
+  return DD_OK;
+}
+
+dd_status grid_result(hipError_t e, const dd::GridSolveStats& st, double tol,
+                      dd_grid_solve_stats* stats) {
+  if (e != hipSuccess) return fail(DD_EDEVICE, "grid solve: %s", hipGetErrorString(e));
   if (stats) {
     stats->iterations = st.iterations;
     stats->batches = st.batches;
@@ -1514,6 +1631,53 @@ dd_status dd_grid_poisson_kernel(dd_ctx* ctx, int32_t G, const uint8_t* node_typ
     return fail(DD_ENOCONV, "relative residual %.3e above tol %.3e after %d iterations",
                 st.max_rel_residual, tol, st.iterations);
   return DD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dd_status dd_grid_poisson_kernel(dd_ctx* ctx, int32_t G, const uint8_t* node_type,
+                                 int32_t col_begin, int32_t ncols, float* P32, int64_t ld32,
+                                 double* P64, int64_t ld64, double tol, int32_t max_iter,
+                                 int32_t batch, dd_grid_solve_stats* stats, void* stream) {
+  int64_t n_int = 0, n_bnd = 0;
+  if (dd_status st = check_grid(ctx, G, node_type, P32, P64, tol, max_iter, batch, n_int, n_bnd))
+    return st;
+  if (col_begin < 0 || ncols < 1 || (int64_t)col_begin + ncols > n_bnd)
+    return fail(DD_EINVAL, "columns [%d, %d + %d) outside the %lld boundary vertices", col_begin,
+                col_begin, ncols, (long long)n_bnd);
+  if (P32 && ld32 < ncols) return fail(DD_EINVAL, "ld32=%lld < ncols=%d", (long long)ld32, ncols);
+  if (P64 && ld64 < ncols) return fail(DD_EINVAL, "ld64=%lld < ncols=%d", (long long)ld64, ncols);
+  HIP_OR(hipSetDevice(ctx->device));
+  int32_t C = 0;
+  if (dd_status st = grid_batch(G, ncols, batch, C)) return st;
+  dd::GridSolveStats st{};
+  const hipError_t e = dd::grid_poisson(G, node_type, col_begin, ncols, C, tol, max_iter, P32,
+                                        ld32, P64, ld64, &st, static_cast<hipStream_t>(stream));
+  return grid_result(e, st, tol, stats);
+}
+
+dd_status dd_grid_green_function(dd_ctx* ctx, int32_t G, const uint8_t* node_type,
+                                 const int32_t* poles, int32_t T, float* D32, int64_t ld32,
+                                 double* D64, int64_t ld64, double tol, int32_t max_iter,
+                                 int32_t batch, dd_grid_solve_stats* stats, void* stream) {
+  int64_t n_int = 0, n_bnd = 0;
+  if (dd_status st = check_grid(ctx, G, node_type, D32, D64, tol, max_iter, batch, n_int, n_bnd))
+    return st;
+  if (T < 1 || !poles) return fail(DD_EINVAL, "T=%d or poles null", T);
+  for (int32_t i = 0; i < T; ++i)
+    if (poles[i] < 0 || poles[i] >= n_int)
+      return fail(DD_EINVAL, "poles[%d]=%d not in [0, %lld)", i, poles[i], (long long)n_int);
+  if (D32 && ld32 < n_int) return fail(DD_EINVAL, "ld32=%lld < N=%lld", (long long)ld32, (long long)n_int);
+  if (D64 && ld64 < n_int) return fail(DD_EINVAL, "ld64=%lld < N=%lld", (long long)ld64, (long long)n_int);
+  HIP_OR(hipSetDevice(ctx->device));
+  int32_t C = 0;
+  if (dd_status st = grid_batch(G, T, batch, C)) return st;
+  dd::GridSolveStats st{};
+  const hipError_t e = dd::grid_green(G, node_type, poles, T, C, tol, max_iter, D32, ld32, D64,
+                                      ld64, &st, static_cast<hipStream_t>(stream));
+  return grid_result(e, st, tol, stats);
 }
 
 dd_status dd_free_kernel(dd_kernel* k) {

@@ -114,6 +114,12 @@ size_t grid_poisson_workspace(int32_t G, int32_t C);
 hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, int32_t ncols,
                         int32_t C, double tol, int32_t max_iter, float* P32, int64_t ld32,
                         double* P64, int64_t ld64, GridSolveStats* st, hipStream_t s);
+// Dirichlet Green's functions D_Ip = (-L_II)^{-1} e_p of the same operator for
+// the interior vertices p = poles[c] (interior-local ids, validated), written
+// one per output row: D32[c][ld32], D64[c][ld64] over the interior rows.
+hipError_t grid_green(int32_t G, const uint8_t* node_type, const int32_t* poles, int32_t ncols,
+                      int32_t C, double tol, int32_t max_iter, float* D32, int64_t ld32,
+                      double* D64, int64_t ld64, GridSolveStats* st, hipStream_t s);
 
 // Truncated fields of many targets in one pass over the stored rows
 // (csr_batch.hip).  Up to kMaxBatch targets per launch; ws holds
@@ -140,7 +146,6 @@ struct PathArgs {
   const int32_t* adj;       // [N][adj_w] neighbour ids, -1 padded
   int32_t adj_w;
   const float* fields;      // [T][N]
-  const float* nv;          // [T][N][adj_w] field value of each neighbour slot (+inf pad)
   const Bound* bounds;      // [T] device, or nullptr when inline
   const int32_t* sources;   // [T] device, or nullptr when inline
   const int32_t* targets;   // [T] device, or nullptr when inline
@@ -161,11 +166,14 @@ struct PathArgs {
 };
 hipError_t launch_target_rows(DenseView dv, CsrView cv, PathArgs a, double* trow, double* tlog,
                               double* tconst, hipStream_t s);
-hipError_t launch_neighbor_values(PathArgs a, int32_t N, float* nv, hipStream_t s);
 hipError_t launch_paths(DenseView dv, CsrView cv, PathArgs a, hipStream_t s);
 // walk that evaluates FP64 distances on demand (no field): uses adj, sources,
 // targets, trow/tlog/tconst, path/len/status, rechecks (= rows evaluated)
 hipError_t launch_paths_on_demand(DenseView dv, CsrView cv, PathArgs a, hipStream_t s);
+// FP64 fields of T targets into out[T][N] (uses T, targets, kind, is_csr,
+// trow/tlog/tconst of PathArgs)
+hipError_t launch_exact_fields(DenseView dv, CsrView cv, PathArgs a, int32_t N, double* out,
+                               hipStream_t s);
 // KL over the truncated support of the target row, one streaming pass
 hipError_t launch_support_kl_field(DenseView v, int32_t target, double tau, int tau_relative,
                                    float* out, hipStream_t s);
@@ -187,7 +195,8 @@ struct TriArgs {
   int32_t vf_w;
   const int32_t* adj;       // [N][adj_w] neighbour ids, -1 padded
   int32_t adj_w;
-  const float* fields;      // [T][N]
+  const float* fields;      // [T][N] FP32, or
+  const double* fields64;   // [T][N] FP64 (exactly one of the two is set)
   const int32_t* sources;   // device [T]
   const int32_t* targets;   // device [T]
   double* points;           // [T][max_steps+1][2]

@@ -25,6 +25,8 @@
 //          + l_lo q_hi on v_mfma_f32_32x32x16_f16, divided by s_t at the end.
 //   BF16X3 the same split in BF16 (no scale: BF16 has the FP32 range) on
 //          v_mfma_f32_32x32x16_bf16; 8 + 8 significant bits per operand.
+//   F16    the hi parts only: l_hi q_hi on v_mfma_f32_32x32x16_f16, half the
+//          operand bytes of F16X3, 11 significant bits per operand.
 //
 // Both forms carry the FP32 accumulators into FP64 after every K-chunk of 64,
 // so the FP32 accumulation error is that of 64-term partial sums; H_t, W_t and
@@ -67,6 +69,7 @@ struct BatchOperand {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Target operands by form: FP32 (0), or hi + lo halves (1, 2; form 3 uses hi).
 static BatchOperand carve(GemmView gv, int Tpad, void* ws) {
   unsigned char* p = static_cast<unsigned char*>(ws);
   BatchOperand o{};
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(256) void batch_target_prep(DenseView dv, GemmView 
       M = fmax(M, red[2][i]);
     }
     double s = 1.0;
-    if (gv.form == 1 && M > 0.0) {
+    if ((gv.form == 1 || gv.form == 3) && M > 0.0) {
       int e = 0;
       frexp(M, &e);          // M in [2^(e-1), 2^e)
       s = ldexp(1.0, 14 - e);
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(256) void batch_target_prep(DenseView dv, GemmView 
       const _Float16 qh = (_Float16)q;
       const _Float16 ql = (_Float16)(q - (float)qh);
       o.bhi[(int64_t)j * gv.lda + k] = __builtin_bit_cast(uint16_t, qh);
-      o.blo[(int64_t)j * gv.lda + k] = __builtin_bit_cast(uint16_t, ql);
+      if (gv.form == 1) o.blo[(int64_t)j * gv.lda + k] = __builtin_bit_cast(uint16_t, ql);
     }
   }
 }
@@ -230,7 +233,9 @@ __device__ __forceinline__ floatx16 split3(u32x4 ah, u32x4 al, u32x4 bh, u32x4 b
   }
 }
 
-template <int NT, bool BF>
+// HI: the F16 form, hi parts only (one product per K step; the lo loads and
+// their registers drop out).
+template <int NT, bool BF, bool HI = false>
 __device__ __forceinline__ void gemm_split_body(GemmView gv, BatchOperand o, int32_t T,
                                                 int32_t groups, float* __restrict__ out) {
   int rb, grp;
@@ -254,7 +259,7 @@ __device__ __forceinline__ void gemm_split_body(GemmView gv, BatchOperand o, int
   const int64_t tile0 = (int64_t)rb * (GROWS * KC);
   const int64_t cstride = gemm_row_tiles(gv.N) * (GROWS * KC);
   const uint16_t* bhp = o.bhi + (int64_t)tbase * gv.lda;
-  const uint16_t* blp = o.blo + (int64_t)tbase * gv.lda;
+  const uint16_t* blp = HI ? nullptr : o.blo + (int64_t)tbase * gv.lda;
   // load q of this lane: row r, columns h*32 + q*8 .. + 8 of the tile (one
   // contiguous kilobyte per wave and load)
   const int64_t lane_off = (int64_t)(wv * 4 * 64 + lane) * 8;
@@ -284,7 +289,7 @@ __device__ __forceinline__ void gemm_split_body(GemmView gv, BatchOperand o, int
   // addresses as a wave-uniform base plus a 32-bit lane offset, so the loads
   // take the scalar-base form and keep few vector registers for addresses
   const uint16_t* abh = gv.lhi + tile0;
-  const uint16_t* abl = gv.llo + tile0;
+  const uint16_t* abl = HI ? nullptr : gv.llo + tile0;
   const int a_lane = (int)lane_off;
   int b_lane[SPT];
 #pragma unroll
@@ -294,20 +299,20 @@ __device__ __forceinline__ void gemm_split_body(GemmView gv, BatchOperand o, int
   }
   auto load_a = [&](int c, u32x4 (&dh)[4], u32x4 (&dl)[4]) {
     const uint16_t* bh_ = abh + (int64_t)c * cstride;
-    const uint16_t* bl_ = abl + (int64_t)c * cstride;
+    const uint16_t* bl_ = HI ? nullptr : abl + (int64_t)c * cstride;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       dh[q] = *reinterpret_cast<const u32x4*>(bh_ + (a_lane + q * 512));
-      dl[q] = *reinterpret_cast<const u32x4*>(bl_ + (a_lane + q * 512));
+      if constexpr (!HI) dl[q] = *reinterpret_cast<const u32x4*>(bl_ + (a_lane + q * 512));
     }
   };
   auto load_b = [&](int c, u32x4 (&dh)[SPT], u32x4 (&dl)[SPT]) {
     const uint16_t* bh_ = bhp + (int64_t)c * KC;
-    const uint16_t* bl_ = blp + (int64_t)c * KC;
+    const uint16_t* bl_ = HI ? nullptr : blp + (int64_t)c * KC;
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       dh[q] = *reinterpret_cast<const u32x4*>(bh_ + b_lane[q]);
-      dl[q] = *reinterpret_cast<const u32x4*>(bl_ + b_lane[q]);
+      if constexpr (!HI) dl[q] = *reinterpret_cast<const u32x4*>(bl_ + b_lane[q]);
     }
   };
   load_a(0, s0h, s0l);
@@ -331,7 +336,7 @@ __device__ __forceinline__ void gemm_split_body(GemmView gv, BatchOperand o, int
     for (int q = 0; q < SPT; ++q) {
       const int sg = threadIdx.x + q * 256;
       *reinterpret_cast<u32x4*>(&sbh[sg >> 3][(sg & 7) * 8]) = th[q];
-      *reinterpret_cast<u32x4*>(&sbl[sg >> 3][(sg & 7) * 8]) = tl[q];
+      if constexpr (!HI) *reinterpret_cast<u32x4*>(&sbl[sg >> 3][(sg & 7) * 8]) = tl[q];
     }
     __syncthreads();
     load_b(min(c + 2, last), th, tl);
@@ -341,8 +346,15 @@ __device__ __forceinline__ void gemm_split_body(GemmView gv, BatchOperand o, int
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
           const u32x4 b_h = *reinterpret_cast<const u32x4*>(&sbh[n * 32 + r][h * 32 + j * 8]);
-          const u32x4 b_l = *reinterpret_cast<const u32x4*>(&sbl[n * 32 + r][h * 32 + j * 8]);
-          acc[n] = split3<BF>(sh[j], sl[j], b_h, b_l, acc[n]);
+          if constexpr (HI) {
+            acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, sh[j]),
+                                                            __builtin_bit_cast(half8, b_h),
+                                                            acc[n], 0, 0, 0);
+          } else {
+            const u32x4 b_l =
+                *reinterpret_cast<const u32x4*>(&sbl[n * 32 + r][h * 32 + j * 8]);
+            acc[n] = split3<BF>(sh[j], sl[j], b_h, b_l, acc[n]);
+          }
         }
         // keep the B fragments of one K step live at a time (register budget)
         __builtin_amdgcn_sched_barrier(0);
@@ -379,6 +391,12 @@ template <int NT>
 __global__ __launch_bounds__(256, 2) void kl_gemm_bf16x3(GemmView gv, BatchOperand o, int32_t T,
                                                       int32_t groups, float* __restrict__ out) {
   gemm_split_body<NT, true>(gv, o, T, groups, out);
+}
+
+template <int NT>
+__global__ __launch_bounds__(256, 2) void kl_gemm_f16(GemmView gv, BatchOperand o, int32_t T,
+                                                   int32_t groups, float* __restrict__ out) {
+  gemm_split_body<NT, false, true>(gv, o, T, groups, out);
 }
 
 template <int NT>
@@ -490,6 +508,11 @@ hipError_t launch_batch_kl(DenseView dv, GemmView gv, TargetList tl, int32_t T, 
       hipLaunchKernelGGL(kl_gemm_bf16x3<1>, grid, dim3(256), 0, s, gv, o, T, groups, out);
     else
       hipLaunchKernelGGL(kl_gemm_bf16x3<2>, grid, dim3(256), 0, s, gv, o, T, groups, out);
+  } else if (gv.form == 3) {
+    if (Tpad == 32)
+      hipLaunchKernelGGL(kl_gemm_f16<1>, grid, dim3(256), 0, s, gv, o, T, groups, out);
+    else
+      hipLaunchKernelGGL(kl_gemm_f16<2>, grid, dim3(256), 0, s, gv, o, T, groups, out);
   } else {
     if (Tpad == 32)
       hipLaunchKernelGGL(kl_gemm_f16x3<1>, grid, dim3(256), 0, s, gv, o, T, groups, out);

@@ -5,10 +5,11 @@
 // or after max_steps moves.
 //
 // The walk is a chain of dependent steps, so its cost is latency per step.
-// A parallel gather first lays out, for every vertex, the field values of its
-// neighbour slots next to each other (nv[v][j] = d(adj[v][j])); a step then
-// needs one round of independent loads (ids and values of the current
-// vertex's row), followed by a scalar best/second-best selection.
+// A step needs one round of independent loads: lane j reads the field value
+// of the current vertex's j-th neighbour and (for rows of at most kPrefetchW
+// slots) that neighbour's own adjacency row, so the row of whichever
+// neighbour is chosen is already in registers for the next step; a scalar
+// best/second-best selection follows.
 //
 // Each decision is checked against the field's stated error bound: when the
 // best and the second-best neighbour (or the best neighbour and the current
@@ -126,17 +127,6 @@ __global__ __launch_bounds__(256) void target_rows_kernel(DenseView dv, CsrView 
   }
 }
 
-__global__ __launch_bounds__(256) void neighbor_values_kernel(PathArgs a, int32_t N, float* nv) {
-  const int64_t per = (int64_t)N * a.adj_w;
-  const int64_t total = per * a.T;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = idx / per;
-    const int32_t u = a.adj[idx - i * per];
-    nv[idx] = u >= 0 ? a.fields[i * N + u] : __builtin_inff();
-  }
-}
-
 // The KL terms are p (log p - log q); chi-squared (q - p)^2 / p (+inf for
 // q > 0 on p = 0); Hellinger (q - p)^2 / (sqrt q + sqrt p)^2, the
 // cancellation-free form of (sqrt q - sqrt p)^2.
@@ -218,6 +208,8 @@ constexpr int kQ = 24;
 // and the extra waves of the walk cost more than they save).
 constexpr int kPathThreads = 512;
 constexpr int kMaxParts = 4;
+// adjacency rows up to this width travel with the neighbours' values (see paths_kernel)
+constexpr int kPrefetchW = 8;
 constexpr int kSplitB = 4096;
 __host__ __device__ inline bool split_rows(int is_csr, int B) { return !is_csr && B >= kSplitB; }
 
@@ -389,7 +381,6 @@ __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrVi
   const int N = a.is_csr ? cv.N : dv.N;
   const int W = a.adj_w;
   const float* d = a.fields + (int64_t)i * N;
-  const float* nvi = a.nv + (int64_t)i * N * W;
   const Bound bnd = path_bound(a, i);
   const double ea = uniform(bnd.abs), er = uniform(bnd.rel);
   const int Bt = a.is_csr ? cv.B : dv.B;
@@ -421,6 +412,11 @@ __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrVi
   int status = 0;
   int rechecks = 0;
   if (threadIdx.x == 0) path[0] = v;
+  // lane j < W holds slot j of v's neighbour row; with W <= kPrefetchW every
+  // neighbour's own row is loaded in the same round as the neighbours' values,
+  // so the next vertex's row is in registers when the step is decided
+  const bool pre = W <= kPrefetchW;
+  int ul = lane < W ? adj[(int64_t)v * W + lane] : -1;
   for (;;) {
     // the walk state is wave-uniform; say so, so that its branches are scalar
     v = __builtin_amdgcn_readfirstlane(v);
@@ -434,11 +430,18 @@ __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrVi
       status = 2;
       break;
     }
-    int ul = -1;
+    // one round of independent loads: the neighbours' field values and, for
+    // narrow rows, the neighbours' own rows
     float vl = __builtin_inff();
-    if (lane < W) {
-      ul = adj[(int64_t)v * W + lane];
-      vl = nvi[(int64_t)v * W + lane];
+    int nrow[kPrefetchW];
+#pragma unroll
+    for (int q = 0; q < kPrefetchW; ++q) nrow[q] = -1;
+    if (ul >= 0) {
+      vl = d[ul];
+      if (pre)
+#pragma unroll
+        for (int q = 0; q < kPrefetchW; ++q)
+          if (q < W) nrow[q] = adj[(int64_t)ul * W + q];
     }
     const uint64_t live = __ballot(ul >= 0);
     if (live == 0) {
@@ -547,6 +550,19 @@ __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrVi
     v = next;
     if (threadIdx.x == 0) path[len] = v;
     ++len;
+    // the next vertex's neighbour row: from the lane that held it, or loaded
+    if (pre) {
+      const int ln = (int)__builtin_ctzll(__ballot(ul == next) & live);
+      int nu = -1;
+#pragma unroll
+      for (int q = 0; q < kPrefetchW; ++q) {
+        const int x = __builtin_amdgcn_readlane(nrow[q], ln);
+        if (lane == q) nu = x;
+      }
+      ul = lane < W ? nu : -1;
+    } else {
+      ul = lane < W ? adj[(int64_t)v * W + lane] : -1;
+    }
   }
   for (int k = len + threadIdx.x; k <= a.max_steps; k += blockDim.x) path[k] = -1;
   if (threadIdx.x == 0) {
@@ -804,20 +820,32 @@ hipError_t launch_resolve_minima(DenseView dv, CsrView cv, PathArgs a, int32_t N
   return hipGetLastError();
 }
 
+// FP64 fields: every row x of every target by exact_distance (one wave per
+// row), the evaluation the FP64 re-decisions use; the target's own entry is
+// 0 by definition (d(t, t) = 0 for every kind).  Grid: (row groups of 4, T).
+__global__ __launch_bounds__(256) void exact_fields_kernel(DenseView dv, CsrView cv, PathArgs a,
+                                                           int32_t N, double* out) {
+  const int i = blockIdx.y;
+  const int64_t x = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (x >= N) return;
+  const int Bt = a.is_csr ? cv.B : dv.B;
+  const int t = path_target(a, i);
+  const double d = exact_distance(dv, cv, a.is_csr, a.kind, a.trow + (int64_t)i * Bt,
+                                  a.tlog + (int64_t)i * Bt, a.tconst + (int64_t)i * 4, (int)x);
+  if ((threadIdx.x & 63) == 0) out[(int64_t)i * N + x] = x == t ? 0.0 : d;
+}
+
+hipError_t launch_exact_fields(DenseView dv, CsrView cv, PathArgs a, int32_t N, double* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(exact_fields_kernel, dim3((unsigned)((N + 3) / 4), (unsigned)a.T), dim3(256),
+                     0, s, dv, cv, a, N, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_target_rows(DenseView dv, CsrView cv, PathArgs a, double* trow, double* tlog,
                               double* tconst, hipStream_t s) {
   hipLaunchKernelGGL(target_rows_kernel, dim3(a.T), dim3(256), 0, s, dv, cv, a, trow, tlog,
                      tconst);
-  return hipGetLastError();
-}
-
-hipError_t launch_neighbor_values(PathArgs a, int32_t N, float* nv, hipStream_t s) {
-  const int64_t total = (int64_t)N * a.adj_w * a.T;
-  int64_t grid = (total + 255) / 256;
-  const int64_t cap = (int64_t)num_cus() * 8;
-  if (grid > cap) grid = cap;
-  if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(neighbor_values_kernel, dim3((unsigned)grid), dim3(256), 0, s, a, N, nv);
   return hipGetLastError();
 }
 

@@ -109,6 +109,14 @@ __global__ void pk_rhs(double* r, const uint8_t* act, int32_t G, int64_t C, cons
   }
 }
 
+// Right-hand sides of a batch of Green's functions: column c is the unit
+// vector of interior vertex src[c] (global grid id; r is zero on entry).
+__global__ void pk_rhs_point(double* r, int64_t C, const int32_t* src, int32_t ncols) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  r[(int64_t)src[c] * C + c] = 1.0;
+}
+
 // part = per-block partials of sum_v a_v b_v per column.
 __global__ __launch_bounds__(256) void pk_dot(const double* a, const double* b, const uint8_t* act,
                                               int32_t G, int64_t C, int groups, double* part) {
@@ -431,7 +439,8 @@ __global__ __launch_bounds__(1024) void pk_dot_final(const double* part, int64_t
 __global__ __launch_bounds__(256) void pk_write(const double* __restrict__ x, const uint8_t* act,
                                                 const int32_t* iloc, int32_t G, int64_t C,
                                                 int groups, int32_t ncols, float* P32,
-                                                int64_t ld32, double* P64, int64_t ld64) {
+                                                int64_t ld32, double* P64, int64_t ld64,
+                                                int trans) {
   const int64_t nodes = (int64_t)G * G;
   int64_t rb;
   int grp;
@@ -444,8 +453,13 @@ __global__ __launch_bounds__(256) void pk_write(const double* __restrict__ x, co
     if (!act[g] || c >= ncols) continue;
     const double v = fmax(x[g * C + c], 0.0);
     const int64_t row = iloc[g];
-    if (P32) P32[row * ld32 + c] = (float)v;
-    if (P64) P64[row * ld64 + c] = v;
+    if (trans) {   // column c is output row c (one field per pole)
+      if (P32) P32[c * ld32 + row] = (float)v;
+      if (P64) P64[c * ld64 + row] = v;
+    } else {
+      if (P32) P32[row * ld32 + c] = (float)v;
+      if (P64) P64[row * ld64 + c] = v;
+    }
   }
 }
 
@@ -493,9 +507,13 @@ size_t grid_poisson_workspace(int32_t G, int32_t C) {
   return bytes;
 }
 
-hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, int32_t ncols,
-                        int32_t C, double tol, int32_t max_iter, float* P32, int64_t ld32,
-                        double* P64, int64_t ld64, GridSolveStats* st, hipStream_t s) {
+// The two column families share the solver: boundary indicators (P_IB, row-
+// major output) or unit vectors of interior vertices (Green's functions,
+// one output row per column).
+static hipError_t grid_solve(int32_t G, const uint8_t* node_type, bool green,
+                             const int32_t* poles, int32_t col_begin, int32_t ncols, int32_t C,
+                             double tol, int32_t max_iter, float* P32, int64_t ld32, double* P64,
+                             int64_t ld64, GridSolveStats* st, hipStream_t s) {
   const int32_t L = grid_levels(G);
   const int64_t nodes = (int64_t)G * G;
   const int groups = C / 64;
@@ -503,13 +521,22 @@ hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, 
   std::vector<std::vector<uint8_t>> act(L);
   std::vector<int32_t> Gs(L);
   act[0].resize(nodes);
-  std::vector<int32_t> iloc(nodes, -1), bnd;
+  std::vector<int32_t> iloc(nodes, -1), bnd, ints;
   int32_t n_int = 0;
   for (int64_t g = 0; g < nodes; ++g) {
     act[0][g] = node_type[g] == 1;
-    if (node_type[g] == 1) iloc[g] = n_int++;
+    if (node_type[g] == 1) {
+      iloc[g] = n_int++;
+      ints.push_back((int32_t)g);
+    }
     if (node_type[g] == 2) bnd.push_back((int32_t)g);
   }
+  // global ids of the batch's sources: boundary vertices, or the poles
+  std::vector<int32_t> src;
+  if (green)
+    for (int32_t c = 0; c < ncols; ++c) src.push_back(ints[poles[c]]);
+  else
+    src.assign(bnd.begin() + col_begin, bnd.begin() + col_begin + ncols);
   Gs[0] = G;
   for (int32_t l = 1; l < L; ++l) {
     const int32_t Gf = Gs[l - 1], Gc = Gf / 2 + 1;
@@ -622,13 +649,16 @@ hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, 
   std::vector<double> h_rr(C), h_bb(C);
   for (int32_t c0 = 0; c0 < ncols; c0 += C) {
     const int32_t nb = ncols - c0 < C ? ncols - c0 : C;
-    PK_OR(hipMemcpyAsync(dbnd.p, bnd.data() + col_begin + c0, (size_t)nb * 4,
-                         hipMemcpyHostToDevice, s));
+    PK_OR(hipMemcpyAsync(dbnd.p, src.data() + c0, (size_t)nb * 4, hipMemcpyHostToDevice, s));
     fill(dr[0].p, (size_t)nodes * C);
     fill(x.p, (size_t)nodes * C);
     fill(done, (size_t)C);
-    hipLaunchKernelGGL(pk_rhs, dim3((nb + 63) / 64), dim3(64), 0, s, dr[0].as<double>(), a0, G,
-                       (int64_t)C, dbnd.as<int32_t>(), nb);
+    if (green)
+      hipLaunchKernelGGL(pk_rhs_point, dim3((nb + 63) / 64), dim3(64), 0, s, dr[0].as<double>(),
+                         (int64_t)C, dbnd.as<int32_t>(), nb);
+    else
+      hipLaunchKernelGGL(pk_rhs, dim3((nb + 63) / 64), dim3(64), 0, s, dr[0].as<double>(), a0, G,
+                         (int64_t)C, dbnd.as<int32_t>(), nb);
     hipLaunchKernelGGL(pk_dot, dim3(g0), dim3(256), 0, s, dr[0].as<double>(), dr[0].as<double>(),
                        a0, G, (int64_t)C, groups, part.as<double>());
     dot_final(nrb0, bb);
@@ -674,9 +704,10 @@ hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, 
     }
     hipLaunchKernelGGL(pk_axpy, dim3(g0), dim3(256), 0, s, x.as<double>(), p.as<double>(), alpha,
                        a0, G, (int64_t)C, groups);
+    float* o32 = P32 ? (green ? P32 + (int64_t)c0 * ld32 : P32 + c0) : nullptr;
+    double* o64 = P64 ? (green ? P64 + (int64_t)c0 * ld64 : P64 + c0) : nullptr;
     hipLaunchKernelGGL(pk_write, dim3(g0), dim3(256), 0, s, x.as<double>(), a0, dil.as<int32_t>(),
-                       G, (int64_t)C, groups, nb, P32 ? P32 + c0 : nullptr, ld32,
-                       P64 ? P64 + c0 : nullptr, ld64);
+                       G, (int64_t)C, groups, nb, o32, ld32, o64, ld64, green ? 1 : 0);
     PK_OR(hipGetLastError());
     st->batches += 1;
     if (!all) st->converged = 0;
@@ -686,6 +717,20 @@ hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, 
   }
   PK_OR(hipStreamSynchronize(s));   // the buffers are freed on return
   return hipSuccess;
+}
+
+hipError_t grid_poisson(int32_t G, const uint8_t* node_type, int32_t col_begin, int32_t ncols,
+                        int32_t C, double tol, int32_t max_iter, float* P32, int64_t ld32,
+                        double* P64, int64_t ld64, GridSolveStats* st, hipStream_t s) {
+  return grid_solve(G, node_type, false, nullptr, col_begin, ncols, C, tol, max_iter, P32, ld32,
+                    P64, ld64, st, s);
+}
+
+hipError_t grid_green(int32_t G, const uint8_t* node_type, const int32_t* poles, int32_t ncols,
+                      int32_t C, double tol, int32_t max_iter, float* D32, int64_t ld32,
+                      double* D64, int64_t ld64, GridSolveStats* st, hipStream_t s) {
+  return grid_solve(G, node_type, true, poles, 0, ncols, C, tol, max_iter, D32, ld32, D64, ld64,
+                    st, s);
 }
 
 }  // namespace dd

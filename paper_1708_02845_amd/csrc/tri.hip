@@ -21,8 +21,10 @@
 //
 // One wave per path.  The state is wave-uniform; at a vertex the incident
 // triangles (one per lane) are evaluated in parallel.  Geometry is FP64 on
-// the FP64 upcast of the given FP32 field, with contraction into FMA turned
-// off so that every product and sum is rounded as written.
+// the given field (an FP32 field upcast, or an FP64 field, on which every
+// decision is the one the exact field takes up to the rounding of its sums),
+// with contraction into FMA turned off so that every product and sum is
+// rounded as written.
 #include <math.h>
 
 #include "dd_internal.h"
@@ -84,11 +86,12 @@ __device__ __forceinline__ double lane_d(double x, int j) {
 
 #pragma clang fp contract(off)
 
-__global__ __launch_bounds__(64) void triangle_paths_kernel(TriArgs a) {
+template <typename F>
+__global__ __launch_bounds__(64) void triangle_paths_kernel(TriArgs a, const F* fields) {
   const int i = blockIdx.x;
   const int lane = threadIdx.x;
   const int N = a.N;
-  const float* d = a.fields + (int64_t)i * N;
+  const F* d = fields + (int64_t)i * N;
   double* pts = a.points + (int64_t)i * (a.max_steps + 1) * 2;
   int32_t* wh = a.where + (int64_t)i * (a.max_steps + 1) * 2;
   const int t = __builtin_amdgcn_readfirstlane(a.targets[i]);
@@ -281,7 +284,10 @@ __global__ __launch_bounds__(64) void triangle_paths_kernel(TriArgs a) {
 #pragma clang fp contract(on)
 
 hipError_t launch_triangle_paths(TriArgs a, hipStream_t s) {
-  hipLaunchKernelGGL(triangle_paths_kernel, dim3(a.T), dim3(64), 0, s, a);
+  if (a.fields64)
+    hipLaunchKernelGGL(triangle_paths_kernel<double>, dim3(a.T), dim3(64), 0, s, a, a.fields64);
+  else
+    hipLaunchKernelGGL(triangle_paths_kernel<float>, dim3(a.T), dim3(64), 0, s, a, a.fields);
   return hipGetLastError();
 }
 

@@ -96,20 +96,32 @@ class Server:
         self._next_id = 0
 
     # ---- admission ----
-    def domain_footprint(self, N, B):
-        """Resident bytes of a domain plus the field memory of its batch slots."""
-        resident = Kernel.dense_footprint(N, B, gemm_form=self.gemm_form)
-        fields = self.slots_per_domain * self.max_batch * N * 4
-        return resident + fields
+    @staticmethod
+    def launch_bytes(N, n, scratch):
+        """Device bytes one batch of n queries holds while it runs: its fields
+        (n x N FP32) and the scratch of its two calls (``scratch`` = (contraction,
+        paths) bytes from Kernel.call_scratch)."""
+        return n * N * 4 + scratch[0] + scratch[1]
+
+    def domain_footprint(self, resident, N, scratch):
+        """Resident bytes of a domain plus what its batch slots hold at full batches."""
+        return resident + self.slots_per_domain * self.launch_bytes(N, self.max_batch, scratch)
 
     def add_domain(self, name, P, adjacency):
-        """Load a domain if its footprint fits the HBM budget; False if refused."""
+        """Load a domain if its footprint (resident bytes, and the fields and call
+        scratch of full batches in every slot) fits the HBM budget; False if
+        refused."""
         N, B = P.shape
-        need = self.domain_footprint(N, B)
-        if self.hbm_used + need > self.hbm_budget:
-            self.refused.append((name, need))
+        pre = Kernel.dense_footprint(N, B, gemm_form=self.gemm_form)
+        if self.hbm_used + pre > self.hbm_budget:
+            self.refused.append((name, pre))
             return False
         k = Kernel.load_dense(self.ctx, P, adjacency=adjacency, gemm_form=self.gemm_form)
+        need = self.domain_footprint(k.footprint(), N, k.call_scratch(self.max_batch, "kl"))
+        if self.hbm_used + need > self.hbm_budget:
+            k.free()
+            self.refused.append((name, need))
+            return False
         slots = [_Slot(self.torch, self.max_batch, self.max_steps)
                  for _ in range(self.slots_per_domain)]
         self.domains[name] = _Domain(name, k, slots)
@@ -142,22 +154,31 @@ class Server:
         n = min(self.max_batch, len(d.queue))
         N = d.kernel.N
         free, _ = torch.cuda.mem_get_info(self.ctx.device)
-        if free < self.field_reserve * n * N * 4:
+        if free < self.field_reserve * self.launch_bytes(N, n, d.kernel.call_scratch(n, "kl")):
             return False                              # wait for memory to free up
-        qs = [d.queue.popleft() for _ in range(n)]
+        qs = take_batch(d.queue, n)
         ts = np.array([q.target for q in qs], dtype=np.int32)
         ss = np.array([q.source for q in qs], dtype=np.int32)
-        with torch.cuda.stream(slot.stream):
-            fields = torch.empty((n, N), dtype=torch.float32, device=f"cuda:{self.ctx.device}")
-            _, bounds = d.kernel.batch_fields(ts, "kl", out=fields, stream=slot.stream)
-            paths, lens, status, rechecks = d.kernel.trace_paths(
-                ss, ts, "kl", fields, bounds, self.max_steps, stream=slot.stream)
-            slot.host_paths[:n].copy_(paths, non_blocking=True)
-            slot.host_info[0, :n].copy_(lens, non_blocking=True)
-            slot.host_info[1, :n].copy_(status, non_blocking=True)
-            slot.host_info[2, :n].copy_(rechecks, non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(slot.stream)
+        try:
+            with torch.cuda.stream(slot.stream):
+                fields = torch.empty((n, N), dtype=torch.float32,
+                                     device=f"cuda:{self.ctx.device}")
+                _, bounds = d.kernel.batch_fields(ts, "kl", out=fields, stream=slot.stream)
+                paths, lens, status, rechecks = d.kernel.trace_paths(
+                    ss, ts, "kl", fields, bounds, self.max_steps, stream=slot.stream)
+                slot.host_paths[:n].copy_(paths, non_blocking=True)
+                slot.host_info[0, :n].copy_(lens, non_blocking=True)
+                slot.host_info[1, :n].copy_(status, non_blocking=True)
+                slot.host_info[2, :n].copy_(rechecks, non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(slot.stream)
+        except Exception:
+            # the queries go back to the front of the queue, in order; with other
+            # batches in flight the launch is retried once they free memory
+            put_back(d.queue, qs)
+            if any(s.busy for dom in self.domains.values() for s in dom.slots):
+                return False
+            raise
         slot.busy, slot.queries, slot.event, slot.fields = True, qs, ev, fields
         self.batch_sizes[n] += 1
         return True
@@ -219,6 +240,16 @@ class Server:
             if now - t0 > timeout:
                 raise TimeoutError("open-loop run did not finish")
         return out
+
+
+def take_batch(queue, n):
+    """The first n queries of a domain queue, removed from it."""
+    return [queue.popleft() for _ in range(n)]
+
+
+def put_back(queue, qs):
+    """Return a batch taken by take_batch to the front of its queue, in order."""
+    queue.extendleft(reversed(qs))
 
 
 def latency_summary(queries):

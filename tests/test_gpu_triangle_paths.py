@@ -1,10 +1,13 @@
 """GPU triangle-based descent paths (Section IV, the method of the paper's
-figures) against the oracle tracer run on the same FP32 field values."""
+figures) against the oracle tracer: on FP32 fields, the tracer run on the same
+FP32 values; on FP64 fields (every decision in FP64), the tracer run on the
+oracle's own FP64 field."""
 
 import numpy as np
 import pytest
 
 from conftest import frac, read_golden
+from oracle import divergence as dv
 from oracle import triangle_path as tp
 from workloads import build_config, grid_domain
 from workloads.seeds import targets_sources
@@ -28,12 +31,12 @@ def run_gpu(k, ss, ts, fields, max_steps):
     return out
 
 
-def check_same(got, ref):
+def check_same(got, ref, tol=1e-12):
     gp, gw, gs = got
     rp, rw, rs = ref
     assert gs == STATUS[rs]
     assert gw == rw
-    assert np.abs(gp - rp).max() <= 1e-12
+    assert np.abs(gp - rp).max() <= tol
 
 
 @pytest.fixture(scope="module")
@@ -44,6 +47,7 @@ def grid(gpu_ctx):
     k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
     faces, xy = g.interior_mesh()
     k.attach_mesh(faces, xy)
+    k.P64 = P.astype(np.float64)
     yield g, k, tp.Mesh(faces, xy)
     k.free()
 
@@ -146,5 +150,52 @@ def test_mesh_validation(gpu_ctx):
                 k.attach_mesh(f, xy)
         k.attach_mesh(np.array([[0, 2, 1], [1, 2, 3]]), xy)   # clockwise input is fine
         del F
+    finally:
+        k.free()
+
+
+@pytest.mark.parametrize("kind", ["kl", "tv", "chi2"])
+def test_exact_fields_match_oracle(grid, kind):
+    g, k, mesh = grid
+    ts = targets_sources(37, g.N, 5)[0]
+    E = k.exact_fields(ts, kind).cpu().numpy()
+    for i, t in enumerate(ts):
+        ref = dv.field(k.P64, int(t), kind)
+        assert E[i, t] == 0.0
+        assert np.abs(E[i] - ref).max() <= 1e-13 * np.abs(ref).max(), (kind, i)
+
+
+@pytest.mark.parametrize("kind", ["kl", "tv"])
+def test_grid_paths_on_fp64_fields_match_oracle_field(grid, kind):
+    """Every decision on FP64 values: the paths equal the oracle's tracer on the
+    oracle's own FP64 field (the fields differ only in the rounding of their
+    sums, which moves the points by far less than 1e-9)."""
+    g, k, mesh = grid
+    ts, ss = targets_sources(38, g.N, 6)
+    E = k.exact_fields(ts, kind)
+    res = run_gpu(k, ss, ts, E, 20000)
+    for i, (s, t) in enumerate(zip(ss, ts)):
+        ref = tp.triangle_path(mesh, dv.field(k.P64, int(t), kind), g.adj_ptr, g.adj_idx, int(s),
+                               int(t), 20000)
+        check_same(res[i], ref, tol=1e-9)
+
+
+def test_disk_paths_on_fp64_fields_match_oracle_field(gpu_ctx):
+    from paper_1708_02845_amd import Kernel
+    inst = build_config("disk4096")
+    k = Kernel.load_dense(gpu_ctx, inst.P, adjacency=(inst.adj_ptr, inst.adj_idx))
+    try:
+        faces, xy = inst.interior_mesh()
+        k.attach_mesh(faces, xy)
+        mesh = tp.Mesh(faces, xy)
+        ts, ss = targets_sources(0, inst.N, 8)
+        for kind in ("kl", "tv"):
+            E = k.exact_fields(ts, kind)
+            res = run_gpu(k, ss, ts, E, 20000)
+            for i, (s, t) in enumerate(zip(ss, ts)):
+                ref = tp.triangle_path(mesh, dv.field(inst.P, int(t), kind), inst.adj_ptr,
+                                       inst.adj_idx, int(s), int(t), 20000)
+                check_same(res[i], ref, tol=1e-9)
+                assert res[i][2] == "reached"
     finally:
         k.free()

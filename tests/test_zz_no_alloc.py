@@ -41,6 +41,7 @@ CASES = [
     ("dense_f16x3", dict(gemm_form="f16x3"), ("kl",), (200, 37)),
     ("dense_f32", dict(gemm_form="f32"), ("kl",), (300, 5)),
     ("dense_bf16x3", dict(gemm_form="bf16x3"), ("kl",), (64, 33)),
+    ("dense_f16", dict(gemm_form="f16"), ("kl",), (100, 31)),
     ("floored_f16x3", dict(gemm_form="f16x3", tau=1e-4), ("kl",), (130, 9)),
     ("csr_f32", dict(tau=1e-5), ("tv", "kl"), (257, 40)),
     ("csr_f16", dict(tau=1e-5, csr_values="f16"), ("tv", "kl"), (200, 12)),
