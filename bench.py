@@ -24,7 +24,8 @@ measurements run and are reported under "rows": the contraction in its other
 forms and at 256 targets, the 256-target pass over the truncated rows with its
 local-minimum census, the distance of the truncated fields from the dense
 ones, the unit-disk workload (latency), the 257x257 grid (cache flushed
-between repetitions) and the Poisson kernel solved on the device.
+between repetitions), the Poisson kernel solved on the device, and the
+comparison distance D (the Dirichlet Green's function) of the batch's targets.
 
 The kernel matrices are built on the host before anything touches the GPU
 (the build forks worker processes).  Under a profiler that initialises the
@@ -45,7 +46,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"f16x3": 2500.0, "bf16x3": 2500.0, "f32": 157.3}
+MFMA_PEAK_TFLOPS = {"f16x3": 2500.0, "bf16x3": 2500.0, "f16": 2500.0, "f32": 157.3}
 # source file of each measured kernel, for matching counter records to the code
 KERNEL_SOURCE = {"dense_tv": "stream.hip", "dense_kl": "stream.hip", "csr_tv": "stream.hip",
                  "csr_kl": "stream.hip", "gemm_kl_T1": "gemm.hip", "kl_gemm_f16x3": "gemm.hip"}
@@ -201,7 +202,7 @@ def cpu_info():
     return model, len(os.sched_getaffinity(0))
 
 
-def cpu_baseline_grid1025(P, g, ts, t0, s0, max_steps, frac=0.0025):
+def cpu_baseline_grid1025(P, g, ts, t0, s0, max_steps, frac=0.005):
     """The FP64 oracle on a seeded row sample of the step: the 64 KL fields of the
     batch and the TV, KL, TV_tau and KL_tau fields of the first target,
     evaluated on frac of the rows (single thread, then a thread pool over the
@@ -424,7 +425,7 @@ def run_grid1025(args):
     torch.cuda.empty_cache()
     if not args.no_rows:
         rows.update(census_fp32_rows(torch, ctx, P, adj, ts_all))
-        for form in ("bf16x3", "f32"):
+        for form in ("bf16x3", "f32", "f16"):
             log(f"loading the {form} operand")
             k = Kernel.load_dense(ctx, P, gemm_form=form)
             rows.update(batch_contraction_rows(torch, k, ts_all, T, form=form, sizes=(T,)))
@@ -433,6 +434,7 @@ def run_grid1025(args):
         rows["d1_disk4096"] = disk_rows(torch, ctx, args.max_steps)
         rows.update(grid257_rows(torch, ctx, g257, P257))
         rows["a0_grid_poisson_kernel"] = grid_poisson_row(torch, ctx, g, P, build_s)
+        rows["d_online_green_function"] = green_row(torch, ctx, g, ts, kernels)
     ctx.close()
 
     dom = kernels["contraction"]
@@ -468,8 +470,8 @@ def batch_contraction_rows(torch, k, ts_all, T, form="f16x3", sizes=(256,)):
         tsT = ts_all[:TT]
         D = torch.empty((TT, N), dtype=torch.float32, device="cuda:0")
         us = repeat(torch, tm, f"c{TT}", lambda: k.batch_fields(tsT, "kl", out=D), reps=10, warm=2)
-        flops = 2.0 * N * B * TT * (1 if form == "f32" else 3)
-        byts = N * lda * 4 + TT * lda * 4 + TT * N * 4 + N * 4
+        flops = 2.0 * N * B * TT * (1 if form in ("f32", "f16") else 3)
+        byts = N * lda * (2 if form == "f16" else 4) + TT * lda * 4 + TT * N * 4 + N * 4
         tf = flops / (us * 1e-6) / 1e12
         out[f"a5_batched_kl_{form}_T{TT}"] = {
             "median_us": round(us, 1), "entries_per_s": N * B * TT / (us * 1e-6),
@@ -674,6 +676,33 @@ def grid_poisson_row(torch, ctx, g, P_host, build_s, batch=1024):
             "levels": st["levels"], "max_rel_residual": st["max_rel_residual"],
             "alg_bytes": byts, "GB/s": round(gbs_, 1), "hbm_frac": round(gbs_ / HBM_PEAK_GBS, 4),
             "max_abs_diff_vs_host_64_rows": diff}
+
+
+def green_row(torch, ctx, g, ts, kernels):
+    """The comparison distance D (the Dirichlet Green's function, one column per
+    target) for the batch's targets on the device, against the KL field per
+    target from the contraction and from the stream (the paper's "D online"
+    against "KL online", Table II)."""
+    T = len(ts)
+    D = torch.empty((T, g.N), dtype=torch.float32, device="cuda:0")
+    ctx.grid_green_function(g.node_type(), ts, out=D, batch=64)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, st = ctx.grid_green_function(g.node_type(), ts, out=D, batch=64)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / reps
+    del D
+    torch.cuda.empty_cache()
+    kl_c = kernels["contraction"]["avg_us"] / 1000.0 / T
+    kl_s = kernels["dense_kl"]["avg_us"] / 1000.0
+    log(f"Green's function: {ms:.1f} ms for {T} targets")
+    return {"targets": T, "ms_per_batch": round(ms, 2), "ms_per_target": round(ms / T, 3),
+            "cg_iterations": st["iterations"], "max_rel_residual": st["max_rel_residual"],
+            "kl_contraction_ms_per_target": round(kl_c, 4), "kl_stream_ms_per_target": round(kl_s, 3),
+            "speedup_kl_contraction_vs_d": round(ms / T / kl_c, 1),
+            "speedup_kl_stream_vs_d": round(ms / T / kl_s, 2)}
 
 
 # ----------------------------------------------------------------------------- grid257

@@ -234,8 +234,11 @@ __device__ __forceinline__ floatx16 split3(u32x4 ah, u32x4 al, u32x4 bh, u32x4 b
 }
 
 // HI: the F16 form, hi parts only (one product per K step; the lo loads and
-// their registers drop out).
-template <int NT, bool BF, bool HI = false>
+// their registers drop out).  ST: the A operand is read with non-temporal
+// loads, for launches of one target group, where no other workgroup reads the
+// same A tile (with several groups the tile's co-running readers share it
+// through L2, which non-temporal loads would give up).
+template <int NT, bool BF, bool HI = false, bool ST = false>
 __device__ __forceinline__ void gemm_split_body(GemmView gv, BatchOperand o, int32_t T,
                                                 int32_t groups, float* __restrict__ out) {
   int rb, grp;
@@ -302,8 +305,14 @@ __device__ __forceinline__ void gemm_split_body(GemmView gv, BatchOperand o, int
     const uint16_t* bl_ = HI ? nullptr : abl + (int64_t)c * cstride;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      dh[q] = *reinterpret_cast<const u32x4*>(bh_ + (a_lane + q * 512));
-      if constexpr (!HI) dl[q] = *reinterpret_cast<const u32x4*>(bl_ + (a_lane + q * 512));
+      if constexpr (ST) {
+        dh[q] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(bh_ + (a_lane + q * 512)));
+        if constexpr (!HI)
+          dl[q] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(bl_ + (a_lane + q * 512)));
+      } else {
+        dh[q] = *reinterpret_cast<const u32x4*>(bh_ + (a_lane + q * 512));
+        if constexpr (!HI) dl[q] = *reinterpret_cast<const u32x4*>(bl_ + (a_lane + q * 512));
+      }
     }
   };
   auto load_b = [&](int c, u32x4 (&dh)[SPT], u32x4 (&dl)[SPT]) {
@@ -381,22 +390,22 @@ __device__ __forceinline__ void gemm_split_body(GemmView gv, BatchOperand o, int
   write_fields<NT>(gv, o, T, tbase, row0, lane, accd, reinterpret_cast<float*>(lds), out);
 }
 
-template <int NT>
+template <int NT, bool ST>
 __global__ __launch_bounds__(256, 2) void kl_gemm_f16x3(GemmView gv, BatchOperand o, int32_t T,
                                                      int32_t groups, float* __restrict__ out) {
-  gemm_split_body<NT, false>(gv, o, T, groups, out);
+  gemm_split_body<NT, false, false, ST>(gv, o, T, groups, out);
 }
 
-template <int NT>
+template <int NT, bool ST>
 __global__ __launch_bounds__(256, 2) void kl_gemm_bf16x3(GemmView gv, BatchOperand o, int32_t T,
                                                       int32_t groups, float* __restrict__ out) {
-  gemm_split_body<NT, true>(gv, o, T, groups, out);
+  gemm_split_body<NT, true, false, ST>(gv, o, T, groups, out);
 }
 
-template <int NT>
+template <int NT, bool ST>
 __global__ __launch_bounds__(256, 2) void kl_gemm_f16(GemmView gv, BatchOperand o, int32_t T,
                                                    int32_t groups, float* __restrict__ out) {
-  gemm_split_body<NT, false, true>(gv, o, T, groups, out);
+  gemm_split_body<NT, false, true, ST>(gv, o, T, groups, out);
 }
 
 template <int NT>
@@ -505,19 +514,25 @@ hipError_t launch_batch_kl(DenseView dv, GemmView gv, TargetList tl, int32_t T, 
       hipLaunchKernelGGL(kl_gemm_f32<2>, grid, dim3(256), 0, s, gv, o, T, groups, out);
   } else if (gv.form == 2) {
     if (Tpad == 32)
-      hipLaunchKernelGGL(kl_gemm_bf16x3<1>, grid, dim3(256), 0, s, gv, o, T, groups, out);
+      hipLaunchKernelGGL((kl_gemm_bf16x3<1, true>), grid, dim3(256), 0, s, gv, o, T, groups, out);
+    else if (groups == 1)
+      hipLaunchKernelGGL((kl_gemm_bf16x3<2, true>), grid, dim3(256), 0, s, gv, o, T, groups, out);
     else
-      hipLaunchKernelGGL(kl_gemm_bf16x3<2>, grid, dim3(256), 0, s, gv, o, T, groups, out);
+      hipLaunchKernelGGL((kl_gemm_bf16x3<2, false>), grid, dim3(256), 0, s, gv, o, T, groups, out);
   } else if (gv.form == 3) {
     if (Tpad == 32)
-      hipLaunchKernelGGL(kl_gemm_f16<1>, grid, dim3(256), 0, s, gv, o, T, groups, out);
+      hipLaunchKernelGGL((kl_gemm_f16<1, true>), grid, dim3(256), 0, s, gv, o, T, groups, out);
+    else if (groups == 1)
+      hipLaunchKernelGGL((kl_gemm_f16<2, true>), grid, dim3(256), 0, s, gv, o, T, groups, out);
     else
-      hipLaunchKernelGGL(kl_gemm_f16<2>, grid, dim3(256), 0, s, gv, o, T, groups, out);
+      hipLaunchKernelGGL((kl_gemm_f16<2, false>), grid, dim3(256), 0, s, gv, o, T, groups, out);
   } else {
     if (Tpad == 32)
-      hipLaunchKernelGGL(kl_gemm_f16x3<1>, grid, dim3(256), 0, s, gv, o, T, groups, out);
+      hipLaunchKernelGGL((kl_gemm_f16x3<1, true>), grid, dim3(256), 0, s, gv, o, T, groups, out);
+    else if (groups == 1)
+      hipLaunchKernelGGL((kl_gemm_f16x3<2, true>), grid, dim3(256), 0, s, gv, o, T, groups, out);
     else
-      hipLaunchKernelGGL(kl_gemm_f16x3<2>, grid, dim3(256), 0, s, gv, o, T, groups, out);
+      hipLaunchKernelGGL((kl_gemm_f16x3<2, false>), grid, dim3(256), 0, s, gv, o, T, groups, out);
   }
   return hipGetLastError();
 }

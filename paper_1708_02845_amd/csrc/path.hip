@@ -18,6 +18,7 @@
 // recomputed in FP64 from the resident master rows and the decision is taken
 // on those.
 #include <cmath>
+#include <type_traits>
 
 #include "dd_internal.h"
 
@@ -133,6 +134,16 @@ __global__ __launch_bounds__(256) void target_rows_kernel(DenseView dv, CsrView 
 // log c_i and 1/c_i for the centres c_i = 1 + (i + 1/2)/128 of the 128
 // intervals of [1, 2), set by init_log_table (host logs, below 1 ulp).
 __device__ double g_logtab[256];
+// The kernels that evaluate FP64 rows copy the table into LDS first
+// (stage_log_table): the terms' table reads are then LDS reads rather than
+// gathers through the vector memory path.
+__shared__ double s_logtab[256];
+
+// Every thread of the block must call this before any use of log_pos.
+__device__ __forceinline__ void stage_log_table() {
+  for (int q = threadIdx.x; q < 256; q += blockDim.x) s_logtab[q] = g_logtab[q];
+  __syncthreads();
+}
 
 // Natural log of a positive normal double: x = m 2^e with m in [1, 2) falls
 // in interval i; with r = m/c_i - 1 (|r| < 2^-8), log x = e ln 2 + log c_i +
@@ -150,8 +161,8 @@ __device__ __forceinline__ double log_pos(double x) {
   const int i = (int)((b >> 45) & 127);
   const double m =
       __longlong_as_double((long long)((b & 0x000fffffffffffffull) | 0x3ff0000000000000ull));
-  const double r = near1 ? x - 1.0 : fma(m, g_logtab[128 + i], -1.0);
-  const double t = near1 ? 0.0 : g_logtab[i];
+  const double r = near1 ? x - 1.0 : fma(m, s_logtab[128 + i], -1.0);
+  const double t = near1 ? 0.0 : s_logtab[i];
   double q = 1.0 / 7.0;
   q = fma(q, r, -1.0 / 6.0);
   q = fma(q, r, 1.0 / 5.0);
@@ -202,7 +213,8 @@ __device__ __forceinline__ double term64(double pb, double lpb, double q, int pa
 // instance per kind family keeps each instance's code small: the walk and the
 // one instance a path uses stay in the instruction cache.
 constexpr int kU = 8;
-constexpr int kQ = 24;
+constexpr int kQ = 32;      // FP32 row entries in flight per lane
+constexpr int kQ64 = 16;    // FP64 row entries in flight per lane
 // Walks on dense rows of at least kSplitB columns split each FP64 re-decision
 // row over kMaxParts waves of a kPathThreads block (below that a row is cheap,
 // and the extra waves of the walk cost more than they save).
@@ -214,26 +226,36 @@ constexpr int kSplitB = 4096;
 __host__ __device__ inline bool split_rows(int is_csr, int B) { return !is_csr && B >= kSplitB; }
 
 template <int F>
-__device__ __noinline__ double exact_dense(const DenseView& dv, const double* p, const double* lp,
+__device__ __forceinline__ double exact_dense(const DenseView& dv, const double* p, const double* lp,
                                            int x, int param, int lo, int hi) {
   const int lane = threadIdx.x & 63;
   double acc = 0.0;
-  const bool f64 = dv.P64 != nullptr;
-  const double* q64 = dv.P64 + (int64_t)x * dv.B;
-  const float* q32 = dv.P + (int64_t)x * dv.ld;
-  for (int b0 = lo + lane; b0 < hi; b0 += 64 * kQ) {
-    double q[kQ];
-    if (f64) {
+  // each lane sums its columns lo + lane, lo + lane + 64, ... in increasing
+  // order whatever the batch width, so a row's value does not depend on kQ
+  if (dv.P64) {
+    const double* q64 = dv.P64 + (int64_t)x * dv.B;
+    for (int b0 = lo + lane; b0 < hi; b0 += 64 * kQ64) {
+      double q[kQ64];
 #pragma unroll
-      for (int u = 0; u < kQ; ++u) q[u] = q64[b0 + 64 * u < hi ? b0 + 64 * u : lo];
-    } else {
+      for (int u = 0; u < kQ64; ++u) q[u] = q64[b0 + 64 * u < hi ? b0 + 64 * u : lo];
 #pragma unroll
-      for (int u = 0; u < kQ; ++u) q[u] = (double)q32[b0 + 64 * u < hi ? b0 + 64 * u : lo];
+      for (int u = 0; u < kQ64; ++u) {
+        const int b = b0 + 64 * u;
+        if (b < hi) acc += term64<F>(p[b], F == 1 ? lp[b] : 0.0, q[u], param);
+      }
     }
+  } else {
+    // FP32 rows: the values stay FP32 in registers until their term
+    const float* q32 = dv.P + (int64_t)x * dv.ld;
+    for (int b0 = lo + lane; b0 < hi; b0 += 64 * kQ) {
+      float q[kQ];
 #pragma unroll
-    for (int u = 0; u < kQ; ++u) {
-      const int b = b0 + 64 * u;
-      if (b < hi) acc += term64<F>(p[b], F == 1 ? lp[b] : 0.0, q[u], param);
+      for (int u = 0; u < kQ; ++u) q[u] = q32[b0 + 64 * u < hi ? b0 + 64 * u : lo];
+#pragma unroll
+      for (int u = 0; u < kQ; ++u) {
+        const int b = b0 + 64 * u;
+        if (b < hi) acc += term64<F>(p[b], F == 1 ? lp[b] : 0.0, (double)q[u], param);
+      }
     }
   }
   return wsum(acc);
@@ -241,7 +263,7 @@ __device__ __noinline__ double exact_dense(const DenseView& dv, const double* p,
 
 // FP64 distance of truncated row x (TV or KL of the truncated rows), one wave.
 template <int F>
-__device__ __noinline__ double exact_csr(const CsrView& cv, const double* p, const double* lp,
+__device__ __forceinline__ double exact_csr(const CsrView& cv, const double* p, const double* lp,
                                          const double* tc, int x) {
   const int lane = threadIdx.x & 63;
   const int64_t s = cv.start[x];
@@ -297,33 +319,39 @@ __device__ __forceinline__ double distance_scale(int kind) {
   return 1.0;
 }
 
+// Kind family of a kind value: 0 TV, 1 KL, 2 chi-squared, 3 Hellinger, 4 the
+// power family (100 + k), 5 the alpha family (200 + j); the kernels that
+// evaluate FP64 rows are instantiated per family (launch_family), so each
+// instance holds one family's terms inline.
+__host__ __device__ inline int kind_family(int kind) {
+  return kind > 200 ? 5 : (kind > 100 ? 4 : kind);
+}
+
 // Part `part` of `parts` of the FP64 distance of row x to the target, computed
 // by one wave from the staged FP64 target row p, its logarithms lp and
 // constants tc: the terms of a column range of a dense row (summed over the
 // parts in order, then times distance_scale), or, on a truncated handle
-// (parts = 1), the whole truncated distance.  kind is the library's kind value
-// (0..3, 100 + k, 200 + j); truncated handles carry TV and KL only.
+// (parts = 1), the whole truncated distance.  F is the kind family of `kind`,
+// the library's kind value (0..3, 100 + k, 200 + j); truncated handles carry
+// TV and KL only.
+template <int F>
 __device__ __forceinline__ double exact_part(const DenseView& dv, const CsrView& cv, int is_csr,
                                              int kind, const double* p, const double* lp,
                                              const double* tc, int x, int part, int parts) {
-  if (is_csr) return kind == 0 ? exact_csr<0>(cv, p, lp, tc, x) : exact_csr<1>(cv, p, lp, tc, x);
+  if constexpr (F <= 1)
+    if (is_csr) return exact_csr<F>(cv, p, lp, tc, x);
   int lo, hi;
   part_range(dv.B, part, parts, lo, hi);
-  if (kind > 200) return exact_dense<5>(dv, p, lp, x, kind - 200, lo, hi);
-  if (kind > 100) return exact_dense<4>(dv, p, lp, x, kind - 100, lo, hi);
-  switch (kind) {
-    case 0: return exact_dense<0>(dv, p, lp, x, 0, lo, hi);
-    case 1: return exact_dense<1>(dv, p, lp, x, 0, lo, hi);
-    case 2: return exact_dense<2>(dv, p, lp, x, 0, lo, hi);
-    default: return exact_dense<3>(dv, p, lp, x, 0, lo, hi);
-  }
+  const int param = F == 5 ? kind - 200 : (F == 4 ? kind - 100 : 0);
+  return exact_dense<F>(dv, p, lp, x, param, lo, hi);
 }
 
 // FP64 distance of row x to the target, one wave.
+template <int F>
 __device__ __forceinline__ double exact_distance(const DenseView& dv, const CsrView& cv,
                                                  int is_csr, int kind, const double* p,
                                                  const double* lp, const double* tc, int x) {
-  return exact_part(dv, cv, is_csr, kind, p, lp, tc, x, 0, 1) * distance_scale(kind);
+  return exact_part<F>(dv, cv, is_csr, kind, p, lp, tc, x, 0, 1) * distance_scale(kind);
 }
 
 __device__ __forceinline__ double uniform(double x) {
@@ -367,6 +395,7 @@ __device__ __forceinline__ float unkey(uint32_t k) {
 // (ties: lowest id) and the set of neighbours that could still be the minimum
 // as one ballot: a few dozen instructions between the loads of consecutive
 // steps.
+template <int F>
 __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrView cv,
                                                            PathArgs a) {
   // rows of the current and the previous FP64 re-decision (at most W + 1 <= 65),
@@ -375,6 +404,7 @@ __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrVi
   __shared__ double cur_d[65], prev_d[65];
   __shared__ double part_d[65 * kMaxParts];
   int prev_n = 0;
+  stage_log_table();
   const int i = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -504,7 +534,7 @@ __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrVi
         if (!have)
           for (int part = 0; part < parts; ++part, ++task)
             if (task % nw == wave) {
-              const double pd = exact_part(dv, cv, a.is_csr, a.kind, p, lpt, tc, x, part, parts);
+              const double pd = exact_part<F>(dv, cv, a.is_csr, a.kind, p, lpt, tc, x, part, parts);
               if (lane == 0) part_d[pos * kMaxParts + part] = pd;
             }
         ++pos;
@@ -579,11 +609,13 @@ __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrVi
 // walk is the one the exact FP64 field gives.  Rows evaluated at the previous
 // step (its neighbours and the vertex itself) are reused.  `rechecks`
 // receives the number of rows evaluated.
+template <int F>
 __global__ __launch_bounds__(256) void paths_on_demand_kernel(DenseView dv, CsrView cv,
                                                               PathArgs a) {
   __shared__ int cur_x[65], prev_x[65];
   __shared__ double cur_d[65], prev_d[65];
   __shared__ double first_d;
+  stage_log_table();
   const int i = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -609,7 +641,7 @@ __global__ __launch_bounds__(256) void paths_on_demand_kernel(DenseView dv, CsrV
   const int t = __builtin_amdgcn_readfirstlane(path_target(a, i));
   int v = __builtin_amdgcn_readfirstlane(path_source(a, i));
   if (wave == 0) {
-    const double dx = exact_distance(dv, cv, a.is_csr, a.kind, p, lpt, tc, v);
+    const double dx = exact_distance<F>(dv, cv, a.is_csr, a.kind, p, lpt, tc, v);
     if (lane == 0) first_d = dx;
   }
   __syncthreads();
@@ -648,7 +680,7 @@ __global__ __launch_bounds__(256) void paths_on_demand_kernel(DenseView dv, CsrV
       if (hit < 0) ++evals;
       if (pos % nw == wave) {
         const double dx = hit >= 0 ? prev_d[hit]
-                                   : exact_distance(dv, cv, a.is_csr, a.kind, p, lpt, tc, x);
+                                   : exact_distance<F>(dv, cv, a.is_csr, a.kind, p, lpt, tc, x);
         if (lane == 0) {
           cur_x[pos] = x;
           cur_d[pos] = dx;
@@ -738,8 +770,10 @@ __global__ __launch_bounds__(256) void local_minima_kernel(PathArgs a, int32_t N
 // wave, rows in turn) and becomes 1 if no neighbour is strictly lower (the
 // oracle's rule: min over neighbours >= d(v)), else 0.  A wave takes 64
 // vertices at a time and works through the undecided ones among them.
+template <int F>
 __global__ __launch_bounds__(256) void resolve_minima_kernel(DenseView dv, CsrView cv, PathArgs a,
                                                              int32_t N, uint8_t* cls) {
+  stage_log_table();
   const int lane = threadIdx.x & 63;
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -757,12 +791,12 @@ __global__ __launch_bounds__(256) void resolve_minima_kernel(DenseView dv, CsrVi
       const double* p = a.trow + (int64_t)i * Bt;
       const double* lp = a.tlog + (int64_t)i * Bt;
       const double* tc = a.tconst + (int64_t)i * 4;
-      const double d0 = exact_distance(dv, cv, a.is_csr, a.kind, p, lp, tc, v);
+      const double d0 = exact_distance<F>(dv, cv, a.is_csr, a.kind, p, lp, tc, v);
       bool minimum = true;
       for (int j = 0; j < a.adj_w && minimum; ++j) {
         const int u = __builtin_amdgcn_readfirstlane(a.adj[(int64_t)v * a.adj_w + j]);
         if (u < 0) break;
-        if (exact_distance(dv, cv, a.is_csr, a.kind, p, lp, tc, u) < d0) minimum = false;
+        if (exact_distance<F>(dv, cv, a.is_csr, a.kind, p, lp, tc, u) < d0) minimum = false;
       }
       if (lane == 0) cls[e] = minimum ? 1 : 0;
     }
@@ -803,6 +837,19 @@ hipError_t launch_local_minima(PathArgs a, int32_t N, uint8_t* cls, int32_t* cou
   return hipGetLastError();
 }
 
+// fn(std::integral_constant<int, F>{}) for the kind family F of `kind`.
+template <typename Fn>
+static hipError_t by_family(int kind, Fn fn) {
+  switch (kind_family(kind)) {
+    case 0: return fn(std::integral_constant<int, 0>{});
+    case 1: return fn(std::integral_constant<int, 1>{});
+    case 2: return fn(std::integral_constant<int, 2>{});
+    case 3: return fn(std::integral_constant<int, 3>{});
+    case 4: return fn(std::integral_constant<int, 4>{});
+    default: return fn(std::integral_constant<int, 5>{});
+  }
+}
+
 hipError_t launch_resolve_minima(DenseView dv, CsrView cv, PathArgs a, int32_t N, uint8_t* cls,
                                  int32_t* counts, hipStream_t s) {
   const int64_t total = (int64_t)N * a.T;
@@ -810,9 +857,11 @@ hipError_t launch_resolve_minima(DenseView dv, CsrView cv, PathArgs a, int32_t N
   const int64_t cap = (int64_t)num_cus() * 8;
   if (grid > cap) grid = cap;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(resolve_minima_kernel, dim3((unsigned)grid), dim3(256), 0, s, dv, cv, a, N,
-                     cls);
-  hipError_t e = hipGetLastError();
+  hipError_t e = by_family(a.kind, [&](auto f) {
+    hipLaunchKernelGGL(resolve_minima_kernel<decltype(f)::value>, dim3((unsigned)grid), dim3(256),
+                       0, s, dv, cv, a, N, cls);
+    return hipGetLastError();
+  });
   if (e != hipSuccess || !counts) return e;
   hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(256), 0, s, counts, 2 * a.T);
   hipLaunchKernelGGL(count_classes_kernel, dim3((unsigned)grid), dim3(256), 0, s, cls, a.T, N,
@@ -823,23 +872,28 @@ hipError_t launch_resolve_minima(DenseView dv, CsrView cv, PathArgs a, int32_t N
 // FP64 fields: every row x of every target by exact_distance (one wave per
 // row), the evaluation the FP64 re-decisions use; the target's own entry is
 // 0 by definition (d(t, t) = 0 for every kind).  Grid: (row groups of 4, T).
+template <int F>
 __global__ __launch_bounds__(256) void exact_fields_kernel(DenseView dv, CsrView cv, PathArgs a,
                                                            int32_t N, double* out) {
+  stage_log_table();
   const int i = blockIdx.y;
   const int64_t x = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (x >= N) return;
   const int Bt = a.is_csr ? cv.B : dv.B;
   const int t = path_target(a, i);
-  const double d = exact_distance(dv, cv, a.is_csr, a.kind, a.trow + (int64_t)i * Bt,
+  const double d = exact_distance<F>(dv, cv, a.is_csr, a.kind, a.trow + (int64_t)i * Bt,
                                   a.tlog + (int64_t)i * Bt, a.tconst + (int64_t)i * 4, (int)x);
   if ((threadIdx.x & 63) == 0) out[(int64_t)i * N + x] = x == t ? 0.0 : d;
 }
 
 hipError_t launch_exact_fields(DenseView dv, CsrView cv, PathArgs a, int32_t N, double* out,
                                hipStream_t s) {
-  hipLaunchKernelGGL(exact_fields_kernel, dim3((unsigned)((N + 3) / 4), (unsigned)a.T), dim3(256),
-                     0, s, dv, cv, a, N, out);
-  return hipGetLastError();
+  return by_family(a.kind, [&](auto f) {
+    hipLaunchKernelGGL(exact_fields_kernel<decltype(f)::value>,
+                       dim3((unsigned)((N + 3) / 4), (unsigned)a.T), dim3(256), 0, s, dv, cv, a, N,
+                       out);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_target_rows(DenseView dv, CsrView cv, PathArgs a, double* trow, double* tlog,
@@ -869,12 +923,16 @@ static hipError_t launch_with_target(K kern, int threads, DenseView dv, CsrView 
 }
 
 hipError_t launch_paths(DenseView dv, CsrView cv, PathArgs a, hipStream_t s) {
-  return launch_with_target(paths_kernel, split_rows(a.is_csr, a.is_csr ? cv.B : dv.B) ? kPathThreads : 256,
-                            dv, cv, a, s);
+  const int threads = split_rows(a.is_csr, a.is_csr ? cv.B : dv.B) ? kPathThreads : 256;
+  return by_family(a.kind, [&](auto f) {
+    return launch_with_target(paths_kernel<decltype(f)::value>, threads, dv, cv, a, s);
+  });
 }
 
 hipError_t launch_paths_on_demand(DenseView dv, CsrView cv, PathArgs a, hipStream_t s) {
-  return launch_with_target(paths_on_demand_kernel, 256, dv, cv, a, s);
+  return by_family(a.kind, [&](auto f) {
+    return launch_with_target(paths_on_demand_kernel<decltype(f)::value>, 256, dv, cv, a, s);
+  });
 }
 
 }  // namespace dd
