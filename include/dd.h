@@ -144,8 +144,28 @@ typedef struct {
   int32_t csr_values;  /* dd_csr_values read by the field entry points (truncated handles) */
 } dd_kernel_info;
 
-/* Create a context on HIP device `device`.  *out receives the handle. */
+/* Create a context on HIP device `device`.  *out receives the handle.  The
+ * first context on a device in a process also checks the device's FP32
+ * hardware log2 on every FP32 value in [2^-126, 1] (a few milliseconds; see
+ * dd_path_level1). */
 dd_status dd_create(int device, dd_ctx** out);
+
+/* Level-1 re-decisions of KL walks on dense handles (dd_trace_paths; the
+ * steepest-descent rule of Section IV).  A near-tie is first re-decided on
+ * row values from FP32 hardware logarithms summed in FP64, each with a
+ * stated bound that covers both the exact value and the FP64 evaluation;
+ * only when those intervals do not settle the step are the rows computed in
+ * FP64.  Either way the step is the one the FP64 values give, so paths do
+ * not change; only the cost of a re-decision does.  The bounds assume that
+ * the hardware log2 L meets |L(x) - log2 x| <= 2^-22 |log2 x| + 2^-40 on
+ * [2^-126, 1], which dd_create checks exhaustively; level 1 is on by default
+ * where the check passed.
+ *   enable   1 on (DD_EINVAL if the device failed the check), 0 off, -1 query
+ *   enabled  host, nullable: the state after the call
+ *   ratios   host [2], nullable: the check's largest error over the assumed
+ *            bound (<= 1 passes), and its largest relative error
+ * Per context; not thread-safe against calls that trace paths. */
+dd_status dd_path_level1(dd_ctx* ctx, int enable, int* enabled, double* ratios);
 
 /* Destroy a context.  Every kernel loaded through it must be freed first
  * (DD_ESTATE otherwise, and the context stays valid). */
@@ -277,7 +297,8 @@ dd_status dd_batch_distance_fields_noalloc(dd_kernel* k, const int32_t* targets,
  *   path_dev     device [T][max_steps+1] int32, vertex ids, -1 past the end
  *   len_dev      device [T] int32 path lengths (vertices, source included)
  *   status_dev   device [T] int32 dd_path_status
- *   rechecks_dev device [T] int32 FP64 re-decisions, nullable
+ *   rechecks_dev device [T] int32 re-decisions (level 1 or FP64, see
+ *                dd_path_level1), nullable
  * Needs the adjacency.  Asynchronous on `stream`. */
 dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const int32_t* targets,
                          int32_t kind, const float* fields_dev, const dd_error_bound* bounds,

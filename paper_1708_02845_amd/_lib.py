@@ -51,6 +51,8 @@ EXPORTS = {
     # name: (restype, argtypes)
     "dd_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
     "dd_destroy": (C.c_int, [C.c_void_p]),
+    "dd_path_level1": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int),
+                                 C.POINTER(C.c_double)]),
     "dd_load_kernel_dense": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
                                        C.c_int32, C.POINTER(dd_adjacency), C.POINTER(dd_load_opts),
                                        C.POINTER(C.c_void_p)]),

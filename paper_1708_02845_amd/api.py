@@ -85,6 +85,15 @@ class Context:
             L.check(self._lib.dd_destroy(self._h))
             self._h = None
 
+    def path_level1(self, enable=None):
+        """(enabled, (ratio to the assumed bound, max relative error)) of the
+        level-1 re-decisions of KL walks; ``enable`` True/False switches them."""
+        on = C.c_int()
+        r = (C.c_double * 2)()
+        L.check(self._lib.dd_path_level1(self._h, -1 if enable is None else int(bool(enable)),
+                                         C.byref(on), r))
+        return bool(on.value), (r[0], r[1])
+
     def grid_poisson_kernel(self, node_type, cols=None, tol=1e-12, max_iter=1000, batch=0,
                             dtype="f32", out=None, stream=None):
         """Poisson kernel P_IB of a grid domain, computed on the device.

@@ -10,10 +10,10 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
-#include <limits>
 #include <vector>
 
 #include "dd_internal.h"
@@ -127,6 +127,9 @@ struct dd_ctx {
   int device = 0;
   std::atomic<int> live_kernels{0};   // loads and frees may come from several threads
   void* scratch = nullptr;            // this device's fixed scratch (dd::fixed_scratch)
+  double log2_ratio[2] = {0.0, 0.0};  // the device's hardware-log2 scan (check_log2_bound)
+  int l1_ok = 0;                      // the scan passed
+  int l1_on = 0;                      // level-1 re-decisions in KL walks
 };
 
 struct dd_kernel {
@@ -659,10 +662,28 @@ dd_status dd_create(int device, dd_ctx** out) {
   HIP_OR(dd::init_log_table());
   void* fixed = nullptr;
   HIP_OR(dd::fixed_scratch(device, &fixed));
+  // the hardware log2 scan, once per device per process
+  static std::mutex scan_mu;
+  static std::unordered_map<int, std::pair<double, double>> scans;
+  std::pair<double, double> r;
+  {
+    std::lock_guard<std::mutex> lk(scan_mu);
+    auto it = scans.find(device);
+    if (it == scans.end()) {
+      double rr[2];
+      HIP_OR(dd::check_log2_bound(rr));
+      it = scans.emplace(device, std::make_pair(rr[0], rr[1])).first;
+    }
+    r = it->second;
+  }
   dd_ctx* c = new (std::nothrow) dd_ctx;
   if (!c) return fail(DD_ENOMEM, "host allocation failed");
   c->device = device;
   c->scratch = fixed;
+  c->log2_ratio[0] = r.first;
+  c->log2_ratio[1] = r.second;
+  c->l1_ok = r.first <= 1.0 ? 1 : 0;
+  c->l1_on = c->l1_ok;
   *out = c;
   return DD_OK;
 }
@@ -673,6 +694,22 @@ dd_status dd_destroy(dd_ctx* ctx) {
     return fail(DD_ESTATE, "%d kernels still loaded in this context", ctx->live_kernels.load());
   ctx->magic = kDead;
   delete ctx;
+  return DD_OK;
+}
+
+dd_status dd_path_level1(dd_ctx* ctx, int enable, int* enabled, double* ratios) {
+  if (!ctx_ok(ctx)) return fail(DD_ESTATE, "not a live context");
+  if (enable != -1 && enable != 0 && enable != 1)
+    return fail(DD_EINVAL, "enable must be -1, 0 or 1, not %d", enable);
+  if (enable == 1 && !ctx->l1_ok)
+    return fail(DD_EINVAL, "the hardware log2 of device %d exceeds the level-1 bound (ratio %g)",
+                ctx->device, ctx->log2_ratio[0]);
+  if (enable >= 0) ctx->l1_on = enable;
+  if (enabled) *enabled = ctx->l1_on;
+  if (ratios) {
+    ratios[0] = ctx->log2_ratio[0];
+    ratios[1] = ctx->log2_ratio[1];
+  }
   return DD_OK;
 }
 
@@ -1138,6 +1175,7 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
   a.max_steps = max_steps;
   a.kind = kind;
   a.is_csr = k->is_csr;
+  a.l1 = k->ctx->l1_on && kind == DD_KL && !k->is_csr ? 1 : 0;
   const PathScratch lay = path_scratch(k, T);
   const bool inl = lay.inl;
   const size_t n_small = lay.n_small, o_row = lay.o_row;

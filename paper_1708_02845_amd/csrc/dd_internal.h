@@ -152,7 +152,7 @@ struct PathArgs {
   PathSmall small;
   const double* trow;       // [T][B] FP64 target rows (truncated rows for CSR handles)
   const double* tlog;       // [T][B] log of trow (0 where trow is 0)
-  const double* tconst;     // [T][4]: W_t, H_t (natural log), |S_t|, unused
+  const double* tconst;     // [T][4]: W_t, H_t (natural log), |S_t|, sum p |ln p|
   int32_t* path;            // [T][max_steps+1]
   int32_t* len;             // [T]
   int32_t* status;          // [T]
@@ -163,6 +163,7 @@ struct PathArgs {
   double tgt_tau;
   int32_t tgt_tau_relative;
   int32_t tgt_in_lds;       // set by the launcher: trow/tlog staged in LDS
+  int32_t l1;               // KL walks on dense rows: level-1 rows first (see path.hip)
 };
 hipError_t launch_target_rows(DenseView dv, CsrView cv, PathArgs a, double* trow, double* tlog,
                               double* tconst, hipStream_t s);
@@ -209,6 +210,9 @@ hipError_t launch_triangle_paths(TriArgs a, hipStream_t s);
 
 // Device table of the FP64 log used by the path kernels; once per device.
 hipError_t init_log_table();
+// Exhaustive check of the FP32 hardware log2 against the bound the level-1
+// rows assume (path.hip); ratio[0] <= 1 means the bound holds on this device.
+hipError_t check_log2_bound(double ratio[2]);
 
 // Fixed per-GPU scratch of the allocation-free batch entry point
 // (scratch.hip): its size, and its device address on `device` (which must be

@@ -18,6 +18,7 @@
 // recomputed in FP64 from the resident master rows and the decision is taken
 // on those.
 #include <cmath>
+#include <cstring>
 #include <type_traits>
 
 #include "dd_internal.h"
@@ -42,7 +43,7 @@ __device__ __forceinline__ Bound path_bound(const PathArgs& a, int i) {
 
 // Target rows in FP64 (dense: the master row; truncated: the stored entries
 // scattered into a dense row), their logarithms, and constants W = sum p,
-// H = sum p ln p, |S| over the nonzero entries.
+// H = sum p ln p, |S| over the nonzero entries, sum p |ln p|.
 __global__ __launch_bounds__(256) void target_rows_kernel(DenseView dv, CsrView cv, PathArgs a,
                                                           double* trow, double* tlog,
                                                           double* tconst) {
@@ -50,9 +51,9 @@ __global__ __launch_bounds__(256) void target_rows_kernel(DenseView dv, CsrView 
   const int B = a.is_csr ? cv.B : dv.B;
   double* out = trow + (int64_t)blockIdx.x * B;
   double* lout = tlog + (int64_t)blockIdx.x * B;
-  __shared__ double red[3][8];
+  __shared__ double red[4][8];
   __shared__ double thr_s;
-  double w = 0.0, h = 0.0, c = 0.0;
+  double w = 0.0, h = 0.0, c = 0.0, ha = 0.0;
   if (!a.is_csr) {
     // threshold of the target-row truncation (none when tgt_tau == 0)
     double thr = 0.0;
@@ -83,6 +84,7 @@ __global__ __launch_bounds__(256) void target_rows_kernel(DenseView dv, CsrView 
       lout[b] = lp;
       w += p;
       h += p * lp;
+      ha += p * fabs(lp);
       c += p > 0.0 ? 1.0 : 0.0;
     }
   } else {
@@ -100,11 +102,13 @@ __global__ __launch_bounds__(256) void target_rows_kernel(DenseView dv, CsrView 
       lout[cv.col[s + i]] = lp;
       w += p;
       h += p * lp;
+      ha += p * fabs(lp);
       c += 1.0;
     }
   }
   w = wsum(w);
   h = wsum(h);
+  ha = wsum(ha);
   c = wsum(c);
   __syncthreads();   // red[] may still be read by the threshold step
   const int wid = threadIdx.x >> 6;
@@ -112,19 +116,21 @@ __global__ __launch_bounds__(256) void target_rows_kernel(DenseView dv, CsrView 
     red[0][wid] = w;
     red[1][wid] = h;
     red[2][wid] = c;
+    red[3][wid] = ha;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double W = 0.0, H = 0.0, C = 0.0;
+    double W = 0.0, H = 0.0, C = 0.0, HA = 0.0;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
       W += red[0][i];
       H += red[1][i];
       C += red[2][i];
+      HA += red[3][i];
     }
     tconst[blockIdx.x * 4 + 0] = W;
     tconst[blockIdx.x * 4 + 1] = H;
     tconst[blockIdx.x * 4 + 2] = C;
-    tconst[blockIdx.x * 4 + 3] = 0.0;
+    tconst[blockIdx.x * 4 + 3] = HA;
   }
 }
 
@@ -183,6 +189,91 @@ hipError_t init_log_table() {
   }
   return hipMemcpyToSymbol(HIP_SYMBOL(g_logtab), h, sizeof h);
 }
+
+// ---- level-1 rows: FP32 logarithms with a verified bound ----
+//
+// The FP64 logarithm above costs a few dozen FP64 operations per entry, which
+// makes a re-decision of a walk bound by the FP64 units of its compute unit.
+// Most re-decisions are settled by values far less accurate than FP64 and far
+// more accurate than the field: level-1 rows take log2 of each FP32 entry from
+// the hardware's v_log_f32 (one transcendental instruction) and sum the KL
+// terms in FP64.  The hardware log is trusted only within
+//   |L(x) - log2 x| <= kL1Rel |log2 x| + kL1Abs  for every normal x in (0, 1],
+// and the library checks that claim at start-up on every FP32 input in that
+// range (log2_scan_kernel, against the FP64 log2); level-1 rows are used only
+// on devices that pass.
+constexpr double kL1Rel = 0x1p-22;
+constexpr double kL1Abs = 0x1p-40;
+constexpr double kLn2 = 0.6931471805599453;
+constexpr double kInvLn2 = 1.4426950408889634;
+
+// out[0] = max over x of |L(x) - log2 x| / (kL1Rel |log2 x| + kL1Abs),
+// out[1] = max of |L(x) - log2 x| / |log2 x| over x != 1; a NaN ratio counts
+// as +inf.  Inputs: the n FP32 values with bit patterns lo, lo + 1, ...
+__global__ __launch_bounds__(256) void log2_scan_kernel(uint32_t lo, uint32_t n,
+                                                        unsigned long long* out) {
+  double m0 = 0.0, m1 = 0.0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float x = __uint_as_float(lo + i);
+    const double y = (double)__builtin_amdgcn_logf(x);
+    const double r = log2((double)x);
+    const double err = fabs(y - r);
+    const double q0 = err / (kL1Rel * fabs(r) + kL1Abs);
+    m0 = q0 == q0 ? fmax(m0, q0) : __builtin_inf();
+    if (r != 0.0) {
+      const double q1 = err / fabs(r);
+      m1 = q1 == q1 ? fmax(m1, q1) : __builtin_inf();
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    m0 = fmax(m0, __shfl_xor(m0, off));
+    m1 = fmax(m1, __shfl_xor(m1, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    // non-negative doubles order as their bit patterns
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(m0));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(m1));
+  }
+}
+
+hipError_t check_log2_bound(double ratio[2]) {
+  unsigned long long* d = nullptr;
+  hipError_t e = hipMalloc(&d, 16);
+  if (e != hipSuccess) return e;
+  e = hipMemset(d, 0, 16);
+  // FLT_MIN = 0x00800000 up to 1.0f = 0x3f800000
+  const uint32_t lo = 0x00800000u, n = 0x3f800000u - 0x00800000u + 1u;
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(log2_scan_kernel, dim3(num_cus() * 8), dim3(256), 0, 0, lo, n, d);
+    e = hipGetLastError();
+  }
+  unsigned long long h[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpy(h, d, 16, hipMemcpyDeviceToHost);
+  const hipError_t f = hipFree(d);
+  if (e == hipSuccess) e = f;
+  for (int i = 0; i < 2; ++i) std::memcpy(&ratio[i], &h[i], 8);
+  return e;
+}
+
+// KL of dense row x over columns [lo, hi) at level 1, one wave: returns
+// sum_b p_b log2 q_b (log2 from v_log_f32 for normal FP32 q <= 1, else from
+// log_pos) and sets s = sum_b p_b |log2 q_b|; terms with p_b = 0 are skipped.
+// The target row p is read as FP32 from LDS (exact for an FP32 matrix); FP64
+// rows and target values are rounded to FP32 first (within 2^-24 relative:
+// within 2^-24 of log q per entry and 2^-24 of p, which l1_bound adds).
+__device__ __forceinline__ void l1_term(float pf, float qf, double q, double& acc, double& s) {
+  if (!(pf > 0.0f)) return;
+  const double pb = (double)pf;
+  double l2;
+  if (qf >= 1.17549435e-38f && qf <= 1.0f)
+    l2 = (double)__builtin_amdgcn_logf(qf);
+  else
+    l2 = q > 0.0 ? log_pos(q) * kInvLn2 : -__builtin_inf();
+  acc += pb * l2;
+  s += pb * fabs(l2);
+}
+
 
 // Terms per kind family F: 0 TV, 1 KL, 2 chi-squared, 3 Hellinger, 4 the
 // power family |q - p|^k / p^(k-1) (k = param), 5 the alpha-divergence term
@@ -259,6 +350,55 @@ __device__ __forceinline__ double exact_dense(const DenseView& dv, const double*
     }
   }
   return wsum(acc);
+}
+
+__device__ __forceinline__ double l1_dense(const DenseView& dv, const float* p, int x, int lo,
+                                           int hi, double& sabs) {
+  const int lane = threadIdx.x & 63;
+  double acc = 0.0, s = 0.0;
+  if (dv.P64) {
+    const double* q64 = dv.P64 + (int64_t)x * dv.B;
+    for (int b0 = lo + lane; b0 < hi; b0 += 64 * kQ64) {
+      double q[kQ64];
+#pragma unroll
+      for (int u = 0; u < kQ64; ++u) q[u] = q64[b0 + 64 * u < hi ? b0 + 64 * u : lo];
+#pragma unroll
+      for (int u = 0; u < kQ64; ++u)
+        if (b0 + 64 * u < hi) l1_term(p[b0 + 64 * u], (float)q[u], q[u], acc, s);
+    }
+  } else {
+    const float* q32 = dv.P + (int64_t)x * dv.ld;
+    for (int b0 = lo + lane; b0 < hi; b0 += 64 * kQ) {
+      float q[kQ];
+#pragma unroll
+      for (int u = 0; u < kQ; ++u) q[u] = q32[b0 + 64 * u < hi ? b0 + 64 * u : lo];
+#pragma unroll
+      for (int u = 0; u < kQ; ++u)
+        if (b0 + 64 * u < hi) l1_term(p[b0 + 64 * u], q[u], (double)q[u], acc, s);
+    }
+  }
+  sabs = wsum(s);
+  return wsum(acc);
+}
+
+// Level-1 KL of a dense row from its parts' sums A = sum p log2 q and
+// S = sum p |log2 q| (natural-log value H - ln2 A), and the bound on its
+// distance from the exact value and from the FP64 evaluation of the same row
+// (so that intervals which settle a decision settle it for the FP64 values
+// too).  Per entry the log is within kL1Rel |ln q| + ln2 kL1Abs (plus 2^-50
+// |ln q| for the FP64 steps after it).  An FP64 matrix adds the FP32
+// rounding of q (2^-24 of ln q, times p: 2^-23 W in all) and of p (2^-24
+// relative: 2^-23 S), and target values below the FP32 range, which drop out
+// (under 2^-120 per entry).  The sums of at most B/64 + 24 terms deep are
+// within that many units of 2^-53 of the sums of magnitudes, counted twice
+// (the FP64 evaluation has the same rounding); H, W and Habs = sum p |ln p|
+// come from the target.
+__device__ __forceinline__ double l1_bound(double S2, double W, double Habs, int B, bool p64) {
+  const double S = kLn2 * S2;
+  const double g = 2.0 * ((double)(B / 64) + 24.0) * 0x1p-53;
+  return (kL1Rel + 0x1p-50 + (p64 ? 0x1p-23 : 0.0)) * (1.0 + 0x1p-20) * S +
+         2.0 * kLn2 * kL1Abs * (1.0 + 0x1p-20) * W + g * (Habs + S) +
+         (p64 ? 0x1p-23 * W + 0x1p-120 * (double)B : 0.0);
 }
 
 // FP64 distance of truncated row x (TV or KL of the truncated rows), one wave.
@@ -400,9 +540,9 @@ __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrVi
                                                            PathArgs a) {
   // rows of the current and the previous FP64 re-decision (at most W + 1 <= 65),
   // and the parts of the rows being evaluated
-  __shared__ int cur_x[65], prev_x[65], cur_new[65];
-  __shared__ double cur_d[65], prev_d[65];
-  __shared__ double part_d[65 * kMaxParts];
+  __shared__ int cur_x[65], prev_x[65];
+  __shared__ double cur_d[65], prev_d[65], cur_e[65], prev_e[65];
+  __shared__ double part_d[65 * kMaxParts], part_s[65 * kMaxParts];
   int prev_n = 0;
   stage_log_table();
   const int i = blockIdx.x;
@@ -431,6 +571,19 @@ __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrVi
     __syncthreads();
     p = tsh;
     lpt = tsh + Bt;
+  }
+  // the FP32 target row of the level-1 rows, after the FP64 rows when those
+  // are staged too
+  const float* p32 = nullptr;
+  if constexpr (F == 1) {
+    if (a.l1) {
+      extern __shared__ double tsh[];
+      float* ps = reinterpret_cast<float*>(tsh + (a.tgt_in_lds ? 2 * Bt : 0));
+      const double* pg = a.trow + (int64_t)i * Bt;
+      for (int b = threadIdx.x; b < Bt; b += blockDim.x) ps[b] = (float)pg[b];
+      __syncthreads();
+      p32 = ps;
+    }
   }
   const double* tc = a.tconst + (int64_t)i * 4;
   int32_t* path = a.path + (int64_t)i * (a.max_steps + 1);
@@ -505,65 +658,138 @@ __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrVi
     } else if (certain && v1 - e1 >= dvv + ev) {
       stuck = true;
     } else {
-      // FP64 re-decision.  Rows: the current vertex, then every candidate
-      // neighbour; wave (position % waves) computes each row, rows known from
-      // the previous re-decision are reused.
+      // Re-decision.  Rows: the current vertex, then every candidate
+      // neighbour, each with a value and a bound (cur_e; 0 for an FP64 value,
+      // negative while unknown).  KL walks on dense rows first take level-1
+      // values (l1_dense); if their intervals settle the step it is the step
+      // the FP64 values take, else the rows are computed in FP64 and the step
+      // is decided on those (ties to the lowest id).  Wave (task % waves)
+      // computes each part of a row; rows of the previous re-decision are
+      // reused at the level they have.
       ++rechecks;
       const int nw = (int)(blockDim.x >> 6);
-      uint64_t rest = cand | (1ull << L);
-      int pos = 0, task = 0;
-      for (;;) {
-        int x = v;
-        if (pos > 0) {
-          if (rest == 0) break;
-          x = __builtin_amdgcn_readlane(ul, (int)__builtin_ctzll(rest));
-          rest &= rest - 1;
-        }
-        double dx = 0.0;
-        bool have = false;
-        for (int q = 0; q < prev_n && !have; ++q)
-          if (prev_x[q] == x) {
-            dx = prev_d[q];
-            have = true;
+      int pos = 0;
+      {
+        uint64_t rest = cand | (1ull << L);
+        for (;;) {
+          int x = v;
+          if (pos > 0) {
+            if (rest == 0) break;
+            x = __builtin_amdgcn_readlane(ul, (int)__builtin_ctzll(rest));
+            rest &= rest - 1;
           }
-        if (threadIdx.x == 0) {
-          cur_x[pos] = x;
-          cur_d[pos] = dx;
-          cur_new[pos] = have ? 0 : 1;
+          double dx = 0.0, ex = -1.0;
+          for (int q = 0; q < prev_n; ++q)
+            if (prev_x[q] == x) {
+              dx = prev_d[q];
+              ex = prev_e[q];
+              break;
+            }
+          if (threadIdx.x == 0) {
+            cur_x[pos] = x;
+            cur_d[pos] = dx;
+            cur_e[pos] = ex;
+          }
+          ++pos;
         }
-        if (!have)
+      }
+      __syncthreads();
+      bool settled = false;
+      int best_u = 0x7fffffff;
+      if constexpr (F == 1) {
+        if (a.l1) {
+          int task = 0;
+          for (int q = 0; q < pos; ++q) {
+            if (cur_e[q] >= 0.0) continue;   // known
+            const int x = cur_x[q];
+            for (int part = 0; part < parts; ++part, ++task)
+              if (task % nw == wave) {
+                int lo, hi;
+                part_range(Bt, part, parts, lo, hi);
+                double sp;
+                const double ap = l1_dense(dv, p32, x, lo, hi, sp);
+                if (lane == 0) {
+                  part_d[q * kMaxParts + part] = ap;
+                  part_s[q * kMaxParts + part] = sp;
+                }
+              }
+          }
+          __syncthreads();
+          if (threadIdx.x < pos && cur_e[threadIdx.x] < 0.0) {
+            double A = 0.0, S = 0.0;
+            for (int part = 0; part < parts; ++part) {
+              A += part_d[threadIdx.x * kMaxParts + part];
+              S += part_s[threadIdx.x * kMaxParts + part];
+            }
+            cur_d[threadIdx.x] = tc[1] - kLn2 * A;
+            cur_e[threadIdx.x] = l1_bound(S, tc[0], tc[3], Bt, dv.P64 != nullptr);
+          }
+          __syncthreads();
+          // the best row by value (ties: lowest id); settled when every other
+          // candidate's interval lies above the best's, and the best's lies
+          // wholly below the current vertex's (a move) or at or above it
+          double best = __builtin_inf(), be = 0.0;
+          for (int q = 1; q < pos; ++q) {
+            const double dq = cur_d[q];
+            const int xq = cur_x[q];
+            if (dq < best || (dq == best && xq < best_u)) {
+              best = dq;
+              be = cur_e[q];
+              best_u = xq;
+            }
+          }
+          bool sep = true;
+          for (int q = 1; q < pos; ++q)
+            if (cur_x[q] != best_u && !(cur_d[q] - cur_e[q] > best + be)) sep = false;
+          const double lo_v = cur_d[0] - cur_e[0], hi_v = cur_d[0] + cur_e[0];
+          if (sep && best + be < lo_v) {
+            settled = true;
+            stuck = false;
+          } else if (sep && best - be >= hi_v) {
+            settled = true;
+            stuck = true;
+          }
+        }
+      }
+      if (!settled) {
+        int task = 0;
+        for (int q = 0; q < pos; ++q) {
+          if (cur_e[q] == 0.0) continue;   // FP64 value known
+          const int x = cur_x[q];
           for (int part = 0; part < parts; ++part, ++task)
             if (task % nw == wave) {
               const double pd = exact_part<F>(dv, cv, a.is_csr, a.kind, p, lpt, tc, x, part, parts);
-              if (lane == 0) part_d[pos * kMaxParts + part] = pd;
+              if (lane == 0) part_d[q * kMaxParts + part] = pd;
             }
-        ++pos;
-      }
-      __syncthreads();
-      // new rows: their parts summed in order
-      if (threadIdx.x < pos && cur_new[threadIdx.x]) {
-        double dsum = 0.0;
-        for (int part = 0; part < parts; ++part) dsum += part_d[threadIdx.x * kMaxParts + part];
-        cur_d[threadIdx.x] = dsum * dscale;
-      }
-      __syncthreads();
-      const double dxv = cur_d[0];
-      double best = __builtin_inf();
-      int best_u = 0x7fffffff;
-      for (int q = 1; q < pos; ++q) {
-        const double dx = cur_d[q];
-        const int cu = cur_x[q];
-        if (dx < best || (dx == best && cu < best_u)) {
-          best = dx;
-          best_u = cu;
         }
+        __syncthreads();
+        // rows computed here: their parts summed in order
+        if (threadIdx.x < pos && cur_e[threadIdx.x] != 0.0) {
+          double dsum = 0.0;
+          for (int part = 0; part < parts; ++part) dsum += part_d[threadIdx.x * kMaxParts + part];
+          cur_d[threadIdx.x] = dsum * dscale;
+          cur_e[threadIdx.x] = 0.0;
+        }
+        __syncthreads();
+        double best = __builtin_inf();
+        best_u = 0x7fffffff;
+        for (int q = 1; q < pos; ++q) {
+          const double dx = cur_d[q];
+          const int cu = cur_x[q];
+          if (dx < best || (dx == best && cu < best_u)) {
+            best = dx;
+            best_u = cu;
+          }
+        }
+        stuck = !(best < cur_d[0]);
       }
       next = __builtin_amdgcn_readfirstlane(best_u);
-      stuck = __builtin_amdgcn_readfirstlane(best < dxv ? 0 : 1) != 0;
+      stuck = __builtin_amdgcn_readfirstlane(stuck ? 1 : 0) != 0;
       __syncthreads();   // everyone has read cur_* before it becomes prev_*
       if (threadIdx.x < pos) {
         prev_x[threadIdx.x] = cur_x[threadIdx.x];
         prev_d[threadIdx.x] = cur_d[threadIdx.x];
+        prev_e[threadIdx.x] = cur_e[threadIdx.x];
       }
       prev_n = pos;   // uniform
       __syncthreads();
@@ -904,15 +1130,25 @@ hipError_t launch_target_rows(DenseView dv, CsrView cv, PathArgs a, double* trow
 }
 
 // Target rows of up to kLdsTargetMax entries are staged in LDS (16 bytes per
-// entry: the row and its logs).
-constexpr int kLdsTargetMax = 8192;
+// entry: the row and its logs).  Longer rows are read from the target-row
+// buffers in the same load rounds as the kernel rows: a walk block holding
+// 130 KB of LDS (B = 8,146) leaves no room on its CU for the field kernels
+// that run beside the walks, which then lose a quarter of the machine (the
+// dense KL stream next to 64 walks at 1025²: 6.98 ms with the row in LDS,
+// 5.79 ms without, against 5.1 ms alone; the walks 14.6 and 16.7 ms).
+constexpr int kLdsTargetMax = 2048;
+
+// Level-1 rows read an FP32 copy of the target row from LDS (4 bytes per
+// entry); walks on longer rows use FP64 re-decisions only.
+constexpr int kL1LdsMax = 16384;
 
 template <typename K>
 static hipError_t launch_with_target(K kern, int threads, DenseView dv, CsrView cv, PathArgs a,
                                      hipStream_t s) {
   const int B = a.is_csr ? cv.B : dv.B;
   a.tgt_in_lds = B <= kLdsTargetMax ? 1 : 0;
-  const size_t lds = a.tgt_in_lds ? 16 * (size_t)B : 0;
+  if (a.is_csr || B > kL1LdsMax) a.l1 = 0;
+  const size_t lds = (a.tgt_in_lds ? 16 * (size_t)B : 0) + (a.l1 ? 4 * (size_t)B : 0);
   if (lds > 65536) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

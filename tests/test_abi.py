@@ -50,6 +50,7 @@ def test_null_handles_are_rejected_without_touching_the_device(lib):
     assert lib.dd_grid_poisson_kernel(None, 9, None, 0, 1, None, 0, None, 0, 1e-12, 10, 0, None,
                                       None) == L.DD_ESTATE
     assert lib.dd_destroy(None) == L.DD_ESTATE
+    assert lib.dd_path_level1(None, -1, None, None) == L.DD_ESTATE
     n = C.c_int32()
     assert lib.dd_plan_path(None, 0, 1, 0, 10, None, C.byref(n), C.byref(n), None, None) \
         == L.DD_ESTATE
