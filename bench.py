@@ -334,14 +334,22 @@ def run_grid1025(args):
     log("loading the tau=1e-5 truncation with FP16 stored values")
     kc = Kernel.load_dense(ctx, P, tau=TAU_1025, adjacency=adj, csr_values="f16")
     N, B = kd.N, kd.B
-    F = torch.empty((T, N), dtype=torch.float32, device="cuda:0")
-    f = torch.empty((4, N), dtype=torch.float32, device="cuda:0")
+    # two sets of field buffers: the walks of step k read set k % 2 on the side
+    # streams while step k + 1 computes its fields into the other set
+    Fs = [torch.empty((T, N), dtype=torch.float32, device="cuda:0") for _ in range(2)]
+    fs = [torch.empty((4, N), dtype=torch.float32, device="cuda:0") for _ in range(2)]
+    read_done = [None, None]
     tm = Timer(torch)
     main_s = torch.cuda.current_stream()
     side = [torch.cuda.Stream(), torch.cuda.Stream()]
     t0a, s0a = [t0], [s0]
 
-    def step(timed):
+    def step(k, timed):
+        j = k % 2
+        F, f = Fs[j], fs[j]
+        if read_done[j] is not None:
+            for e in read_done[j]:   # the walks of step k - 2 have read this set
+                main_s.wait_event(e)
         _, bds = tm.run("contraction", lambda: kd.batch_fields(ts, "kl", out=F), timed)
         ev = torch.cuda.Event()
         ev.record(main_s)
@@ -349,32 +357,42 @@ def run_grid1025(args):
         with torch.cuda.stream(side[0]):
             r_kl = tm.run("paths_kl", lambda: kd.trace_paths(ss, ts, "kl", F, bds,
                                                              args.max_steps), timed)
-        _, btv = tm.run("dense_tv", lambda: kd.field(t0, "tv", out=f[0]), timed)
+        # TV and KL of the first target: one pass over the dense rows, one over
+        # the truncated rows
+        _, (btv, _) = tm.run("dense_tv_kl", lambda: kd.fields_tv_kl(t0, out=f[0:2]), timed)
         ev = torch.cuda.Event()
         ev.record(main_s)
         side[1].wait_event(ev)
         with torch.cuda.stream(side[1]):
             r_tv = tm.run("path_tv", lambda: kd.trace_paths(s0a, t0a, "tv", f[0:1], [btv],
                                                             args.max_steps), timed)
-        tm.run("dense_kl", lambda: kd.field(t0, "kl", out=f[1]), timed)
-        tm.run("csr_tv", lambda: kc.field(t0, "tv", out=f[2]), timed)
-        tm.run("csr_kl", lambda: kc.field(t0, "kl", out=f[3]), timed)
+        tm.run("csr_tv_kl", lambda: kc.fields_tv_kl(t0, out=f[2:4]), timed)
+        read_done[j] = []
         for st in side:
-            main_s.wait_stream(st)
+            e = torch.cuda.Event()
+            e.record(st)
+            read_done[j].append(e)
         return r_kl, r_tv
 
+    def drain():
+        for st in side:
+            main_s.wait_stream(st)
+
     log(f"{args.warmup} warm-up steps, {args.steps} timed steps")
-    for _ in range(args.warmup):
-        step(False)
+    for k in range(args.warmup):
+        step(k, False)
+    drain()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
     e0.record()
-    for _ in range(args.steps):
-        r_kl, r_tv = step(True)
+    for k in range(args.steps):
+        r_kl, r_tv = step(k, True)
+    drain()   # the last step's walks end inside the timed region
     e1.record()
     torch.cuda.synchronize()
+    F, f = Fs[(args.steps - 1) % 2], fs[(args.steps - 1) % 2]
     wall = time.perf_counter() - wall0
     ms_per_step = e0.elapsed_time(e1) / args.steps
     fields_per_step = T + 4
@@ -382,11 +400,12 @@ def run_grid1025(args):
 
     lda = (B + 63) // 64 * 64
     nnz = kc.nnz
+    # CSR rows: 4 bytes per stored entry (FP16 value, 16-bit column); per row the
+    # start (8), length (4), scale (4), log floor (8) and two outputs (8)
     alg = {"contraction": N * lda * 4 + T * lda * 4 + T * N * 4 + N * 4,
-           "dense_tv": N * B * 4 + N * 4, "dense_kl": N * B * 4 + N * 4,
-           "csr_tv": nnz * 4 + N * 20, "csr_kl": nnz * 4 + N * 28}
+           "dense_tv_kl": N * B * 4 + 2 * N * 4, "csr_tv_kl": nnz * 4 + N * 32}
     kernels = {}
-    for n in ["contraction", "paths_kl", "dense_tv", "path_tv", "dense_kl", "csr_tv", "csr_kl"]:
+    for n in ["contraction", "paths_kl", "dense_tv_kl", "path_tv", "csr_tv_kl"]:
         us = tm.avg_us(n)
         kernels[n] = {"avg_us": round(us, 1)}
         if n in alg:
@@ -421,7 +440,7 @@ def run_grid1025(args):
     rows["truncation_bias"] = trunc_bias
     kc.free()
     kd.free()
-    del F, f
+    del F, f, Fs, fs
     torch.cuda.empty_cache()
     if not args.no_rows:
         rows.update(census_fp32_rows(torch, ctx, P, adj, ts_all))
@@ -444,8 +463,10 @@ def run_grid1025(args):
            "data": "synthetic",
            "config": {"workload": "grid 1025x1025, 20 rectangular obstacles (sides "
                                   "U[0.025,0.075]); 64 queries per step: KL fields by one f16x3 "
-                                  "contraction + 64 paths, dense TV/KL and truncated (tau=1e-5, "
-                                  "FP16 values) TV/KL streams of the first target, TV path",
+                                  "contraction + 64 paths, dense TV+KL and truncated (tau=1e-5, "
+                                  "FP16 values) TV+KL passes of the first target (both fields "
+                                  "per pass), TV path; "
+                                  "the walks of step k run beside the fields of step k+1",
                       "N": N, "B": B, "targets": T, "fields_per_step": fields_per_step,
                       "csr_nnz": nnz, "kernel_matrix_build_s": round(build_s, 1),
                       "cache": "cold by size (32 GB operands, 256 MB last-level cache)"},
@@ -628,6 +649,17 @@ def grid257_rows(torch, ctx, g, P):
     fns = {"dense_tv": lambda: kd.field(t, "tv", out=f), "dense_kl": lambda: kd.field(t, "kl", out=f),
            "csr_tv": lambda: kc.field(t, "tv", out=f), "csr_kl": lambda: kc.field(t, "kl", out=f),
            "gemm_kl_T1": lambda: kd.batch_fields([t], "kl", out=f)}
+    for kind in ("chi2", "hellinger"):
+        alg[f"dense_{kind}"] = N * B * 4 + N * 4
+        fns[f"dense_{kind}"] = (lambda kd_=kd, k_=kind: kd_.field(t, k_, out=f))
+    prow = np.asarray(P[t], dtype=np.float64)[np.asarray(P.max(axis=0) > 0)]
+    for tau_s in (1e-3, 1e-6):
+        keep = (prow > 0) & (prow >= tau_s * prow.max())
+        pieces = np.zeros((B + 3) // 4 * 4, dtype=bool)
+        pieces[:B] = keep
+        # 16 bytes per row piece meeting the target's support, plus the field
+        alg[f"support_kl_tau{tau_s:g}"] = N * int(pieces.reshape(-1, 4).any(axis=1).sum()) * 16 + N * 4
+        fns[f"support_kl_tau{tau_s:g}"] = (lambda ts_=tau_s: kd.support_kl_field(t, ts_, out=f))
     out = {}
     for n, fn in fns.items():
         cold = repeat(torch, tm, n + "c", fn, flush=flush)
@@ -635,11 +667,44 @@ def grid257_rows(torch, ctx, g, P):
         out[n] = {"median_us_flushed": round(cold, 2), "median_us_warm": round(warm, 2),
                   "alg_bytes": alg[n], "GB/s_flushed": round(gbs(alg[n], cold), 1),
                   "hbm_frac_flushed": round(gbs(alg[n], cold) / HBM_PEAK_GBS, 4)}
+    # 64 queries: paths on contraction fields, on-demand walks (FP64 rows only
+    # where the walk needs them), triangle paths on FP32 fields and on FP64 fields
+    T = 64
+    ts, ss = targets_sources(1, g.N, T)
+    D, bounds = kd.batch_fields(ts, "kl")
+    walks = {}
+    us = repeat(torch, tm, "paths", lambda: kd.trace_paths(ss, ts, "kl", D, bounds, 4000), reps=5,
+                warm=1)
+    r = kd.trace_paths(ss, ts, "kl", D, bounds, 4000)
+    walks["edge_paths_kl_T64"] = {"median_us": round(us, 1), "mean_vertices": float(r[1].float().mean()),
+                                  "fp64_rechecks": int(r[3].sum().item())}
+    for TT in (1, T):
+        us = repeat(torch, tm, f"od{TT}", lambda: kd.trace_paths_on_demand(ss[:TT], ts[:TT], "kl", 4000),
+                    reps=5, warm=1)
+        r = kd.trace_paths_on_demand(ss[:TT], ts[:TT], "kl", 4000)
+        walks[f"on_demand_kl_T{TT}"] = {"median_us": round(us, 1),
+                                        "rows_evaluated": int(r[3].sum().item())}
+    kd.attach_mesh(*g.interior_mesh())
+    us = repeat(torch, tm, "tri", lambda: kd.trace_paths_triangles(ss, ts, D, 20000), reps=5, warm=1)
+    r = kd.trace_paths_triangles(ss, ts, D, 20000)
+    walks["triangle_paths_kl_T64_fp32_fields"] = {"median_us": round(us, 1),
+                                                  "mean_points": float(r[2].float().mean()),
+                                                  "reached": int((r[3] == 0).sum().item())}
+    E = torch.empty((T, N), dtype=torch.float64, device="cuda:0")
+    us = repeat(torch, tm, "exact", lambda: kd.exact_fields(ts, "kl", out=E), reps=3, warm=1)
+    walks["exact_fp64_fields_kl_T64"] = {"median_us": round(us, 1), "us_per_field": round(us / T, 1)}
+    us = repeat(torch, tm, "tri64", lambda: kd.trace_paths_triangles(ss, ts, E, 20000), reps=5, warm=1)
+    r = kd.trace_paths_triangles(ss, ts, E, 20000)
+    walks["triangle_paths_kl_T64_fp64_fields"] = {"median_us": round(us, 1),
+                                                  "mean_points": float(r[2].float().mean()),
+                                                  "reached": int((r[3] == 0).sum().item())}
+    del D, E
     kd.free()
     kc.free()
     del scratch
     torch.cuda.empty_cache()
-    return {"d2_grid257": {"N": N, "B": B, "csr_nnz": nnz, "tau": TAU_257, "kernels": out}}
+    return {"d2_grid257": {"N": N, "B": B, "csr_nnz": nnz, "tau": TAU_257, "kernels": out,
+                           "walks": walks}}
 
 
 def grid_poisson_row(torch, ctx, g, P_host, build_s, batch=1024):
@@ -696,7 +761,7 @@ def green_row(torch, ctx, g, ts, kernels):
     del D
     torch.cuda.empty_cache()
     kl_c = kernels["contraction"]["avg_us"] / 1000.0 / T
-    kl_s = kernels["dense_kl"]["avg_us"] / 1000.0
+    kl_s = kernels["dense_tv_kl"]["avg_us"] / 1000.0   # one pass gives KL (and TV)
     log(f"Green's function: {ms:.1f} ms for {T} targets")
     return {"targets": T, "ms_per_batch": round(ms, 2), "ms_per_target": round(ms / T, 3),
             "cg_iterations": st["iterations"], "max_rel_residual": st["max_rel_residual"],
@@ -805,6 +870,13 @@ def run_grid257(args):
 
 def run_serving(args):
     """Open-loop serving over resident grid domains (2/5/10/20 obstacles)."""
+    # a hardware queue per domain slot, with room for the default stream and
+    # torch's side streams (the HIP runtime reads this when the first GPU call
+    # initialises it; a larger setting in the environment is kept)
+    from workloads import CONFIGS as _C
+    queues = min(32, len(_C["serving4"]["domains"]) * args.slots + 4)
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(queues)
     import torch  # noqa: F401
 
     from workloads import CONFIGS, grid_domain
@@ -824,7 +896,7 @@ def run_serving(args):
         return
 
     from paper_1708_02845_amd import Context
-    from paper_1708_02845_amd.serve import Server, latency_summary
+    from paper_1708_02845_amd.serve import Server, latency_breakdown, latency_summary
     ctx = Context(0)
     srv = Server(ctx, max_batch=c["max_batch"], slots_per_domain=args.slots,
                  max_steps=c["max_steps"])
@@ -852,7 +924,8 @@ def run_serving(args):
         sel = [q for q in qs if q.domain == nm]
         if sel:
             per_dom[nm] = {"N": n, "B": b, **latency_summary(sel),
-                           "reached": sum(q.status == "reached" for q in sel)}
+                           "reached": sum(q.status == "reached" for q in sel),
+                           "parts": latency_breakdown(sel)}
     out = {"metric": METRIC, "value": entries / wall, "unit": "entries/s", "n_gpus": 1,
            "steps": len(qs), "warmup": len(doms), "ms_per_step": 1000.0 * wall / len(qs),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16x3",
@@ -862,7 +935,8 @@ def run_serving(args):
                                   "batching",
                       "domains": [nm for nm, _, _ in doms], "refused": [r[0] for r in srv.refused],
                       "qps_offered": args.qps, "qps_achieved": len(qs) / wall,
-                      "max_batch": c["max_batch"], "slots_per_domain": args.slots},
+                      "max_batch": c["max_batch"], "slots_per_domain": args.slots,
+                      "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
            "latency": summ, "per_domain": per_dom,
            "batch_size_hist": dict(sorted(srv.batch_sizes.items())),
            "hbm_admitted_bytes": srv.hbm_used}

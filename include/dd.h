@@ -237,6 +237,16 @@ dd_status dd_dense_footprint(int32_t N, int32_t B, int32_t p_is_f64, const dd_lo
 dd_status dd_distance_field(dd_kernel* k, int32_t target, int32_t kind, float* out_dev,
                             dd_error_bound* bound, void* stream);
 
+/* The TV field (eq. 34) and the KL field (eq. 35) of one target in one pass
+ * over the rows: the values, and the bounds, of two dd_distance_field calls
+ * (DD_TV into tv_dev, DD_KL into kl_dev) for the bytes of one.  Dense and
+ * truncated handles (on a truncated handle, TV_tau and KL_tau).
+ *   tv_dev, kl_dev  device [N] FP32 each, distinct
+ *   bounds          host [2] (TV, KL), nullable
+ * Asynchronous on `stream`. */
+dd_status dd_distance_fields_tv_kl(dd_kernel* k, int32_t target, float* tv_dev, float* kl_dev,
+                                   dd_error_bound* bounds, void* stream);
+
 /* Distance fields of T targets into out_dev[T][N] (device FP32, one field
  * contiguous per target).  targets: host [T].  For DD_KL on a dense handle
  * built with a gemm_form the fields come from one contraction,

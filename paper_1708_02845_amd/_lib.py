@@ -65,6 +65,8 @@ EXPORTS = {
                                      C.POINTER(C.c_size_t)]),
     "dd_distance_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                     C.POINTER(dd_error_bound), C.c_void_p]),
+    "dd_distance_fields_tv_kl": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                           C.POINTER(dd_error_bound), C.c_void_p]),
     "dd_batch_distance_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                            C.POINTER(dd_error_bound), C.c_void_p]),
     "dd_trace_paths": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,

@@ -286,6 +286,16 @@ class Kernel:
                                             _stream_handle(stream)))
         return out, bound_tuple(b)
 
+    def fields_tv_kl(self, target, out=None, stream=None):
+        """(fields [2, N]: TV then KL, [(abs, rel) of TV, of KL]) of one target
+        from one pass over the rows."""
+        out = self._out((2, self.N), out)
+        b = (L.dd_error_bound * 2)()
+        L.check(self._lib.dd_distance_fields_tv_kl(
+            self._h, int(target), C.c_void_p(out[0].data_ptr()), C.c_void_p(out[1].data_ptr()), b,
+            _stream_handle(stream)))
+        return out, [bound_tuple(b[0]), bound_tuple(b[1])]
+
     def batch_fields(self, targets, kind, out=None, stream=None):
         """(fields [T, N], list of (abs, rel) bounds) for T targets: KL through the
         contraction when the handle has an operand, the pass over the stored rows

@@ -987,6 +987,24 @@ dd_status dd_distance_field(dd_kernel* k, int32_t target, int32_t kind, float* o
   return DD_OK;
 }
 
+dd_status dd_distance_fields_tv_kl(dd_kernel* k, int32_t target, float* tv_dev, float* kl_dev,
+                                   dd_error_bound* bounds, void* stream) {
+  if (!kernel_ok(k)) return fail(DD_ESTATE, "not a live kernel");
+  if (target < 0 || target >= k->N) return fail(DD_EINVAL, "target %d not in [0, %d)", target, k->N);
+  if (!tv_dev || !kl_dev) return fail(DD_EINVAL, "tv_dev or kl_dev is null");
+  if (tv_dev == kl_dev) return fail(DD_EINVAL, "tv_dev and kl_dev are the same buffer");
+  HIP_OR(hipSetDevice(k->ctx->device));
+  if (k->is_csr)
+    HIP_OR(dd::launch_csr_tv_kl(k->csr(), target, tv_dev, kl_dev, as_stream(stream)));
+  else
+    HIP_OR(dd::launch_dense_tv_kl(k->dense(), target, tv_dev, kl_dev, as_stream(stream)));
+  if (bounds) {
+    bounds[0] = field_bound(k, DD_TV, target);
+    bounds[1] = field_bound(k, DD_KL, target);
+  }
+  return DD_OK;
+}
+
 namespace {
 
 // Device scratch a batch call takes, in the order it takes it.

@@ -60,6 +60,10 @@ hipError_t launch_log_forms(DenseView v, int form, int64_t lda, float* l32, uint
 // ---- streaming fields (stream.hip) ----
 hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out, hipStream_t s);
 hipError_t launch_csr_field(CsrView v, int32_t target, int kind, float* out, hipStream_t s);
+// TV and KL of one target in one pass over the rows (the same values as two
+// single-kind launches)
+hipError_t launch_dense_tv_kl(DenseView v, int32_t target, float* tv, float* kl, hipStream_t s);
+hipError_t launch_csr_tv_kl(CsrView v, int32_t target, float* tv, float* kl, hipStream_t s);
 
 // ---- batched KL contraction (gemm.hip) ----
 // The log-kernel operand is stored in tiles of kGemmRows rows by kGemmK

@@ -18,6 +18,10 @@
 // exactly 0; the ln 2 factor is applied once per row in FP64.  Four FP32
 // terms are summed in FP32, then carried in FP64.
 //
+// KIND 7 computes the TV and the KL field of one target in one pass (the
+// same terms and sums as KINDs 0 and 1, so the same values): a caller that
+// wants both reads the rows once.
+//
 // chi-squared keeps 1/p_b in LDS (+inf where p_b = 0, so a row with mass
 // outside the target's support gets +inf) and forms (q - p) * ((q - p) / p).
 // Hellinger is evaluated as ((q - p) / (sqrt q + sqrt p))^2, which equals
@@ -87,7 +91,7 @@ __device__ __forceinline__ float alpha_term(float p, float r, float q, int j) {
 // sqrt p (Hellinger).
 template <int KIND>
 __device__ __forceinline__ float stage_aux(float p) {
-  if (KIND == 1) return p > 0.f ? hw_log2(p) : 0.f;
+  if (KIND == 1 || KIND == 7) return p > 0.f ? hw_log2(p) : 0.f;
   if (KIND == 2 || KIND == 4) return p > 0.f ? 1.0f / p : __builtin_inff();
   if (KIND == 5) return p > 0.f ? 1.0f / p : 0.f;
   return sqrtf(p);
@@ -129,7 +133,8 @@ __device__ __forceinline__ double row_factor(int param) {
 template <int LPR, int KIND, int UNROLL>
 __global__ __launch_bounds__(512) void dense_field_kernel(const float* __restrict__ P, int64_t ld,
                                                           int32_t N, int32_t target, int param,
-                                                          float* __restrict__ out) {
+                                                          float* __restrict__ out,
+                                                          float* __restrict__ out2) {
   extern __shared__ float4 smem4[];
   const int nv = (int)(ld >> 2);
   float4* sp = smem4;
@@ -149,7 +154,7 @@ __global__ __launch_bounds__(512) void dense_field_kernel(const float* __restric
   const int gpb = blockDim.x / LPR;
   for (int64_t row = (int64_t)blockIdx.x * gpb + grp; row < N; row += (int64_t)gridDim.x * gpb) {
     const float4* q = reinterpret_cast<const float4*>(P + row * ld);
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
     for (int base = lane; base < nv; base += LPR * UNROLL) {
       float4 v[UNROLL];
 #pragma unroll
@@ -163,13 +168,24 @@ __global__ __launch_bounds__(512) void dense_field_kernel(const float* __restric
         if (i < nv) {
           const float4 p = sp[i];
           const float4 aux = KIND != 0 ? sl[i] : p;
-          acc += (double)term4<KIND>(p, aux, v[u], param);
+          if (KIND == 7) {
+            acc += (double)term4<0>(p, p, v[u], param);
+            acc2 += (double)term4<1>(p, aux, v[u], param);
+          } else {
+            acc += (double)term4<KIND>(p, aux, v[u], param);
+          }
         }
       }
     }
 #pragma unroll
-    for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
-    if (lane == 0) out[row] = (float)(KIND == 1 || KIND == 5 ? acc * row_factor<KIND>(param) : acc);
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+      acc += __shfl_xor(acc, off, LPR);
+      if (KIND == 7) acc2 += __shfl_xor(acc2, off, LPR);
+    }
+    if (lane == 0) {
+      out[row] = (float)(KIND == 1 || KIND == 5 ? acc * row_factor<KIND>(param) : acc);
+      if (KIND == 7) out2[row] = (float)(acc2 * row_factor<1>(0));
+    }
   }
 }
 
@@ -270,7 +286,8 @@ __device__ __forceinline__ float f16_value(uint16_t h, float rs) {
 
 template <int LPR, int KIND, int UNROLL, int F16>
 __global__ __launch_bounds__(512) void csr_field_kernel(CsrView v, int32_t target,
-                                                        float* __restrict__ out) {
+                                                        float* __restrict__ out,
+                                                        float* __restrict__ out2) {
   // LDS: the truncated target row as (p, log2 p) pairs, zeros where dropped
   extern __shared__ float2 smem2[];
   const int Bp = (v.B + 3) & ~3;
@@ -317,7 +334,7 @@ __global__ __launch_bounds__(512) void csr_field_kernel(CsrView v, int32_t targe
     const float rs = F16 ? v.rscale[row] : 1.f;
     const ushort4* col4 = reinterpret_cast<const ushort4*>(v.col + s);
     const int nv = (n + 3) >> 2;
-    double acc = 0.0, A = 0.0, E = 0.0;
+    double acc = 0.0, acc2 = 0.0, A = 0.0, E = 0.0;
     // Loads are unconditional (index clamped into the row) and entries past
     // the row's end are masked arithmetically, so the loop has no divergent
     // branch that would make the loads wait.  Padding slots hold column 0.
@@ -342,38 +359,41 @@ __global__ __launch_bounds__(512) void csr_field_kernel(CsrView v, int32_t targe
         const int rem = i < nv ? n - 4 * i : 0;
         const float qv[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
         const int bv[4] = {cb[u].x, cb[u].y, cb[u].z, cb[u].w};
-        float ts4 = 0.f, as4 = 0.f, es4 = 0.f;
+        float ts4 = 0.f, ks4 = 0.f, as4 = 0.f, es4 = 0.f;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const bool ok = e < rem;
           const float2 pl = spl[bv[e]];
           const float p = ok ? pl.x : 0.f;
           as4 += p;
-          if (KIND == 0) {
-            ts4 += fabsf((ok ? qv[e] : 0.f) - p);
-          } else {
-            ts4 += p * (pl.y - hw_log2(ok ? qv[e] : 1.f));
+          if (KIND != 1) ts4 += fabsf((ok ? qv[e] : 0.f) - p);
+          if (KIND != 0) {
+            ks4 += p * (pl.y - hw_log2(ok ? qv[e] : 1.f));
             es4 += p * pl.y;
           }
         }
-        acc += (double)ts4;
+        if (KIND != 1) acc += (double)ts4;
+        if (KIND != 0) acc2 += (double)ks4;
         A += (double)as4;
-        if (KIND == 1) E += (double)es4;
+        if (KIND != 0) E += (double)es4;
       }
     }
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1) {
-      acc += __shfl_xor(acc, off, LPR);
+      if (KIND != 1) acc += __shfl_xor(acc, off, LPR);
+      if (KIND != 0) {
+        acc2 += __shfl_xor(acc2, off, LPR);
+        E += __shfl_xor(E, off, LPR);
+      }
       A += __shfl_xor(A, off, LPR);
-      if (KIND == 1) E += __shfl_xor(E, off, LPR);
     }
     if (lane == 0) {
-      double d;
-      if (KIND == 0)
-        d = acc + (Wt - A);
-      else
-        d = (acc + (Hbt - E) - v.lphi[row] * (Wt - A)) * 0.69314718055994530942;
-      out[row] = row == target ? 0.f : (float)d;
+      // KIND 0: TV into out; 1: KL into out; 2: TV into out and KL into out2
+      const double tv = acc + (Wt - A);
+      const double kl = (acc2 + (Hbt - E) - v.lphi[row] * (Wt - A)) * 0.69314718055994530942;
+      if (KIND != 1) out[row] = row == target ? 0.f : (float)tv;
+      if (KIND == 1) out[row] = row == target ? 0.f : (float)kl;
+      if (KIND == 2) out2[row] = row == target ? 0.f : (float)kl;
     }
   }
 }
@@ -414,27 +434,29 @@ static int grid_for(int64_t groups_needed, int gpb, int threads, size_t lds) {
 }
 
 template <int LPR, int KIND>
-static hipError_t dense_launch(DenseView v, int32_t target, int param, float* out, hipStream_t s) {
-  // TV and KL: six 16-byte loads per lane in flight (a 257^2 row in one round
-  // trip); the other kinds carry more per-entry state
-  constexpr int UNROLL = KIND <= 1 ? 6 : 4;
+static hipError_t dense_launch(DenseView v, int32_t target, int param, float* out, hipStream_t s,
+                               float* out2 = nullptr) {
+  // TV and KL (apart or together): six 16-byte loads per lane in flight (a
+  // 257^2 row in one round trip); the other kinds carry more per-entry state
+  constexpr int UNROLL = KIND <= 1 || KIND == 7 ? 6 : 4;
   auto kern = dense_field_kernel<LPR, KIND, UNROLL>;
   const size_t lds = (size_t)v.ld * sizeof(float) * (KIND != 0 ? 2 : 1);
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int threads = block_threads(lds);
   const int grid = grid_for(v.N, threads / LPR, threads, lds);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v.P, v.ld, v.N, target, param, out);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v.P, v.ld, v.N, target, param, out,
+                     out2);
   return hipGetLastError();
 }
 
 template <int KIND>
 static hipError_t dense_dispatch(DenseView v, int32_t target, int param, float* out,
-                                 hipStream_t s) {
+                                 hipStream_t s, float* out2 = nullptr) {
   const int64_t nv = v.ld / 4;
-  if (nv >= 256) return dense_launch<64, KIND>(v, target, param, out, s);
-  if (nv >= 128) return dense_launch<32, KIND>(v, target, param, out, s);
-  return dense_launch<16, KIND>(v, target, param, out, s);
+  if (nv >= 256) return dense_launch<64, KIND>(v, target, param, out, s, out2);
+  if (nv >= 128) return dense_launch<32, KIND>(v, target, param, out, s, out2);
+  return dense_launch<16, KIND>(v, target, param, out, s, out2);
 }
 
 // kind: 0 TV, 1 KL, 2 chi-squared, 3 Hellinger, 100 + k power k (1..16),
@@ -449,6 +471,10 @@ hipError_t launch_dense_field(DenseView v, int32_t target, int kind, float* out,
     case 3: return dense_dispatch<3>(v, target, 0, out, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_dense_tv_kl(DenseView v, int32_t target, float* tv, float* kl, hipStream_t s) {
+  return dense_dispatch<7>(v, target, 0, tv, s, kl);
 }
 
 template <int LPR>
@@ -474,14 +500,15 @@ hipError_t launch_support_kl_field(DenseView v, int32_t target, double tau, int 
 }
 
 template <int LPR, int KIND, int F16>
-static hipError_t csr_launch(CsrView v, int32_t target, float* out, hipStream_t s) {
+static hipError_t csr_launch(CsrView v, int32_t target, float* out, hipStream_t s,
+                             float* out2 = nullptr) {
   auto kern = csr_field_kernel<LPR, KIND, 2, F16>;
   const size_t lds = (size_t)((v.B + 3) & ~3) * sizeof(float) * 2;
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int threads = block_threads(lds);
   const int grid = grid_for(v.N, threads / LPR, threads, lds);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v, target, out);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, v, target, out, out2);
   return hipGetLastError();
 }
 
@@ -493,6 +520,11 @@ hipError_t launch_csr_field(CsrView v, int32_t target, int kind, float* out, hip
   }
   if (kind == 0) return csr_launch<64, 0, 0>(v, target, out, s);
   return csr_launch<64, 1, 0>(v, target, out, s);
+}
+
+hipError_t launch_csr_tv_kl(CsrView v, int32_t target, float* tv, float* kl, hipStream_t s) {
+  if (v.val16) return csr_launch<64, 2, 1>(v, target, tv, s, kl);
+  return csr_launch<64, 2, 0>(v, target, tv, s, kl);
 }
 
 }  // namespace dd

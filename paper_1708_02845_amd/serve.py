@@ -17,7 +17,9 @@ query keeps a device view of its own field (``Query.field``).
 """
 
 import collections
+import os
 import time
+import warnings
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -34,7 +36,10 @@ class Query:
     source: int
     target: int
     arrival: float                # host clock (perf_counter seconds)
+    launched: float = None        # host clock when its batch was launched
     done: float = None
+    gpu_ms: float = None          # its batch's time on the device (stream events)
+    launch_host_ms: float = None  # host time spent enqueuing its batch
     path: list = None
     status: str = None
     rechecks: int = 0
@@ -45,6 +50,11 @@ class Query:
     def latency(self):
         return None if self.done is None else self.done - self.arrival
 
+    @property
+    def wait(self):
+        """Arrival to launch (queueing behind the domain's previous batch)."""
+        return None if self.launched is None else self.launched - self.arrival
+
 
 class _Slot:
     def __init__(self, torch, max_batch, max_steps):
@@ -52,6 +62,9 @@ class _Slot:
         self.busy = False
         self.queries = []
         self.event = None
+        self.start = None
+        self.launched = None
+        self.launch_host_ms = None
         self.fields = None
         self.host_paths = torch.empty((max_batch, max_steps + 1), dtype=torch.int32,
                                       pin_memory=True)
@@ -70,10 +83,17 @@ class Server:
     """Resident domains, per-domain queues and continuous batching.
 
     Each slot is a stream.  HIP maps a process's streams onto a few hardware
-    queues (GPU_MAX_HW_QUEUES, 4 by default); keeping domains x slots within
-    that number gives every domain a queue of its own, so a short batch never
-    waits behind another domain's long one.
+    queues (GPU_MAX_HW_QUEUES, 4 by default, read when the runtime starts);
+    streams beyond that share queues, and a batch then waits behind whatever
+    another stream of its queue holds.  The default stream takes a queue too,
+    so domains x slots + 1 queues give every slot one of its own
+    (``queues_needed``); add_domain warns when the setting is below that.
     """
+
+    @staticmethod
+    def queues_needed(n_domains, slots_per_domain):
+        return n_domains * slots_per_domain + 1
+
 
     def __init__(self, ctx, max_batch=64, slots_per_domain=1, max_steps=4000,
                  hbm_budget=None, gemm_form="f16x3", field_reserve=2, keep_fields=False):
@@ -122,6 +142,12 @@ class Server:
             k.free()
             self.refused.append((name, need))
             return False
+        queues = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+        wanted = self.queues_needed(len(self.domains) + 1, self.slots_per_domain)
+        if wanted > queues:
+            warnings.warn(f"{wanted} hardware queues would give every batch slot its own, "
+                          f"GPU_MAX_HW_QUEUES is {queues}: slots share queues, and a short "
+                          "batch can wait behind a long one of another domain")
         slots = [_Slot(self.torch, self.max_batch, self.max_steps)
                  for _ in range(self.slots_per_domain)]
         self.domains[name] = _Domain(name, k, slots)
@@ -159,8 +185,11 @@ class Server:
         qs = take_batch(d.queue, n)
         ts = np.array([q.target for q in qs], dtype=np.int32)
         ss = np.array([q.source for q in qs], dtype=np.int32)
+        t_launch = time.perf_counter()
         try:
             with torch.cuda.stream(slot.stream):
+                start = torch.cuda.Event(enable_timing=True)
+                start.record(slot.stream)
                 fields = torch.empty((n, N), dtype=torch.float32,
                                      device=f"cuda:{self.ctx.device}")
                 _, bounds = d.kernel.batch_fields(ts, "kl", out=fields, stream=slot.stream)
@@ -170,7 +199,7 @@ class Server:
                 slot.host_info[0, :n].copy_(lens, non_blocking=True)
                 slot.host_info[1, :n].copy_(status, non_blocking=True)
                 slot.host_info[2, :n].copy_(rechecks, non_blocking=True)
-                ev = torch.cuda.Event()
+                ev = torch.cuda.Event(enable_timing=True)
                 ev.record(slot.stream)
         except Exception:
             # the queries go back to the front of the queue, in order; with other
@@ -180,6 +209,8 @@ class Server:
                 return False
             raise
         slot.busy, slot.queries, slot.event, slot.fields = True, qs, ev, fields
+        slot.start, slot.launched = start, t_launch
+        slot.launch_host_ms = 1e3 * (time.perf_counter() - t_launch)
         self.batch_sizes[n] += 1
         return True
 
@@ -187,11 +218,13 @@ class Server:
         now = time.perf_counter()
         info = slot.host_info.numpy()
         paths = slot.host_paths.numpy()
+        gpu_ms = slot.start.elapsed_time(slot.event)
         for i, q in enumerate(slot.queries):
             q.path = paths[i, :info[0, i]].tolist()
             q.status = _STATUS[int(info[1, i])]
             q.rechecks = int(info[2, i])
             q.batch_size = len(slot.queries)
+            q.launched, q.gpu_ms, q.launch_host_ms = slot.launched, gpu_ms, slot.launch_host_ms
             if self.keep_fields:
                 q.field = slot.fields[i]
             q.done = now
@@ -257,3 +290,22 @@ def latency_summary(queries):
     return {"queries": len(lat), "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
             "mean_ms": float(lat.mean())}
+
+
+def latency_breakdown(queries):
+    """p50/p99/max (ms) of the parts of the latency: the wait from arrival to
+    the launch of the query's batch, the host time of that launch, and the
+    batch's time on the device (from its first to its last stream event,
+    including any time its kernels wait for the device behind other streams'
+    work), and the rest: the time before the batch's first event runs (behind
+    earlier work in the same hardware queue) and until the host polls the
+    completion."""
+    out = {}
+    rest = [1e3 * q.latency - 1e3 * q.wait - q.launch_host_ms - q.gpu_ms for q in queries]
+    for name, vals in (("wait", [1e3 * q.wait for q in queries]),
+                       ("launch_host", [q.launch_host_ms for q in queries]),
+                       ("gpu", [q.gpu_ms for q in queries]), ("rest", rest)):
+        v = np.array(vals, dtype=np.float64)
+        out[name] = {"p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99)),
+                     "max_ms": float(v.max())}
+    return out

@@ -21,7 +21,7 @@ def domains():
 
 
 def test_mix_equals_alone(gpu_ctx, domains):
-    from paper_1708_02845_amd.serve import Server, latency_summary
+    from paper_1708_02845_amd.serve import Server, latency_breakdown, latency_summary
     srv = Server(gpu_ctx, max_batch=16, slots_per_domain=2, max_steps=2000, keep_fields=True)
     try:
         for name, (P, adj) in domains.items():
@@ -37,6 +37,9 @@ def test_mix_equals_alone(gpu_ctx, domains):
             assert q.path[0] == q.source
         s = latency_summary(qs)
         assert 0 < s["p50_ms"] <= s["p99_ms"] <= s["max_ms"]
+        b = latency_breakdown(qs)
+        assert b["gpu"]["p50_ms"] > 0 and b["wait"]["p50_ms"] >= 0
+        assert b["gpu"]["max_ms"] <= s["max_ms"] and b["wait"]["max_ms"] <= s["max_ms"]
         # each query alone: the same field (bit for bit) and the same path
         for q in qs[::7]:
             k = srv.domains[q.domain].kernel
