@@ -295,6 +295,11 @@ def cpu_baseline_grid257(P32, tau, t, s, adj, max_steps, entries_per_step):
 # ----------------------------------------------------------------------------- grid1025
 
 def run_grid1025(args):
+    # four streams (the main one, two for the walks, one for the TV path), each
+    # on a hardware queue of its own (read when the first GPU call starts the
+    # runtime)
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
+        os.environ["GPU_MAX_HW_QUEUES"] = "8"
     import torch  # noqa: F401  (no GPU call before the kernel matrices exist)
 
     from workloads import build_config
@@ -334,14 +339,17 @@ def run_grid1025(args):
     log("loading the tau=1e-5 truncation with FP16 stored values")
     kc = Kernel.load_dense(ctx, P, tau=TAU_1025, adjacency=adj, csr_values="f16")
     N, B = kd.N, kd.B
-    # two sets of field buffers: the walks of step k read set k % 2 on the side
-    # streams while step k + 1 computes its fields into the other set
+    # two sets of field buffers: the walks of step k read set k % 2 on their own
+    # stream (one per set, so the walks of consecutive steps may overlap) while
+    # step k + 1 computes its fields into the other set
     Fs = [torch.empty((T, N), dtype=torch.float32, device="cuda:0") for _ in range(2)]
     fs = [torch.empty((4, N), dtype=torch.float32, device="cuda:0") for _ in range(2)]
     read_done = [None, None]
     tm = Timer(torch)
     main_s = torch.cuda.current_stream()
-    side = [torch.cuda.Stream(), torch.cuda.Stream()]
+    walk_s = [torch.cuda.Stream(), torch.cuda.Stream()]
+    tv_s = torch.cuda.Stream()
+    side = walk_s + [tv_s]
     t0a, s0a = [t0], [s0]
 
     def step(k, timed):
@@ -353,8 +361,8 @@ def run_grid1025(args):
         _, bds = tm.run("contraction", lambda: kd.batch_fields(ts, "kl", out=F), timed)
         ev = torch.cuda.Event()
         ev.record(main_s)
-        side[0].wait_event(ev)
-        with torch.cuda.stream(side[0]):
+        walk_s[j].wait_event(ev)
+        with torch.cuda.stream(walk_s[j]):
             r_kl = tm.run("paths_kl", lambda: kd.trace_paths(ss, ts, "kl", F, bds,
                                                              args.max_steps), timed)
         # TV and KL of the first target: one pass over the dense rows, one over
@@ -362,13 +370,13 @@ def run_grid1025(args):
         _, (btv, _) = tm.run("dense_tv_kl", lambda: kd.fields_tv_kl(t0, out=f[0:2]), timed)
         ev = torch.cuda.Event()
         ev.record(main_s)
-        side[1].wait_event(ev)
-        with torch.cuda.stream(side[1]):
+        tv_s.wait_event(ev)
+        with torch.cuda.stream(tv_s):
             r_tv = tm.run("path_tv", lambda: kd.trace_paths(s0a, t0a, "tv", f[0:1], [btv],
                                                             args.max_steps), timed)
         tm.run("csr_tv_kl", lambda: kc.fields_tv_kl(t0, out=f[2:4]), timed)
         read_done[j] = []
-        for st in side:
+        for st in (walk_s[j], tv_s):
             e = torch.cuda.Event()
             e.record(st)
             read_done[j].append(e)

@@ -544,6 +544,9 @@ __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrVi
   __shared__ double cur_d[65], prev_d[65], cur_e[65], prev_e[65];
   __shared__ double part_d[65 * kMaxParts], part_s[65 * kMaxParts];
   int prev_n = 0;
+  // the walk is a chain of short dependent steps that shares its compute unit
+  // with the field kernels of other streams: its waves issue first
+  __builtin_amdgcn_s_setprio(3);
   stage_log_table();
   const int i = blockIdx.x;
   const int lane = threadIdx.x & 63;
