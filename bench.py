@@ -49,7 +49,8 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f16x3": 2500.0, "bf16x3": 2500.0, "f16": 2500.0, "f32": 157.3}
 # source file of each measured kernel, for matching counter records to the code
 KERNEL_SOURCE = {"dense_tv": "stream.hip", "dense_kl": "stream.hip", "csr_tv": "stream.hip",
-                 "csr_kl": "stream.hip", "gemm_kl_T1": "gemm.hip", "kl_gemm_f16x3": "gemm.hip"}
+                 "csr_kl": "stream.hip", "gemm_kl_T1": "gemm.hip", "kl_gemm_f16x3": "gemm.hip",
+                 "dense_tv_kl": "stream.hip", "csr_tv_kl": "stream.hip"}
 METRIC = "kernel entries/sec (N·B·targets/s)"
 TAU_1025 = 1e-5
 TAU_257 = 1e-6
@@ -419,6 +420,8 @@ def run_grid1025(args):
         if n in alg:
             kernels[n].update({"alg_bytes": alg[n], "GB/s": round(gbs(alg[n], us), 1),
                                "hbm_frac": round(gbs(alg[n], us) / HBM_PEAK_GBS, 4)})
+        if n in ("dense_tv_kl", "csr_tv_kl"):
+            kernels[n]["traffic"] = measured_traffic("grid1025", n)
     c_us = kernels["contraction"]["avg_us"]
     flops = 6.0 * N * B * T
     kernels["contraction"]["mfma_TFLOP/s"] = round(flops / (c_us * 1e-6) / 1e12, 1)
