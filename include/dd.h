@@ -317,9 +317,11 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
 
 /* Paths with distances evaluated on demand (Section V: the CPU evaluates
  * the distances only at the vertices the path needs): no field is given; at
- * each step the FP64 distances of the current vertex's neighbours are
- * computed from the resident rows and the walk of dd_trace_paths is taken on
- * them, so the path is the one the exact FP64 field gives.
+ * each step the distances of the current vertex's neighbours are computed
+ * from the resident rows (for DD_KL on a dense handle first as level-1 values,
+ * see dd_path_level1, and in FP64 where those do not settle the step) and the
+ * walk of dd_trace_paths is taken on them, so the path is the one the exact
+ * FP64 field gives.
  *   kind          as for the field entry points (dense: all kinds; CSR: TV, KL
  *                 of the truncated rows)
  *   target_tau    0, or with DD_KL on a dense handle the truncation of the
@@ -327,7 +329,8 @@ dd_status dd_trace_paths(dd_kernel* k, int32_t T, const int32_t* sources, const 
  *                 dd_support_kl_field); row-relative if target_tau_relative
  *   sources, targets  host [T]
  *   path_dev, len_dev, status_dev  as for dd_trace_paths
- *   evals_dev     device [T] int32 distances evaluated per path, nullable
+ *   evals_dev     device [T] int32 rows evaluated per path (each row counted
+ *                 once, whether at level 1, in FP64 or both), nullable
  * Needs the adjacency.  Asynchronous on `stream`. */
 dd_status dd_trace_paths_on_demand(dd_kernel* k, int32_t T, const int32_t* sources,
                                    const int32_t* targets, int32_t kind, double target_tau,

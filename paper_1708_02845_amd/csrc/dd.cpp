@@ -1269,6 +1269,7 @@ dd_status dd_trace_paths_on_demand(dd_kernel* k, int32_t T, const int32_t* sourc
   a.max_steps = max_steps;
   a.kind = kind;
   a.is_csr = k->is_csr;
+  a.l1 = k->ctx->l1_on && kind == DD_KL && !k->is_csr ? 1 : 0;
   a.tgt_tau = target_tau;
   a.tgt_tau_relative = target_tau_relative ? 1 : 0;
   // scratch: [sources, targets when T is large] [FP64 target rows, logs, constants]

@@ -841,8 +841,8 @@ __global__ __launch_bounds__(kPathThreads) void paths_kernel(DenseView dv, CsrVi
 template <int F>
 __global__ __launch_bounds__(256) void paths_on_demand_kernel(DenseView dv, CsrView cv,
                                                               PathArgs a) {
-  __shared__ int cur_x[65], prev_x[65];
-  __shared__ double cur_d[65], prev_d[65];
+  __shared__ int cur_x[66], prev_x[66];
+  __shared__ double cur_d[66], prev_d[66], cur_e[66], prev_e[66], new_d[66], new_e[66];
   __shared__ double first_d;
   stage_log_table();
   const int i = blockIdx.x;
@@ -864,6 +864,19 @@ __global__ __launch_bounds__(256) void paths_on_demand_kernel(DenseView dv, CsrV
     p = tsh;
     lpt = tsh + Bt;
   }
+  // the FP32 target row of the level-1 rows, after the FP64 rows when those
+  // are staged too
+  const float* p32 = nullptr;
+  if constexpr (F == 1) {
+    if (a.l1) {
+      extern __shared__ double tsh[];
+      float* ps = reinterpret_cast<float*>(tsh + (a.tgt_in_lds ? 2 * Bt : 0));
+      const double* pg = a.trow + (int64_t)i * Bt;
+      for (int b = threadIdx.x; b < Bt; b += blockDim.x) ps[b] = (float)pg[b];
+      __syncthreads();
+      p32 = ps;
+    }
+  }
   const double* tc = a.tconst + (int64_t)i * 4;
   int32_t* path = a.path + (int64_t)i * (a.max_steps + 1);
   const int32_t* __restrict__ adj = a.adj;
@@ -874,7 +887,7 @@ __global__ __launch_bounds__(256) void paths_on_demand_kernel(DenseView dv, CsrV
     if (lane == 0) first_d = dx;
   }
   __syncthreads();
-  double dcur = uniform(first_d);
+  double dcur = uniform(first_d), ecur = 0.0;
   int evals = 1;
   int prev_n = 0;
   int len = 1;
@@ -897,56 +910,127 @@ __global__ __launch_bounds__(256) void paths_on_demand_kernel(DenseView dv, CsrV
       status = 1;
       break;
     }
+    // rows: the current vertex (position 0, known) and its neighbours, each
+    // with a value and a bound (0 for an FP64 value, negative while unknown).
+    // KL walks on dense rows take level-1 values first (l1_dense, l1_bound)
+    // and compute rows in FP64 only when those intervals do not settle the
+    // step, which is then the step of the FP64 values.
     uint64_t rest = live;
-    int pos = 0;
+    int pos = 1;
+    if (threadIdx.x == 0) {
+      cur_x[0] = v;
+      cur_d[0] = dcur;
+      cur_e[0] = ecur;
+    }
     while (rest) {
       const int x = __builtin_amdgcn_readlane(ul, (int)__builtin_ctzll(rest));
       rest &= rest - 1;
-      int hit = -1;
+      double dx = 0.0, ex = -1.0;
       for (int q = 0; q < prev_n; ++q)
-        if (prev_x[q] == x) hit = q;
-      hit = __builtin_amdgcn_readfirstlane(hit);
-      if (hit < 0) ++evals;
-      if (pos % nw == wave) {
-        const double dx = hit >= 0 ? prev_d[hit]
-                                   : exact_distance<F>(dv, cv, a.is_csr, a.kind, p, lpt, tc, x);
-        if (lane == 0) {
-          cur_x[pos] = x;
-          cur_d[pos] = dx;
+        if (prev_x[q] == x) {
+          dx = prev_d[q];
+          ex = prev_e[q];
         }
+      if (ex < 0.0) ++evals;
+      if (threadIdx.x == 0) {
+        cur_x[pos] = x;
+        cur_d[pos] = dx;
+        cur_e[pos] = ex;
       }
       ++pos;
     }
     __syncthreads();
-    double best = __builtin_inf();
+    bool settled = false, stop = false;
     int best_u = 0x7fffffff;
-    for (int q = 0; q < pos; ++q) {
-      const double dx = cur_d[q];
-      const int cu = cur_x[q];
-      if (dx < best || (dx == best && cu < best_u)) {
-        best = dx;
-        best_u = cu;
+    double best = __builtin_inf(), best_e = 0.0;
+    if constexpr (F == 1) {
+      if (a.l1) {
+        int task = 0;
+        for (int q = 1; q < pos; ++q) {
+          if (cur_e[q] >= 0.0) continue;   // known
+          if (task++ % nw == wave) {
+            double sp;
+            const double ap = l1_dense(dv, p32, cur_x[q], 0, Bt, sp);
+            if (lane == 0) {
+              new_d[q] = tc[1] - kLn2 * ap;
+              new_e[q] = l1_bound(sp, tc[0], tc[3], Bt, dv.P64 != nullptr);
+            }
+          }
+        }
+        __syncthreads();
+        if (threadIdx.x < pos && cur_e[threadIdx.x] < 0.0) {
+          cur_d[threadIdx.x] = new_d[threadIdx.x];
+          cur_e[threadIdx.x] = new_e[threadIdx.x];
+        }
+        __syncthreads();
+        for (int q = 1; q < pos; ++q) {
+          const double dq = cur_d[q];
+          const int xq = cur_x[q];
+          if (dq < best || (dq == best && xq < best_u)) {
+            best = dq;
+            best_e = cur_e[q];
+            best_u = xq;
+          }
+        }
+        bool sep = true;
+        for (int q = 1; q < pos; ++q)
+          if (cur_x[q] != best_u && !(cur_d[q] - cur_e[q] > best + best_e)) sep = false;
+        if (sep && best + best_e < cur_d[0] - cur_e[0]) {
+          settled = true;
+        } else if (sep && best - best_e >= cur_d[0] + cur_e[0]) {
+          settled = true;
+          stop = true;
+        }
       }
     }
+    if (!settled) {
+      // FP64 values for every row that has none (the current vertex included)
+      int task = 0;
+      for (int q = 0; q < pos; ++q) {
+        if (cur_e[q] == 0.0) continue;
+        if (task++ % nw == wave) {
+          const double dx = exact_distance<F>(dv, cv, a.is_csr, a.kind, p, lpt, tc, cur_x[q]);
+          if (lane == 0) new_d[q] = dx;
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x < pos && cur_e[threadIdx.x] != 0.0) {
+        cur_d[threadIdx.x] = new_d[threadIdx.x];
+        cur_e[threadIdx.x] = 0.0;
+      }
+      __syncthreads();
+      best = __builtin_inf();
+      best_u = 0x7fffffff;
+      for (int q = 1; q < pos; ++q) {
+        const double dx = cur_d[q];
+        const int cu = cur_x[q];
+        if (dx < best || (dx == best && cu < best_u)) {
+          best = dx;
+          best_u = cu;
+        }
+      }
+      best_e = 0.0;
+      stop = !(best < cur_d[0]);
+    }
     best = uniform(best);
+    best_e = uniform(best_e);
     best_u = __builtin_amdgcn_readfirstlane(best_u);
+    stop = __builtin_amdgcn_readfirstlane(stop ? 1 : 0) != 0;
     __syncthreads();   // everyone has read cur_* before it becomes prev_*
     if (threadIdx.x < pos) {
       prev_x[threadIdx.x] = cur_x[threadIdx.x];
       prev_d[threadIdx.x] = cur_d[threadIdx.x];
+      prev_e[threadIdx.x] = cur_e[threadIdx.x];
     }
-    if (threadIdx.x == 0) {
-      prev_x[pos] = v;
-      prev_d[pos] = dcur;
-    }
-    prev_n = pos + 1;
+    prev_n = pos;
     __syncthreads();
-    if (!(best < dcur)) {
+    if (stop) {
       status = 1;
       break;
     }
     v = best_u;
     dcur = best;
+    ecur = best_e;
     if (threadIdx.x == 0) path[len] = v;
     ++len;
   }

@@ -104,3 +104,58 @@ def test_level1_switch_is_checked(gpu_ctx):
         L.check(lib.dd_path_level1(gpu_ctx.handle, -2, None, None))
     on = C.c_int()
     assert lib.dd_path_level1(gpu_ctx.handle, -1, C.byref(on), None) == L.DD_OK and on.value == 1
+
+
+def _on_demand(k, ss, ts, **kw):
+    import torch
+    paths, lens, status, evals = k.trace_paths_on_demand(ss, ts, "kl", 4000, **kw)
+    torch.cuda.synchronize()
+    lens = lens.cpu().numpy()
+    paths = paths.cpu().numpy()
+    return ([paths[i, :lens[i]].tolist() for i in range(len(ts))], status.cpu().numpy(),
+            evals.cpu().numpy())
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-3])
+def test_level1_leaves_on_demand_walks_unchanged(gpu_ctx, grid257, tau):
+    # the on-demand walk (no field) decides every step on row values: level 1
+    # first, FP64 where it does not settle the step
+    from paper_1708_02845_amd import Kernel
+    g, P = grid257
+    k = Kernel.load_dense(gpu_ctx, P, adjacency=(g.adj_ptr, g.adj_idx))
+    try:
+        ts, ss = targets_sources(6, g.N, 24)
+        on = _on_demand(k, ss, ts, target_tau=tau)
+        try:
+            assert not gpu_ctx.path_level1(False)[0]
+            off = _on_demand(k, ss, ts, target_tau=tau)
+        finally:
+            assert gpu_ctx.path_level1(True)[0]
+        assert on[0] == off[0] and np.array_equal(on[1], off[1]) and np.array_equal(on[2], off[2])
+        if tau == 0.0:
+            fields, bounds = k.batch_fields(ts[:4], "kl")
+            walked = _trace(k, ss[:4], ts[:4], fields, bounds)
+            assert on[0][:4] == walked[0] and np.array_equal(on[1][:4], walked[1])
+            ref, st = _oracle(P, g.adj_ptr, g.adj_idx, int(ss[0]), int(ts[0]))
+            assert on[0][0] == ref and int(on[1][0]) == st
+    finally:
+        k.free()
+
+
+def test_level1_on_demand_fp64_matrix(gpu_ctx):
+    from paper_1708_02845_amd import Kernel
+    inst = build_config("disk4096")
+    k = Kernel.load_dense(gpu_ctx, inst.P, adjacency=(inst.adj_ptr, inst.adj_idx))
+    try:
+        ts, ss = targets_sources(7, inst.N, 16)
+        on = _on_demand(k, ss, ts)
+        try:
+            gpu_ctx.path_level1(False)
+            off = _on_demand(k, ss, ts)
+        finally:
+            gpu_ctx.path_level1(True)
+        assert on[0] == off[0] and np.array_equal(on[1], off[1])
+        ref, st = _oracle(inst.P, inst.adj_ptr, inst.adj_idx, int(ss[3]), int(ts[3]))
+        assert on[0][3] == ref and int(on[1][3]) == st
+    finally:
+        k.free()
