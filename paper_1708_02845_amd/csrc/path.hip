@@ -15,8 +15,10 @@
 // best and the second-best neighbour (or the best neighbour and the current
 // vertex) cannot be told apart within the bound, the distances of every
 // neighbour that could be the minimum, and of the current vertex, are
-// recomputed in FP64 from the resident master rows and the decision is taken
-// on those.
+// recomputed from the resident master rows and the decision is taken on
+// those: for KL on dense rows first as level-1 values (FP32 hardware
+// logarithms summed in FP64, with a stated bound), and in FP64 where those
+// intervals still do not settle the step.
 #include <cmath>
 #include <cstring>
 #include <type_traits>

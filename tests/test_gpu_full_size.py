@@ -149,21 +149,33 @@ def test_streams_and_truncation_bias(request, gpu_ctx, full, kl_refs):
                           f"{_nw(ref, ref64):.3e}")
             assert _nw(fs, ref) <= 1e-5 and within_bound(fs, ref, b)
             assert _nw(ref, ref64) <= 1e-6
+        # both fields from one pass: the same values, all N of them
+        both, _ = k.fields_tv_kl(t)
+        for i, kind in enumerate(("tv", "kl")):
+            assert torch.equal(both[i], k.field(t, kind)[0]), kind
+        del both
     finally:
         k.free()
-    kc = Kernel.load_dense(gpu_ctx, P, tau=TAU)
-    try:
-        Pt1, thr1 = dv.truncate(P1, TAU)
-        for kind in ("tv", "kl"):
-            f, b = kc.field(t, kind)
-            fs = f[sel].cpu().numpy().astype(np.float64)
-            ref = dv.tv_trunc_field(Pt1, 0)[1:] if kind == "tv" else dv.kl_trunc_field(Pt1, 0, thr1)[1:]
-            assert _nw(fs, ref) <= 1e-5 and within_bound(fs, ref, b)
-            live(request, f"truncated {kind} (tau={TAU:g}): library {_nw(fs, ref):.3e}; "
-                          f"distance from the dense field (oracle, 1% sample) "
-                          f"{_nw(ref, dense[kind]):.3e} normwise")
-    finally:
-        kc.free()
+    for values in ("f32", "f16"):
+        kc = Kernel.load_dense(gpu_ctx, P, tau=TAU, csr_values=values)
+        try:
+            Pt1, thr1 = dv.truncate(P1, TAU)
+            both, (btv, bkl) = kc.fields_tv_kl(t)
+            for i, (kind, bnd) in enumerate((("tv", btv), ("kl", bkl))):
+                f, b = kc.field(t, kind)
+                assert torch.equal(both[i], f) and bnd == b, kind
+                fs = f[sel].cpu().numpy().astype(np.float64)
+                ref = dv.tv_trunc_field(Pt1, 0)[1:] if kind == "tv" else dv.kl_trunc_field(Pt1, 0, thr1)[1:]
+                # FP16 stored values: within the stated bound (it covers their rounding)
+                assert within_bound(fs, ref, b)
+                if values == "f32":
+                    assert _nw(fs, ref) <= 1e-5
+                live(request, f"truncated {kind} (tau={TAU:g}, {values} values): library "
+                              f"{_nw(fs, ref):.3e}; distance from the dense field (oracle, 1% "
+                              f"sample) {_nw(ref, dense[kind]):.3e} normwise")
+            del both
+        finally:
+            kc.free()
 
 
 def test_truncated_census_on_sample(gpu_ctx, full):
