@@ -12,10 +12,13 @@ batch:
 
   target preparation and the KL fields of the 64 targets   one f16x3 contraction
   64 steepest-descent paths on those fields                one launch, side stream
-  dense TV and dense KL fields of the first target         streaming over N x B rows
+  dense TV and dense KL fields of the first target         one pass over the N x B rows
   a TV path on the dense TV field                          side stream
-  truncated TV and KL fields of the first target           streaming over the CSR rows
+  truncated TV and KL fields of the first target           one pass over the CSR rows
 
+Steps are pipelined: the walks of step k (on one of two walk streams) run
+beside the fields of step k + 1, which go into the other of two field
+buffers; the timed region ends when the last step's walks have finished.
 The value is kernel entries per second, N*B per field, 68 fields per step.
 The kernel matrices are resident in HBM before the timed region.  The
 roofline object is that of the dominant kernel (the contraction), timed with
