@@ -451,6 +451,7 @@ def run_grid1025(args):
         del Fc
         rows.update(csr_batch_rows(torch, kc, ts_all, "tau1e-5_f16"))
         rows["paths_kl_T64_detail"] = path_rows(torch, kd, ss, ts, F, args.max_steps)
+        rows["step_kernels_alone"] = step_kernels_alone(torch, kd, kc, ts, F, f, alg)
     rows["truncation_bias"] = trunc_bias
     kc.free()
     kd.free()
@@ -516,6 +517,22 @@ def batch_contraction_rows(torch, k, ts_all, T, form="f16x3", sizes=(256,)):
         log(f"contraction {form} T={TT}: {us:.0f} us")
         del D
     torch.cuda.empty_cache()
+    return out
+
+
+def step_kernels_alone(torch, kd, kc, ts, F, f, alg):
+    """The step's field kernels with the GPU to themselves (no walks beside them):
+    median over repetitions, against their algorithmic bytes."""
+    tm = Timer(torch)
+    t0 = int(ts[0])
+    fns = {"contraction": lambda: kd.batch_fields(ts, "kl", out=F),
+           "dense_tv_kl": lambda: kd.fields_tv_kl(t0, out=f[0:2]),
+           "csr_tv_kl": lambda: kc.fields_tv_kl(t0, out=f[2:4])}
+    out = {}
+    for n, fn in fns.items():
+        us = repeat(torch, tm, n, fn, reps=10, warm=2)
+        out[n] = {"median_us": round(us, 1), "GB/s": round(gbs(alg[n], us), 1),
+                  "hbm_frac": round(gbs(alg[n], us) / HBM_PEAK_GBS, 4)}
     return out
 
 
