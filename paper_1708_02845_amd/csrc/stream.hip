@@ -338,38 +338,56 @@ __global__ __launch_bounds__(512) void csr_field_kernel(CsrView v, int32_t targe
     // Loads are unconditional (index clamped into the row) and entries past
     // the row's end are masked arithmetically, so the loop has no divergent
     // branch that would make the loads wait.  Padding slots hold column 0.
+    // Every load of an iteration is issued before any of its values is used
+    // (the FP16 values are converted in the compute loop), and a group of
+    // four entries wholly inside the row for every lane of the wave (all but
+    // a row's last iteration) skips the masking.
     for (int base = lane; base < nv; base += LPR * UNROLL) {
       float4 q[UNROLL];
+      ushort4 hq[UNROLL];
       ushort4 cb[UNROLL];
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
         const int i = min(base + u * LPR, nv - 1);
-        if (F16) {
-          const ushort4 hq = h4[i];
-          q[u] = make_float4(f16_value(hq.x, rs), f16_value(hq.y, rs), f16_value(hq.z, rs),
-                             f16_value(hq.w, rs));
-        } else {
+        if (F16)
+          hq[u] = h4[i];
+        else
           q[u] = ld_stream(val4 + i);
-        }
         cb[u] = col4[i];
       }
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
         const int i = base + u * LPR;
         const int rem = i < nv ? n - 4 * i : 0;
+        if (F16)
+          q[u] = make_float4(f16_value(hq[u].x, rs), f16_value(hq[u].y, rs),
+                             f16_value(hq[u].z, rs), f16_value(hq[u].w, rs));
         const float qv[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
         const int bv[4] = {cb[u].x, cb[u].y, cb[u].z, cb[u].w};
         float ts4 = 0.f, ks4 = 0.f, as4 = 0.f, es4 = 0.f;
+        if (__all(rem >= 4)) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool ok = e < rem;
-          const float2 pl = spl[bv[e]];
-          const float p = ok ? pl.x : 0.f;
-          as4 += p;
-          if (KIND != 1) ts4 += fabsf((ok ? qv[e] : 0.f) - p);
-          if (KIND != 0) {
-            ks4 += p * (pl.y - hw_log2(ok ? qv[e] : 1.f));
-            es4 += p * pl.y;
+          for (int e = 0; e < 4; ++e) {
+            const float2 pl = spl[bv[e]];
+            as4 += pl.x;
+            if (KIND != 1) ts4 += fabsf(qv[e] - pl.x);
+            if (KIND != 0) {
+              ks4 += pl.x * (pl.y - hw_log2(qv[e]));
+              es4 += pl.x * pl.y;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const bool ok = e < rem;
+            const float2 pl = spl[bv[e]];
+            const float p = ok ? pl.x : 0.f;
+            as4 += p;
+            if (KIND != 1) ts4 += fabsf((ok ? qv[e] : 0.f) - p);
+            if (KIND != 0) {
+              ks4 += p * (pl.y - hw_log2(ok ? qv[e] : 1.f));
+              es4 += p * pl.y;
+            }
           }
         }
         if (KIND != 1) acc += (double)ts4;
