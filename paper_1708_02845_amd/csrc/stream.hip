@@ -155,25 +155,34 @@ __global__ __launch_bounds__(512) void dense_field_kernel(const float* __restric
   for (int64_t row = (int64_t)blockIdx.x * gpb + grp; row < N; row += (int64_t)gridDim.x * gpb) {
     const float4* q = reinterpret_cast<const float4*>(P + row * ld);
     double acc = 0.0, acc2 = 0.0;
+    auto terms = [&](int i, const float4& qv) {
+      const float4 p = sp[i];
+      const float4 aux = KIND != 0 ? sl[i] : p;
+      if (KIND == 7) {
+        acc += (double)term4<0>(p, p, qv, param);
+        acc2 += (double)term4<1>(p, aux, qv, param);
+      } else {
+        acc += (double)term4<KIND>(p, aux, qv, param);
+      }
+    };
     for (int base = lane; base < nv; base += LPR * UNROLL) {
       float4 v[UNROLL];
+      if (__all(base + (UNROLL - 1) * LPR < nv)) {
+        // every load of every lane inside its row: no masks
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        const int i = base + u * LPR;
-        v[u] = i < nv ? ld_stream(q + i) : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
+        for (int u = 0; u < UNROLL; ++u) v[u] = ld_stream(q + base + u * LPR);
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        const int i = base + u * LPR;
-        if (i < nv) {
-          const float4 p = sp[i];
-          const float4 aux = KIND != 0 ? sl[i] : p;
-          if (KIND == 7) {
-            acc += (double)term4<0>(p, p, v[u], param);
-            acc2 += (double)term4<1>(p, aux, v[u], param);
-          } else {
-            acc += (double)term4<KIND>(p, aux, v[u], param);
-          }
+        for (int u = 0; u < UNROLL; ++u) terms(base + u * LPR, v[u]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const int i = base + u * LPR;
+          v[u] = i < nv ? ld_stream(q + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const int i = base + u * LPR;
+          if (i < nv) terms(i, v[u]);
         }
       }
     }
